@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the 3D SBP-SAT FDTD leapfrog step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) may import, call, link or execute anything in this
+package; only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+leg of ``bench.py`` use it.  It shares no code, headers, tables or constant
+generators with the HIP path.
+
+Two independent forms of the same method:
+
+* ``operators`` / ``system``: the matrix form.  The 1D SBP operators of the
+  paper's Appendix, the 3D operators as Kronecker products (ED_1-ED_3), the
+  SAT penalties written as sigma (P''')^-1 R^T P'' (...) exactly as in
+  E13-E15, E19-E21 and EPBC1-EPBC6, leapfrog time marching (Section V) and
+  the discrete energy (E16).  scipy.sparse matrices, fp64.
+* ``loops``: plain C loops (``loops.c``) applying the same step row by row
+  (Appendix rows, E24), for one block at a time; fast enough to time on the
+  host and to run the large single-block workloads.
+
+``yee`` is a plain Yee FDTD reference, used only to pin the interior.
+
+Parity pins live in ``tests/test_oracle_*.py``.  Functions whose results no
+pin covers say "parity unpinned" in their docstring.
+"""
