@@ -1,0 +1,214 @@
+"""Benchmark of the SBP-SAT FDTD leapfrog step on one MI355X.
+
+One "step" is one leapfrog step (H half step, E step, energy W^n, source and
+probe samples) of the dielectric-boxes workload: one 256^3-cell block, 32
+seeded dielectric boxes (eps_r in [1, 4]), PEC faces, modulated-Gaussian Ez
+source, fp32 fields with fp64 energy accumulation.  Inputs are resident in
+HBM before timing.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Extra keys: the fp64 path on the same workload, the field error of both
+paths against the fp64 oracle on a reduced case of the same recipe, the
+roofline of the dominant kernel (algorithmic bytes / mean launch time from
+HIP events on the kernel's stream), and the oracle timed on the host cores
+on a bounded sample of the workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def node_counts(n):
+    nx, ny, nz = n
+    e = (nx + 2) * (ny + 1) * (nz + 1) + (nx + 1) * (ny + 2) * (nz + 1) + (nx + 1) * (ny + 1) * (nz + 2)
+    h = (nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2) + (nx + 2) * (ny + 2) * (nz + 1)
+    return e, h
+
+
+def algorithmic_bytes(problem, elem):
+    """Bytes each launch must move: every node read once and written once per
+    update, the other field read once, per-cell materials read once."""
+    eb = hb = 0
+    for b in problem["blocks"]:
+        ne, nh = node_counts(b["n"])
+        cells = b["n"][0] * b["n"][1] * b["n"][2]
+        mats = sum(1 for k in ("eps_r", "mu_r", "sigma") if b.get(k) is not None)
+        e_mats = sum(1 for k in ("eps_r", "sigma") if b.get(k) is not None)
+        h_mats = 1 if b.get("mu_r") is not None else 0
+        del mats
+        eb += elem * (2 * ne + nh + e_mats * cells)
+        hb += elem * (2 * nh + ne + h_mats * cells)
+    return hb, eb
+
+
+def traffic_entry(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2206_00638_amd", "csrc", "step.hip")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+        with open(src, "rb") as fh:
+            h = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if t.get("step_hip_sha256") != h:
+        return None
+    return t.get("kernels", {}).get(kernel)
+
+
+def run_gpu(problem, prec, steps, warmup, profile_kernels):
+    import torch
+    from paper_2206_00638_amd import build_problem
+    stream = torch.cuda.Stream()
+    ctx = build_problem(problem, prec=prec, stream=stream, history=max(steps + warmup + 8, 64))
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()
+    kern = None
+    if profile_kernels:
+        ctx.profile(True)
+        ctx.step(min(steps, 50))
+        torch.cuda.synchronize()
+        kern = ctx.kernel_ms()
+        ctx.profile(False)
+    launch = ctx.get_launch()
+    n = ctx.steps_done()
+    energy = ctx.read_energy(n - 1, 1)[0]
+    ctx.close()
+    return {"wall_s": wall, "event_ms": ev_ms, "kernel_ms": kern, "launch": launch, "last_energy": energy}
+
+
+def accuracy(scale):
+    """Field/probe/energy error of the fp32 and fp64 paths against the fp64
+    loop oracle on the same recipe at 256/scale cells per axis."""
+    import numpy as np
+    from oracle import loops
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(2, scale=scale)
+    steps = prob["steps"]
+    ref = loops.run_block(prob)
+    out = {"workload": f"same recipe at {prob['blocks'][0]['n'][0]}^3, {steps} steps"}
+    for prec in ("f32", "f64"):
+        ctx = build_problem(prob, prec=prec)
+        ctx.step(steps)
+        num = {"E": 0.0, "H": 0.0}
+        den = {"E": 0.0, "H": 0.0}
+        for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+            g = ctx.read_field(0, c)
+            r = ref["fields"][c]
+            num[c[0]] += float(np.sum((g - r) ** 2))
+            den[c[0]] += float(np.sum(r * r))
+        pr = np.array([ctx.read_probe(p, 0, steps) for p in range(len(prob["probes"]))])
+        en = ctx.read_energy(0, steps)
+        ctx.close()
+        out[prec] = {"E_rel_l2": math.sqrt(num["E"] / den["E"]), "H_rel_l2": math.sqrt(num["H"] / den["H"]),
+                     "probe_rel_l2": float(np.linalg.norm(pr - ref["probes"]) / np.linalg.norm(ref["probes"])),
+                     "energy_rel": float(np.linalg.norm(en - ref["energy"]) / np.linalg.norm(ref["energy"]))}
+    return out
+
+
+def cpu_baseline(problem, target_s=15.0):
+    """The loop oracle (plain C, OpenMP) on the host cores, on a bounded
+    sample of the workload: the full block for a few steps."""
+    from oracle import loops
+    cells = problem["blocks"][0]["n"][0] * problem["blocks"][0]["n"][1] * problem["blocks"][0]["n"][2]
+    threads = loops.max_threads()
+    t0 = time.perf_counter()
+    loops.run_block(problem, steps=1)
+    t1 = time.perf_counter() - t0           # setup + one step
+    t0 = time.perf_counter()
+    loops.run_block(problem, steps=3)
+    t3 = time.perf_counter() - t0           # setup + three steps
+    per_step = max((t3 - t1) / 2.0, 1e-6)
+    k = int(max(2, min(200, target_s / per_step)))
+    t0 = time.perf_counter()
+    loops.run_block(problem, steps=k + 1)
+    tk = time.perf_counter() - t0
+    rate = k * cells / max(tk - t1 + per_step, 1e-9)   # exclude the one-off setup
+    return {"value": rate / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {problem['blocks'][0]['n'][0]}^3 block, {k} steps (setup excluded), fp64 loop form"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from sbp_inputs import make_config
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    prob = make_config(2)
+    n = prob["blocks"][0]["n"]
+    cells = n[0] * n[1] * n[2]
+    f32 = run_gpu(prob, "f32", args.steps, args.warmup, profile_kernels=True)
+    ms_per_step = f32["wall_s"] * 1e3 / args.steps
+    value = cells * args.steps / f32["wall_s"] / 1e6
+    hb, eb = algorithmic_bytes(prob, 4)
+    h_ms, e_ms = f32["kernel_ms"]
+    dom, dom_ms, dom_bytes = ("e_update", e_ms, eb) if e_ms >= h_ms else ("h_update", h_ms, hb)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    tr = traffic_entry(dom)
+    out = {
+        "metric": "Mcell-updates/s and HBM GB/s (% peak), FP32 vs FP64 step at stated field error",
+        "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": prob["name"], "cells": cells, "block": list(n), "dx_m": 1e-3,
+                   "faces": "pec", "source": "modulated gaussian Ez 10 GHz", "launch": list(f32["launch"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "kernel": dom, "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": dom_ms},
+        "kernels_ms": {"h_update": h_ms, "e_update": e_ms},
+        "step_hbm_gbs_algorithmic": (hb + eb) / (ms_per_step * 1e-3) / 1e9,
+        "event_ms_per_step": f32["event_ms"] / args.steps,
+    }
+    if not args.no_fp64:
+        f64 = run_gpu(prob, "f64", args.steps, args.warmup, profile_kernels=True)
+        hb8, eb8 = algorithmic_bytes(prob, 8)
+        out["fp64"] = {"value": cells * args.steps / f64["wall_s"] / 1e6, "unit": "Mcell-updates/s",
+                       "ms_per_step": f64["wall_s"] * 1e3 / args.steps, "kernels_ms": list(f64["kernel_ms"]),
+                       "step_hbm_gbs_algorithmic": (hb8 + eb8) / (f64["wall_s"] / args.steps) / 1e9}
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy(4)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

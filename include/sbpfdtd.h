@@ -1,0 +1,162 @@
+/*
+ * sbpfdtd: the leapfrog E/H step of the 3D SBP-SAT FDTD method
+ * (Cheng, Liu et al., "Towards the Development of a Three-Dimensional
+ * SBP-SAT FDTD Method: Theory and Validation"), native HIP for gfx950.
+ *
+ * C ABI.  Plain pointers and sizes; no C++ or torch types.  Every call
+ * returns an sbp_status; no exception or abort crosses the ABI.  The last
+ * error message of a context is available from sbp_last_error().
+ *
+ * Conventions
+ *  - Cells of a block are indexed (i, j, k), i fastest.  Field components
+ *    live on the grids of Table T1: Ex on (x-, y+, z+), Ey (x+, y-, z+),
+ *    Ez (x+, y+, z-), Hx (x+, y-, z-), Hy (x-, y+, z-), Hz (x-, y-, z+); a
+ *    "+" axis of n cells has n+1 nodes (x_i = i h), a "-" axis n+2 nodes
+ *    (0, h/2, 3h/2, ..., nh) (Section II-A).  Node arrays are i fastest.
+ *  - Faces: 0 = -x, 1 = +x, 2 = -y, 3 = +y, 4 = -z, 5 = +z.
+ *  - Host arrays passed in are copied during the call; the caller keeps
+ *    ownership.  Device memory is taken from the allocator callbacks given
+ *    to sbp_create (or hipMalloc when they are NULL) and returned on
+ *    sbp_destroy.
+ *  - sbp_step() only enqueues work on the context's stream; the read calls
+ *    synchronise that stream and copy into caller memory (fp32 fields are
+ *    widened to double).
+ *  - A context is used from one host thread at a time.
+ */
+#ifndef SBPFDTD_H
+#define SBPFDTD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbp_ctx sbp_ctx;
+
+typedef enum {
+  SBP_OK = 0,
+  SBP_EINVAL = -1,     /* bad argument (sizes, indices, face pairing, ratio) */
+  SBP_ENOMEM = -2,     /* device allocation failed */
+  SBP_EHIP = -3,       /* a HIP runtime call failed */
+  SBP_ESTATE = -4,     /* call out of order (e.g. step before finalize) */
+  SBP_EUNSTABLE = -5,  /* time step above the stability limit, or non-finite energy */
+  SBP_ERANGE = -6      /* requested samples not (or no longer) available */
+} sbp_status;
+
+typedef enum { SBP_FP64 = 0, SBP_FP32 = 1 } sbp_prec;
+
+/* Face treatments (Section III): PEC and PMC penalties (E13-E15 / E18,
+ * E19-E21 / E23); SBP_ABC1 is a first-order absorbing (characteristic)
+ * penalty, which the paper does not have (it truncates with CPML). */
+typedef enum { SBP_PEC = 0, SBP_PMC = 1, SBP_ABC1 = 2 } sbp_bc;
+
+typedef enum { SBP_EX = 0, SBP_EY, SBP_EZ, SBP_HX, SBP_HY, SBP_HZ } sbp_comp;
+
+/* Source waveforms of Section VI: 0 = Gaussian pulse exp(-4 pi (t-t0)^2/tw^2),
+ * 1 = the same times sin(2 pi f0 t). */
+typedef enum { SBP_GAUSS = 0, SBP_MODGAUSS = 1 } sbp_wave;
+
+typedef void *(*sbp_alloc_fn)(size_t bytes, void *user);
+typedef void (*sbp_free_fn)(void *ptr, void *user);
+
+/* Creates a context computing fields in `prec` on HIP stream `hip_stream`
+ * (NULL = default stream) of the current device.  `alloc`/`free_fn` may be
+ * NULL (hipMalloc/hipFree). */
+sbp_status sbp_create(sbp_ctx **out, sbp_prec prec, void *hip_stream,
+                      sbp_alloc_fn alloc, sbp_free_fn free_fn, void *user);
+
+/* Adds a block of nx*ny*nz cells (each >= 4: the boundary closures of the
+ * Appendix need four cells) of size dx*dy*dz metres at origin (x0,y0,z0).
+ * eps_r, mu_r, sigma (S/m): per-cell host arrays of nx*ny*nz doubles, i
+ * fastest, or NULL for 1, 1, 0.  The node value is the mean over the cells
+ * whose closed box contains the node.  All faces start as PEC. */
+sbp_status sbp_add_block(sbp_ctx *ctx, int nx, int ny, int nz, double dx, double dy,
+                         double dz, double x0, double y0, double z0, const double *eps_r,
+                         const double *mu_r, const double *sigma, int *block_id);
+
+/* Sets the treatment of one outer face of a block. */
+sbp_status sbp_set_face_bc(sbp_ctx *ctx, int block, int face, sbp_bc bc);
+
+/* Couples face_a of blk_a with face_b of blk_b (opposite faces of one axis,
+ * covering each other exactly) through interface penalties: the pattern of
+ * EPBC1-EPBC6 with zero phase and sigma = chi = +-1/2 (EPBCP).  ratio = cells
+ * of blk_b per cell of blk_a along the face, 1 or 2; at 2 the neighbour's
+ * face values are interpolated by a norm-compatible pair of operators. */
+sbp_status sbp_connect(sbp_ctx *ctx, int blk_a, int face_a, int blk_b, int face_b, int ratio);
+
+/* Soft source (a current density inside the E update) on node (i,j,k) of an
+ * E component; p = {tw, t0, f0} in seconds / Hz; evaluated at (n+1/2) dt. */
+sbp_status sbp_add_source(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int k,
+                          sbp_wave waveform, const double p[3], double amplitude, int *id);
+
+/* Probe of one node per step: sample n is E^{n+1} (or H^{n+1/2}). */
+sbp_status sbp_add_probe(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int k, int *id);
+
+/* Builds the plan and device buffers.  dt = cfl_fraction times the Yee limit
+ * of the finest block (the limit the paper reports for its SBP-SAT scheme,
+ * Section VI-A).  cfl_fraction > 1 gives SBP_EUNSTABLE unless `force` != 0.
+ * history = number of per-step energy / probe samples retained (ring). */
+sbp_status sbp_finalize(sbp_ctx *ctx, double cfl_fraction, int force, long history,
+                        double *dt_out);
+
+/* Replaces the per-cell materials of a block after finalize (NULL = 1,1,0). */
+sbp_status sbp_set_materials(sbp_ctx *ctx, int block, const double *eps_r, const double *mu_r,
+                             const double *sigma);
+
+/* Enqueues nsteps leapfrog steps (H half step, then E step, Section V). */
+sbp_status sbp_step(sbp_ctx *ctx, long nsteps);
+
+/* Number of steps taken so far. */
+sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
+
+/* Node counts (Sx, Sy, Sz) of a component of a block. */
+sbp_status sbp_field_shape(const sbp_ctx *ctx, int block, sbp_comp c, int shape[3]);
+
+/* Copies a component to / from host doubles (Sx*Sy*Sz, i fastest).  Writing
+ * sets E^n or H^{n-1/2} of the current step. */
+sbp_status sbp_read_field(sbp_ctx *ctx, int block, sbp_comp c, double *dst, size_t count);
+sbp_status sbp_write_field(sbp_ctx *ctx, int block, sbp_comp c, const double *src, size_t count);
+
+/* Energy W^n (E16, leapfrog pairing of H) for n = first .. first+count-1. */
+sbp_status sbp_read_energy(sbp_ctx *ctx, long first, long count, double *dst);
+
+/* Probe samples n = first .. first+count-1 of probe `id`. */
+sbp_status sbp_read_probe(sbp_ctx *ctx, int id, long first, long count, double *dst);
+
+/* Device-to-device snapshot of the time-stepping state (fields and step
+ * index).  bytes must be >= sbp_state_bytes(). */
+sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
+sbp_status sbp_save_state(sbp_ctx *ctx, void *dev_buf, size_t bytes);
+sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
+
+/* Launch shape of the step kernels: tile tx*ty nodes in x*y, cz planes in z
+ * per tile, `workgroups` resident workgroups looping over the tile list (0 =
+ * one workgroup per tile).  tx*ty must be 64, 128, 256 or 512. */
+sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
+sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
+
+/* Measures candidate launch shapes on the current state (restored after)
+ * and keeps the fastest; writes ms per step of the winner. */
+sbp_status sbp_autotune(sbp_ctx *ctx, int steps_per_trial, double *best_ms);
+
+/* Records `steps` consecutive steps in a HIP graph; later sbp_step calls
+ * replay it for whole multiples of `steps` (0 disables). */
+sbp_status sbp_use_graph(sbp_ctx *ctx, int steps);
+
+/* Time (ms) of the last sbp_step call between HIP events on the stream;
+ * valid after the stream has reached the end event. */
+sbp_status sbp_last_step_ms(sbp_ctx *ctx, double *ms);
+
+/* Mean duration (ms) per launch of the H and E kernels over the last
+ * sbp_step call, from per-launch HIP events (enabled by sbp_profile(ctx,1)). */
+sbp_status sbp_profile(sbp_ctx *ctx, int enable);
+sbp_status sbp_kernel_ms(sbp_ctx *ctx, double out[2]);
+
+const char *sbp_last_error(const sbp_ctx *ctx);
+void sbp_destroy(sbp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1166 @@
+// Host plan and C ABI of the SBP-SAT FDTD step (see include/sbpfdtd.h).
+//
+// The plan turns blocks, faces, interfaces, sources and probes into device
+// descriptors: per-block closure-row tables (Appendix rows with the Section
+// III SAT row changes), a flat tile list over all blocks (one launch per half
+// step covers every block), face buffers and gather jobs for interfaces, and
+// ring buffers for the per-step energy and probe samples.  Each step enqueues
+// [gather E] -> H update -> [gather H] -> E update on the context's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sbpfdtd.h"
+#include "plan.h"
+
+namespace sbp {
+template <typename T> hipError_t launch_h(const KArgs&, int, int, hipStream_t);
+template <typename T> hipError_t launch_e(const KArgs&, int, int, hipStream_t);
+template <typename T> hipError_t launch_e_energy(const KArgs&, int, int, hipStream_t);
+template <typename T>
+hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*,
+                         hipStream_t);
+}  // namespace sbp
+
+using namespace sbp;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4e-7 * kPi;
+constexpr double kC0 = 299792458.0;
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+
+struct HostBlock {
+  int n[3];
+  double h[3], x0[3];
+  std::vector<double> eps, mu, sig;
+  int faces[6];
+  int iface[6];  // index into ifaces or -1
+};
+
+struct HostIface {
+  int a, fa, b, fb, ratio;
+};
+
+struct HostSource {
+  int block;
+  Source s;
+};
+struct HostProbe {
+  int block;
+  Probe p;
+};
+
+}  // namespace
+
+struct sbp_ctx {
+  sbp_prec prec = SBP_FP64;
+  hipStream_t stream = nullptr;
+  sbp_alloc_fn alloc = nullptr;
+  sbp_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  int device = 0;
+  std::vector<HostBlock> blocks;
+  std::vector<HostIface> ifaces;
+  std::vector<HostSource> srcs;
+  std::vector<HostProbe> prbs;
+  bool finalized = false;
+  double dt = 0.0;
+  long long nstep = 0;
+  long history = 0;
+  // device buffers
+  void* pool = nullptr;
+  size_t pool_elems = 0;
+  void* mat[3] = {nullptr, nullptr, nullptr};
+  size_t ncells = 0;
+  DevBlock* d_blocks = nullptr;
+  std::vector<DevBlock> hblocks;
+  Tile* d_tiles = nullptr;
+  int ntiles = 0;
+  size_t tiles_cap = 0;
+  Source* d_src = nullptr;
+  Probe* d_prb = nullptr;
+  std::vector<int> probe_order;  // user probe id -> device probe index
+  double* d_energy = nullptr;
+  double* d_probes = nullptr;
+  double* d_partials = nullptr;
+  size_t partials_cap = 0;
+  StepState* d_st = nullptr;
+  double* d_face = nullptr;
+  FaceJob* d_jobs_e = nullptr;
+  FaceJob* d_jobs_h = nullptr;
+  int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
+  Taps* d_taps = nullptr;
+  int tx = 64, ty = 4, cz = 16, wgs = 0;
+  bool e_energy_dirty = true;
+  std::string err;
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  bool profile = false;
+  std::vector<hipEvent_t> kev;
+  int kev_used = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+sbp_status fail(sbp_ctx* c, sbp_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                               \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(ctx, SBP_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+void* dalloc(sbp_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(bytes, c->user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void dfree(sbp_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  if (c->free_fn) c->free_fn(p, c->user);
+  else (void)hipFree(p);
+}
+
+size_t elem_size(const sbp_ctx* c) { return c->prec == SBP_FP64 ? 8 : 4; }
+
+// grid type per component and axis: true = "+" (n+1 nodes), false = "-" (n+2), Table T1
+const bool kPlus[6][3] = {{false, true, true}, {true, false, true}, {true, true, false},
+                          {true, false, false}, {false, true, false}, {false, false, true}};
+
+int comp_dim(const HostBlock& b, int c, int a) { return kPlus[c][a] ? b.n[a] + 1 : b.n[a] + 2; }
+
+// ---------------------------------------------------------- closure tables
+// Appendix rows (times h): D+ rows 0, 1, n-1, n; D- rows 0, 1, 2, n-1, n, n+1.
+// SAT row changes (Section III): a PEC face flips the boundary-E coefficient
+// of the D- face row (H update), a PMC or absorbing face flips the boundary-H
+// coefficient of the D+ face row (E update); an interface face moves that
+// coefficient onto the neighbour's value (penalties of EPBC1-6 at zero phase
+// with sigma = chi = +-1/2).
+Row mkrow(int s, double c0, double c1, double c2, double ih) {
+  Row r;
+  r.s = s;
+  r.nbr = 0;
+  r.c[0] = c0 * ih;
+  r.c[1] = c1 * ih;
+  r.c[2] = c2 * ih;
+  r.cn = 0.0;
+  return r;
+}
+
+void build_rows(const HostBlock& b, DevBlock& d) {
+  for (int a = 0; a < 3; ++a) {
+    const int n = b.n[a];
+    const double ih = 1.0 / b.h[a];
+    const int flo = b.faces[2 * a], fhi = b.faces[2 * a + 1];
+    const bool ilo = b.iface[2 * a] >= 0, ihi = b.iface[2 * a + 1] >= 0;
+    (void)n;
+    // D+ (E update)
+    d.dp[a][0] = mkrow(0, -1.0, 0.5, 0.5, ih);
+    d.dp[a][1] = mkrow(-1, -0.5, -0.25, 0.75, ih);
+    d.dp[a][2] = mkrow(0, -0.75, 0.25, 0.5, ih);
+    d.dp[a][3] = mkrow(-1, -0.5, -0.5, 1.0, ih);
+    if (ilo) {
+      d.dp[a][0].cn = d.dp[a][0].c[0];
+      d.dp[a][0].c[0] = 0.0;
+      d.dp[a][0].nbr = 1;
+    } else if (flo == SBP_PMC || flo == SBP_ABC1) {
+      d.dp[a][0].c[0] = -d.dp[a][0].c[0];
+    }
+    if (ihi) {
+      d.dp[a][3].cn = d.dp[a][3].c[2];
+      d.dp[a][3].c[2] = 0.0;
+      d.dp[a][3].nbr = 1;
+    } else if (fhi == SBP_PMC || fhi == SBP_ABC1) {
+      d.dp[a][3].c[2] = -d.dp[a][3].c[2];
+    }
+    // D- (H update)
+    d.dm[a][0] = mkrow(0, -1.0, 1.0, 0.0, ih);
+    d.dm[a][1] = mkrow(-1, -1.0, 1.0, 0.0, ih);
+    d.dm[a][2] = mkrow(-2, -0.2, -0.6, 0.8, ih);
+    d.dm[a][3] = mkrow(-1, -0.8, 0.6, 0.2, ih);
+    d.dm[a][4] = mkrow(-2, 0.0, -1.0, 1.0, ih);
+    d.dm[a][5] = mkrow(-3, 0.0, -1.0, 1.0, ih);
+    if (ilo) {
+      d.dm[a][0].cn = d.dm[a][0].c[0];
+      d.dm[a][0].c[0] = 0.0;
+      d.dm[a][0].nbr = 1;
+    } else if (flo == SBP_PEC) {
+      d.dm[a][0].c[0] = -d.dm[a][0].c[0];
+    }
+    if (ihi) {
+      d.dm[a][5].cn = d.dm[a][5].c[2];
+      d.dm[a][5].c[2] = 0.0;
+      d.dm[a][5].nbr = 1;
+    } else if (fhi == SBP_PEC) {
+      d.dm[a][5].c[2] = -d.dm[a][5].c[2];
+    }
+  }
+}
+
+// ------------------------------------------------ 1:2 interface operators
+// Node coordinates (units of the coarse h) and norm weights of the two 1D
+// grids (Section II-A, Appendix).
+std::vector<double> nodes(bool plus, int n, double h) {
+  std::vector<double> x;
+  if (plus) {
+    for (int i = 0; i <= n; ++i) x.push_back(i * h);
+  } else {
+    x.push_back(0.0);
+    for (int j = 1; j <= n; ++j) x.push_back((j - 0.5) * h);
+    x.push_back(n * h);
+  }
+  return x;
+}
+std::vector<double> norm_weights(bool plus, int n, double h) {
+  std::vector<double> w;
+  if (plus) {
+    for (int i = 0; i <= n; ++i) w.push_back((i == 0 || i == n) ? 0.5 * h : h);
+  } else {
+    for (int r = 0; r <= n + 1; ++r) {
+      double v = 1.0;
+      if (r == 0 || r == n + 1) v = 0.5;
+      else if (r == 1 || r == n) v = 0.25;
+      else if (r == 2 || r == n - 1) v = 1.25;
+      w.push_back(v * h);
+    }
+  }
+  return w;
+}
+
+// Coarse-to-fine interpolation, dense (rows = fine nodes).  "+" grid: linear
+// interpolation (fine nodes at coarse nodes and midpoints).  "-" grid:
+// linear interpolation inside; the four fine rows at each end, over the
+// first three coarse nodes, are the rows nearest (Frobenius) to linear
+// interpolation such that every row sums to one and the fine-norm-weighted
+// column sums equal the coarse norm weights (the restriction
+// Wc^-1 I^T Wf then reproduces constants).  Exact values of that solution:
+const double kMinusBlock[4][3] = {{49.0 / 46, -13.0 / 92, 7.0 / 92},
+                                  {49.0 / 92, 79.0 / 184, 7.0 / 184},
+                                  {15.0 / 92, 73.0 / 184, 81.0 / 184},
+                                  {3.0 / 23, -3.0 / 92, 83.0 / 92}};
+
+std::vector<double> c2f(bool plus, int nc) {
+  const std::vector<double> xc = nodes(plus, nc, 1.0), xf = nodes(plus, 2 * nc, 0.5);
+  const int rf = (int)xf.size(), rc = (int)xc.size();
+  std::vector<double> m((size_t)rf * rc, 0.0);
+  for (int r = 0; r < rf; ++r) {
+    int i = 0;
+    while (i + 2 < rc && xc[i + 1] <= xf[r]) ++i;
+    const double t = (xf[r] - xc[i]) / (xc[i + 1] - xc[i]);
+    m[(size_t)r * rc + i] = 1.0 - t;
+    m[(size_t)r * rc + i + 1] = t;
+  }
+  if (!plus) {
+    for (int r = 0; r < 4; ++r)
+      for (int s = 0; s < rc; ++s) {
+        m[(size_t)r * rc + s] = s < 3 ? kMinusBlock[r][s] : 0.0;
+        m[(size_t)(rf - 1 - r) * rc + s] = s >= rc - 3 ? kMinusBlock[r][rc - 1 - s] : 0.0;
+      }
+  }
+  return m;
+}
+
+// rows of a dense matrix as tap lists (consecutive support)
+bool to_taps(const std::vector<double>& m, int rows, int cols, std::vector<Taps>& out) {
+  for (int r = 0; r < rows; ++r) {
+    int lo = cols, hi = -1;
+    for (int c = 0; c < cols; ++c)
+      if (m[(size_t)r * cols + c] != 0.0) {
+        lo = std::min(lo, c);
+        hi = std::max(hi, c);
+      }
+    Taps t;
+    std::memset(&t, 0, sizeof(t));
+    if (hi < lo) {
+      t.start = 0;
+      t.count = 0;
+    } else {
+      if (hi - lo + 1 > MAX_TAPS) return false;
+      t.start = lo;
+      t.count = hi - lo + 1;
+      for (int c = lo; c <= hi; ++c) t.w[c - lo] = m[(size_t)r * cols + c];
+    }
+    out.push_back(t);
+  }
+  return true;
+}
+
+// taps mapping neighbour nodes to own nodes along one tangential axis
+bool axis_taps(bool plus, int own_n, int role, std::vector<Taps>& out) {
+  if (role == 0) {  // same mesh
+    const int cnt = plus ? own_n + 1 : own_n + 2;
+    for (int r = 0; r < cnt; ++r) {
+      Taps t;
+      std::memset(&t, 0, sizeof(t));
+      t.start = r;
+      t.count = 1;
+      t.w[0] = 1.0;
+      out.push_back(t);
+    }
+    return true;
+  }
+  if (role == 1) {  // own fine, neighbour coarse: I_c2f
+    const int nc = own_n / 2;
+    const std::vector<double> m = c2f(plus, nc);
+    return to_taps(m, plus ? 2 * nc + 1 : 2 * nc + 2, plus ? nc + 1 : nc + 2, out);
+  }
+  // own coarse, neighbour fine: I_f2c = Wc^-1 I_c2f^T Wf
+  const int nc = own_n;
+  const std::vector<double> m = c2f(plus, nc);
+  const int rf = plus ? 2 * nc + 1 : 2 * nc + 2, rc = plus ? nc + 1 : nc + 2;
+  const std::vector<double> wc = norm_weights(plus, nc, 1.0), wf = norm_weights(plus, 2 * nc, 0.5);
+  std::vector<double> r((size_t)rc * rf, 0.0);
+  for (int i = 0; i < rc; ++i)
+    for (int f = 0; f < rf; ++f) r[(size_t)i * rf + f] = m[(size_t)f * rc + i] * wf[f] / wc[i];
+  return to_taps(r, rc, rf, out);
+}
+
+template <typename T>
+void put_cells(std::vector<T>& dst, size_t off, const std::vector<double>& src) {
+  for (size_t q = 0; q < src.size(); ++q) dst[off + q] = (T)src[q];
+}
+
+sbp_status upload_materials(sbp_ctx* c) {
+  const bool fp64 = c->prec == SBP_FP64;
+  for (int kind = 0; kind < 3; ++kind) {
+    bool any = false;
+    for (auto& b : c->blocks) {
+      const std::vector<double>& v = kind == 0 ? b.eps : (kind == 1 ? b.mu : b.sig);
+      any |= !v.empty();
+    }
+    if (!any) continue;
+    if (!c->mat[kind]) {
+      c->mat[kind] = dalloc(c, c->ncells * elem_size(c));
+      if (!c->mat[kind]) return fail(c, SBP_ENOMEM, "material allocation failed");
+    }
+    std::vector<double> dflt;
+    if (fp64) {
+      std::vector<double> h(c->ncells, kind == 2 ? 0.0 : 1.0);
+      size_t off = 0;
+      for (auto& b : c->blocks) {
+        const std::vector<double>& v = kind == 0 ? b.eps : (kind == 1 ? b.mu : b.sig);
+        if (!v.empty()) put_cells(h, off, v);
+        off += (size_t)b.n[0] * b.n[1] * b.n[2];
+      }
+      HIPCHK(c, hipMemcpyAsync(c->mat[kind], h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+      std::vector<float> h(c->ncells, kind == 2 ? 0.0f : 1.0f);
+      size_t off = 0;
+      for (auto& b : c->blocks) {
+        const std::vector<double>& v = kind == 0 ? b.eps : (kind == 1 ? b.mu : b.sig);
+        if (!v.empty()) put_cells(h, off, v);
+        off += (size_t)b.n[0] * b.n[1] * b.n[2];
+      }
+      HIPCHK(c, hipMemcpyAsync(c->mat[kind], h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+  }
+  // flags per block
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    const HostBlock& b = c->blocks[bi];
+    DevBlock& d = c->hblocks[bi];
+    d.mat = (b.eps.empty() ? 0 : MAT_EPS) | (b.mu.empty() ? 0 : MAT_MU) | (b.sig.empty() ? 0 : MAT_SIG);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_blocks, c->hblocks.data(), c->hblocks.size() * sizeof(DevBlock),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SBP_OK;
+}
+
+void drop_graph(sbp_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+sbp_status build_tiles(sbp_ctx* c) {
+  std::vector<Tile> tl;
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    const HostBlock& b = c->blocks[bi];
+    for (int z0 = 0; z0 < b.n[2] + 2; z0 += c->cz)
+      for (int y0 = 0; y0 < b.n[1] + 2; y0 += c->ty)
+        for (int x0 = 0; x0 < b.n[0] + 2; x0 += c->tx) tl.push_back(Tile{(int)bi, x0, y0, z0});
+  }
+  if (tl.size() > c->tiles_cap) {
+    dfree(c, c->d_tiles);
+    c->d_tiles = (Tile*)dalloc(c, tl.size() * sizeof(Tile));
+    if (!c->d_tiles) return fail(c, SBP_ENOMEM, "tile list allocation failed");
+    c->tiles_cap = tl.size();
+  }
+  c->ntiles = (int)tl.size();
+  HIPCHK(c, hipMemcpyAsync(c->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  const size_t grid = c->wgs > 0 ? std::min<size_t>(c->wgs, tl.size()) : tl.size();
+  if (grid > c->partials_cap) {
+    dfree(c, c->d_partials);
+    c->d_partials = (double*)dalloc(c, grid * sizeof(double));
+    if (!c->d_partials) return fail(c, SBP_ENOMEM, "partials allocation failed");
+    c->partials_cap = grid;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  return SBP_OK;
+}
+
+KArgs kargs(sbp_ctx* c) {
+  KArgs a;
+  a.blocks = c->d_blocks;
+  a.tiles = c->d_tiles;
+  a.ntiles = c->ntiles;
+  a.tx = c->tx;
+  a.cz = c->cz;
+  a.pool = c->pool;
+  a.mat_eps = c->mat[0];
+  a.mat_mu = c->mat[1];
+  a.mat_sig = c->mat[2];
+  a.face = c->d_face;
+  a.src = c->d_src;
+  a.prb = c->d_prb;
+  a.energy = c->d_energy;
+  a.ecap = (int)c->history;
+  a.probes = c->d_probes;
+  a.pcap = (int)c->history;
+  a.partials = c->d_partials;
+  a.st = c->d_st;
+  a.dt = c->dt;
+  a.eps0 = kEps0;
+  a.mu0 = kMu0;
+  return a;
+}
+
+int grid_size(const sbp_ctx* c) { return c->wgs > 0 ? std::min(c->wgs, c->ntiles) : c->ntiles; }
+
+sbp_status enqueue_e_energy(sbp_ctx* c) {
+  const KArgs a = kargs(c);
+  const int threads = c->tx * c->ty;
+  hipError_t e = c->prec == SBP_FP64 ? launch_e_energy<double>(a, grid_size(c), threads, c->stream)
+                                     : launch_e_energy<float>(a, grid_size(c), threads, c->stream);
+  HIPCHK(c, e);
+  return SBP_OK;
+}
+
+// One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E update.
+sbp_status enqueue_step(sbp_ctx* c, bool events) {
+  const KArgs a = kargs(c);
+  const int threads = c->tx * c->ty;
+  const int grid = grid_size(c);
+  const bool f64 = c->prec == SBP_FP64;
+  hipError_t e;
+  if (c->njobs_e) {
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream);
+    HIPCHK(c, e);
+  }
+  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  e = f64 ? launch_h<double>(a, grid, threads, c->stream) : launch_h<float>(a, grid, threads, c->stream);
+  HIPCHK(c, e);
+  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  if (c->njobs_h) {
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream);
+    HIPCHK(c, e);
+  }
+  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  e = f64 ? launch_e<double>(a, grid, threads, c->stream) : launch_e<float>(a, grid, threads, c->stream);
+  HIPCHK(c, e);
+  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  return SBP_OK;
+}
+
+bool check_block(const sbp_ctx* c, int b) { return b >= 0 && b < (int)c->blocks.size(); }
+
+template <typename T>
+void extract(const std::vector<T>& box, const DevBlock& d, const int s[3], double* dst) {
+  size_t q = 0;
+  for (int k = 0; k < s[2]; ++k)
+    for (int j = 0; j < s[1]; ++j)
+      for (int i = 0; i < s[0]; ++i) dst[q++] = (double)box[(size_t)i + d.sx * j + d.sxy * k];
+}
+template <typename T>
+void insert(std::vector<T>& box, const DevBlock& d, const int s[3], const double* src) {
+  size_t q = 0;
+  for (int k = 0; k < s[2]; ++k)
+    for (int j = 0; j < s[1]; ++j)
+      for (int i = 0; i < s[0]; ++i) box[(size_t)i + d.sx * j + d.sxy * k] = (T)src[q++];
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+sbp_status sbp_create(sbp_ctx** out, sbp_prec prec, void* hip_stream, sbp_alloc_fn alloc,
+                      sbp_free_fn free_fn, void* user) {
+  if (!out) return SBP_EINVAL;
+  *out = nullptr;
+  if (prec != SBP_FP64 && prec != SBP_FP32) return SBP_EINVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return SBP_EINVAL;
+  sbp_ctx* c = new (std::nothrow) sbp_ctx();
+  if (!c) return SBP_ENOMEM;
+  c->prec = prec;
+  c->stream = (hipStream_t)hip_stream;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = user;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return SBP_EHIP;
+  }
+  *out = c;
+  return SBP_OK;
+}
+
+sbp_status sbp_add_block(sbp_ctx* c, int nx, int ny, int nz, double dx, double dy, double dz,
+                         double x0, double y0, double z0, const double* eps_r, const double* mu_r,
+                         const double* sigma, int* block_id) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "add_block after finalize");
+  if (nx < 4 || ny < 4 || nz < 4)
+    return fail(c, SBP_EINVAL, "a block needs at least 4 cells per axis (Appendix closures)");
+  if (!(dx > 0 && dy > 0 && dz > 0)) return fail(c, SBP_EINVAL, "cell sizes must be positive");
+  HostBlock b;
+  b.n[0] = nx; b.n[1] = ny; b.n[2] = nz;
+  b.h[0] = dx; b.h[1] = dy; b.h[2] = dz;
+  b.x0[0] = x0; b.x0[1] = y0; b.x0[2] = z0;
+  const size_t nc = (size_t)nx * ny * nz;
+  for (int f = 0; f < 6; ++f) {
+    b.faces[f] = SBP_PEC;
+    b.iface[f] = -1;
+  }
+  auto take = [&](const double* p, std::vector<double>& v, bool positive) -> bool {
+    if (!p) return true;
+    v.assign(p, p + nc);
+    for (double x : v)
+      if (!std::isfinite(x) || (positive ? !(x > 0) : x < 0)) return false;
+    return true;
+  };
+  if (!take(eps_r, b.eps, true) || !take(mu_r, b.mu, true) || !take(sigma, b.sig, false))
+    return fail(c, SBP_EINVAL, "materials must be finite; eps_r, mu_r > 0, sigma >= 0");
+  c->blocks.push_back(std::move(b));
+  if (block_id) *block_id = (int)c->blocks.size() - 1;
+  return SBP_OK;
+}
+
+sbp_status sbp_set_face_bc(sbp_ctx* c, int block, int face, sbp_bc bc) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "set_face_bc after finalize");
+  if (!check_block(c, block) || face < 0 || face > 5) return fail(c, SBP_EINVAL, "bad block or face");
+  if (bc != SBP_PEC && bc != SBP_PMC && bc != SBP_ABC1) return fail(c, SBP_EINVAL, "bad face treatment");
+  c->blocks[block].faces[face] = bc;
+  return SBP_OK;
+}
+
+sbp_status sbp_connect(sbp_ctx* c, int a, int fa, int b, int fb, int ratio) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "connect after finalize");
+  if (!check_block(c, a) || !check_block(c, b) || a == b) return fail(c, SBP_EINVAL, "bad blocks");
+  if (fa < 0 || fa > 5 || fb < 0 || fb > 5) return fail(c, SBP_EINVAL, "bad face");
+  if (fa / 2 != fb / 2 || fa % 2 == fb % 2) return fail(c, SBP_EINVAL, "faces must be opposite faces of one axis");
+  if (ratio != 1 && ratio != 2) return fail(c, SBP_EINVAL, "ratio must be 1 or 2");
+  HostBlock &A = c->blocks[a], &B = c->blocks[b];
+  if (A.iface[fa] >= 0 || B.iface[fb] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
+  const int ax = fa / 2;
+  const double tol = 1e-9;
+  auto close = [&](double u, double v, double scale) { return std::fabs(u - v) <= tol * scale; };
+  const double la = A.n[ax] * A.h[ax], lb = B.n[ax] * B.h[ax];
+  const double pa = A.x0[ax] + (fa % 2 ? la : 0.0), pb = B.x0[ax] + (fb % 2 ? lb : 0.0);
+  if (!close(pa, pb, std::max(la, lb))) return fail(c, SBP_EINVAL, "interface faces are not coincident");
+  for (int t = 0; t < 3; ++t) {
+    if (t == ax) continue;
+    if (B.n[t] != ratio * A.n[t]) return fail(c, SBP_EINVAL, "interface face extents do not match the ratio");
+    const double lt = A.n[t] * A.h[t];
+    if (!close(A.x0[t], B.x0[t], lt) || !close(lt, B.n[t] * B.h[t], lt))
+      return fail(c, SBP_EINVAL, "interface faces do not cover each other");
+    if (ratio == 2 && A.n[t] < 6) return fail(c, SBP_EINVAL, "1:2 interfaces need >= 6 coarse cells along the face");
+  }
+  c->ifaces.push_back(HostIface{a, fa, b, fb, ratio});
+  A.iface[fa] = (int)c->ifaces.size() - 1;
+  B.iface[fb] = (int)c->ifaces.size() - 1;
+  return SBP_OK;
+}
+
+sbp_status sbp_add_source(sbp_ctx* c, int block, sbp_comp comp, int i, int j, int k, sbp_wave w,
+                          const double p[3], double amplitude, int* id) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "add_source after finalize");
+  if (!check_block(c, block) || comp < SBP_EX || comp > SBP_EZ) return fail(c, SBP_EINVAL, "sources act on E components");
+  const HostBlock& b = c->blocks[block];
+  if (i < 0 || j < 0 || k < 0 || i >= comp_dim(b, comp, 0) || j >= comp_dim(b, comp, 1) || k >= comp_dim(b, comp, 2))
+    return fail(c, SBP_EINVAL, "source node outside the component grid");
+  if (w != SBP_GAUSS && w != SBP_MODGAUSS) return fail(c, SBP_EINVAL, "bad waveform");
+  if (!p || !(p[0] > 0)) return fail(c, SBP_EINVAL, "source width must be positive");
+  HostSource s;
+  s.block = block;
+  std::memset(&s.s, 0, sizeof(s.s));
+  s.s.comp = comp; s.s.i = i; s.s.j = j; s.s.k = k;
+  s.s.wave = w;
+  s.s.tw = p[0]; s.s.t0 = p[1]; s.s.f0 = p[2];
+  s.s.amp = amplitude;
+  c->srcs.push_back(s);
+  if (id) *id = (int)c->srcs.size() - 1;
+  return SBP_OK;
+}
+
+sbp_status sbp_add_probe(sbp_ctx* c, int block, sbp_comp comp, int i, int j, int k, int* id) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "add_probe after finalize");
+  if (!check_block(c, block) || comp < SBP_EX || comp > SBP_HZ) return fail(c, SBP_EINVAL, "bad block or component");
+  const HostBlock& b = c->blocks[block];
+  if (i < 0 || j < 0 || k < 0 || i >= comp_dim(b, comp, 0) || j >= comp_dim(b, comp, 1) || k >= comp_dim(b, comp, 2))
+    return fail(c, SBP_EINVAL, "probe node outside the component grid");
+  HostProbe p;
+  p.block = block;
+  p.p.comp = comp; p.p.i = i; p.p.j = j; p.p.k = k;
+  c->prbs.push_back(p);
+  if (id) *id = (int)c->prbs.size() - 1;
+  return SBP_OK;
+}
+
+sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double* dt_out) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "already finalized");
+  if (c->blocks.empty()) return fail(c, SBP_ESTATE, "no blocks");
+  if (!(cfl > 0)) return fail(c, SBP_EINVAL, "cfl_fraction must be positive");
+  if (cfl > 1.0 && !force) return fail(c, SBP_EUNSTABLE, "cfl_fraction above the stability limit");
+  if (history < 2) history = 2;
+  if (history > (1L << 26)) return fail(c, SBP_EINVAL, "history too long");
+  HIPCHK(c, hipSetDevice(c->device));
+  // time step: Yee limit of the finest block
+  double lim = 1e300;
+  for (auto& b : c->blocks)
+    lim = std::min(lim, 1.0 / (kC0 * std::sqrt(1.0 / (b.h[0] * b.h[0]) + 1.0 / (b.h[1] * b.h[1]) + 1.0 / (b.h[2] * b.h[2]))));
+  c->dt = cfl * lim;
+  c->history = history;
+  // per-source / per-probe: group by block
+  std::vector<Source> dsrc;
+  std::vector<Probe> dprb;
+  c->hblocks.assign(c->blocks.size(), DevBlock());
+  c->probe_order.assign(c->prbs.size(), 0);
+  size_t foff = 0, coff = 0, fboff = 0;
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    HostBlock& b = c->blocks[bi];
+    DevBlock& d = c->hblocks[bi];
+    std::memset(&d, 0, sizeof(d));
+    for (int a = 0; a < 3; ++a) {
+      d.n[a] = b.n[a];
+      d.h[a] = b.h[a];
+      d.ih[a] = 1.0 / b.h[a];
+    }
+    d.sx = b.n[0] + 2;
+    d.sxy = d.sx * (b.n[1] + 2);
+    d.csz = d.sxy * (b.n[2] + 2);
+    d.foff = (long long)foff;
+    foff += 6 * (size_t)d.csz;
+    d.coff = (long long)coff;
+    coff += (size_t)b.n[0] * b.n[1] * b.n[2];
+    d.eps_r0 = 1.0;
+    d.mu_r0 = 1.0;
+    d.sig0 = 0.0;
+    d.abc_mask = 0;
+    d.iface_mask = 0;
+    for (int f = 0; f < 6; ++f) {
+      if (b.iface[f] >= 0) {
+        d.iface_mask |= 1 << f;
+        const int ax = f / 2;
+        const int e0 = ax == 0 ? b.n[1] + 2 : b.n[0] + 2;
+        const int e1 = ax == 2 ? b.n[1] + 2 : b.n[2] + 2;
+        d.fsz[f] = (long long)e0 * e1;
+        d.fboff[f] = (long long)fboff;
+        fboff += 4 * (size_t)d.fsz[f];
+      } else {
+        d.fsz[f] = 0;
+        d.fboff[f] = 0;
+        if (b.faces[f] == SBP_ABC1) d.abc_mask |= 1 << f;
+      }
+    }
+    build_rows(b, d);
+    d.src0 = (int)dsrc.size();
+    for (auto& s : c->srcs)
+      if (s.block == (int)bi) dsrc.push_back(s.s);
+    d.nsrc = (int)dsrc.size() - d.src0;
+    d.prb0 = (int)dprb.size();
+    for (size_t p = 0; p < c->prbs.size(); ++p)
+      if (c->prbs[p].block == (int)bi) {
+        c->probe_order[p] = (int)dprb.size();
+        dprb.push_back(c->prbs[p].p);
+      }
+    d.nprb = (int)dprb.size() - d.prb0;
+  }
+  // the kernels track at most two sources and two E (two H) probes per
+  // (block, i, j) node column
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    const DevBlock& d = c->hblocks[bi];
+    for (int q = 0; q < d.nsrc; ++q) {
+      int cnt = 0;
+      for (int r = 0; r < d.nsrc; ++r)
+        cnt += dsrc[d.src0 + r].i == dsrc[d.src0 + q].i && dsrc[d.src0 + r].j == dsrc[d.src0 + q].j;
+      if (cnt > 2) return fail(c, SBP_EINVAL, "more than two sources on one node column");
+    }
+    for (int q = 0; q < d.nprb; ++q) {
+      int cnt = 0;
+      const Probe& P = dprb[d.prb0 + q];
+      for (int r = 0; r < d.nprb; ++r) {
+        const Probe& R = dprb[d.prb0 + r];
+        cnt += R.i == P.i && R.j == P.j && (R.comp >= 3) == (P.comp >= 3);
+      }
+      if (cnt > 2) return fail(c, SBP_EINVAL, "more than two probes of one field on one node column");
+    }
+  }
+  c->pool_elems = foff;
+  c->ncells = coff;
+  c->pool = dalloc(c, foff * elem_size(c));
+  c->d_blocks = (DevBlock*)dalloc(c, c->hblocks.size() * sizeof(DevBlock));
+  c->d_src = (Source*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(Source));
+  c->d_prb = (Probe*)dalloc(c, std::max<size_t>(dprb.size(), 1) * sizeof(Probe));
+  c->d_energy = (double*)dalloc(c, (size_t)history * sizeof(double));
+  c->d_probes = (double*)dalloc(c, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double));
+  c->d_st = (StepState*)dalloc(c, sizeof(StepState));
+  c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
+  if (!c->pool || !c->d_blocks || !c->d_src || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
+    return fail(c, SBP_ENOMEM, "device allocation failed");
+  HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_energy, 0, (size_t)history * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_probes, 0, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_face, 0, std::max<size_t>(fboff, 1) * sizeof(double), c->stream));
+  if (!dsrc.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_src, dsrc.data(), dsrc.size() * sizeof(Source), hipMemcpyHostToDevice, c->stream));
+  if (!dprb.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_prb, dprb.data(), dprb.size() * sizeof(Probe), hipMemcpyHostToDevice, c->stream));
+  // interface gather jobs
+  std::vector<FaceJob> je, jh;
+  std::vector<Taps> taps;
+  int maxn = 0;
+  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+    const HostBlock& b = c->blocks[bi];
+    for (int f = 0; f < 6; ++f) {
+      if (b.iface[f] < 0) continue;
+      const HostIface& I = c->ifaces[b.iface[f]];
+      const bool is_a = I.a == (int)bi && I.fa == f;
+      const int nb = is_a ? I.b : I.a;
+      const int fn = is_a ? I.fb : I.fa;
+      const int role = I.ratio == 1 ? 0 : (is_a ? 2 : 1);  // 2: own coarse, 1: own fine
+      const int ax = f / 2;
+      const int ta[2] = {ax == 0 ? 1 : 0, ax == 2 ? 1 : 2};
+      for (int is_h = 0; is_h < 2; ++is_h)
+        for (int slot = 0; slot < 2; ++slot) {
+          FaceJob J;
+          std::memset(&J, 0, sizeof(J));
+          J.block = (int)bi;
+          J.face = f;
+          J.is_h = is_h;
+          J.slot = slot;
+          J.comp = is_h ? 3 + ta[slot] : ta[slot];
+          J.nb = nb;
+          const HostBlock& N = c->blocks[nb];
+          // face-normal index of the neighbour's face: "+" along the normal for
+          // tangential E (0 or n), "-" for tangential H (0 or n+1)
+          J.nb_idx = (fn % 2) ? (is_h ? N.n[ax] + 1 : N.n[ax]) : 0;
+          for (int q = 0; q < 2; ++q) {
+            J.t_axis[q] = ta[q];
+            const bool plus = kPlus[J.comp][ta[q]];
+            J.ext[q] = plus ? b.n[ta[q]] + 1 : b.n[ta[q]] + 2;
+            J.taps_off[q] = (long long)taps.size();
+            if (!axis_taps(plus, b.n[ta[q]], role, taps))
+              return fail(c, SBP_EINVAL, "interface interpolation wider than the tap limit");
+          }
+          maxn = std::max(maxn, J.ext[0] * J.ext[1]);
+          (is_h ? jh : je).push_back(J);
+        }
+    }
+  }
+  c->njobs_e = (int)je.size();
+  c->njobs_h = (int)jh.size();
+  c->max_face_nodes = maxn;
+  if (!je.empty()) {
+    c->d_jobs_e = (FaceJob*)dalloc(c, je.size() * sizeof(FaceJob));
+    c->d_jobs_h = (FaceJob*)dalloc(c, jh.size() * sizeof(FaceJob));
+    c->d_taps = (Taps*)dalloc(c, taps.size() * sizeof(Taps));
+    if (!c->d_jobs_e || !c->d_jobs_h || !c->d_taps) return fail(c, SBP_ENOMEM, "device allocation failed");
+    HIPCHK(c, hipMemcpyAsync(c->d_jobs_e, je.data(), je.size() * sizeof(FaceJob), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_jobs_h, jh.data(), jh.size() * sizeof(FaceJob), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_taps, taps.data(), taps.size() * sizeof(Taps), hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipEventCreate(&c->ev0));
+  HIPCHK(c, hipEventCreate(&c->ev1));
+  c->finalized = true;
+  sbp_status st = upload_materials(c);
+  if (st != SBP_OK) return st;
+  st = build_tiles(c);
+  if (st != SBP_OK) return st;
+  c->nstep = 0;
+  c->e_energy_dirty = true;
+  if (dt_out) *dt_out = c->dt;
+  return SBP_OK;
+}
+
+sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const double* mu_r,
+                             const double* sigma) {
+  if (!c) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "set_materials before finalize");
+  if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
+  HostBlock& b = c->blocks[block];
+  const size_t nc = (size_t)b.n[0] * b.n[1] * b.n[2];
+  std::vector<double> e, m, s;
+  if (eps_r) e.assign(eps_r, eps_r + nc);
+  if (mu_r) m.assign(mu_r, mu_r + nc);
+  if (sigma) s.assign(sigma, sigma + nc);
+  for (double x : e) if (!(x > 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "eps_r must be positive");
+  for (double x : m) if (!(x > 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "mu_r must be positive");
+  for (double x : s) if (!(x >= 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "sigma must be >= 0");
+  b.eps.swap(e);
+  b.mu.swap(m);
+  b.sig.swap(s);
+  void* old[3] = {c->mat[0], c->mat[1], c->mat[2]};
+  sbp_status st = upload_materials(c);
+  if (st != SBP_OK) return st;
+  if (old[0] != c->mat[0] || old[1] != c->mat[1] || old[2] != c->mat[2]) drop_graph(c);
+  c->e_energy_dirty = true;
+  return SBP_OK;
+}
+
+sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
+  if (!c) return SBP_EINVAL;
+  const int t = tx * ty;
+  if (tx < 1 || ty < 1 || (t != 64 && t != 128 && t != 256 && t != 512)) return fail(c, SBP_EINVAL, "tx*ty must be 64, 128, 256 or 512");
+  if (cz < 1 || workgroups < 0) return fail(c, SBP_EINVAL, "bad cz or workgroups");
+  c->tx = tx;
+  c->ty = ty;
+  c->cz = cz;
+  c->wgs = workgroups;
+  if (c->finalized) return build_tiles(c);
+  return SBP_OK;
+}
+
+sbp_status sbp_get_launch(const sbp_ctx* c, int out[4]) {
+  if (!c || !out) return SBP_EINVAL;
+  out[0] = c->tx; out[1] = c->ty; out[2] = c->cz; out[3] = c->wgs;
+  return SBP_OK;
+}
+
+sbp_status sbp_step(sbp_ctx* c, long nsteps) {
+  if (!c) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "step before finalize");
+  if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
+  if (nsteps == 0) return SBP_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  if (c->e_energy_dirty) {
+    sbp_status st = enqueue_e_energy(c);
+    if (st != SBP_OK) return st;
+    c->e_energy_dirty = false;
+  }
+  long done = 0;
+  if (c->graph_steps > 0 && nsteps >= c->graph_steps && !c->profile) {
+    if (!c->gexec) {
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      sbp_status st = SBP_OK;
+      for (int s = 0; s < c->graph_steps && st == SBP_OK; ++s) st = enqueue_step(c, false);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(c->stream, &g);
+      if (st != SBP_OK) return st;
+      HIPCHK(c, ee);
+      c->graph = g;
+      HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    }
+    while (nsteps - done >= c->graph_steps) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      done += c->graph_steps;
+    }
+  }
+  if (c->profile) {
+    const size_t need = (size_t)(nsteps - done) * 4;
+    while (c->kev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->kev.push_back(e);
+    }
+    c->kev_used = 0;
+  }
+  for (; done < nsteps; ++done) {
+    sbp_status st = enqueue_step(c, c->profile);
+    if (st != SBP_OK) return st;
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  c->timed = true;
+  c->nstep += nsteps;
+  return SBP_OK;
+}
+
+sbp_status sbp_steps_done(const sbp_ctx* c, long* n) {
+  if (!c || !n) return SBP_EINVAL;
+  *n = (long)c->nstep;
+  return SBP_OK;
+}
+
+sbp_status sbp_field_shape(const sbp_ctx* c, int block, sbp_comp comp, int shape[3]) {
+  if (!c || !shape) return SBP_EINVAL;
+  if (!check_block(c, block) || comp < SBP_EX || comp > SBP_HZ) return SBP_EINVAL;
+  for (int a = 0; a < 3; ++a) shape[a] = comp_dim(c->blocks[block], comp, a);
+  return SBP_OK;
+}
+
+sbp_status sbp_read_field(sbp_ctx* c, int block, sbp_comp comp, double* dst, size_t count) {
+  if (!c || !dst) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "read_field before finalize");
+  if (!check_block(c, block) || comp < SBP_EX || comp > SBP_HZ) return fail(c, SBP_EINVAL, "bad block or component");
+  int s[3];
+  sbp_field_shape(c, block, comp, s);
+  if (count < (size_t)s[0] * s[1] * s[2]) return fail(c, SBP_EINVAL, "destination too small");
+  const DevBlock& d = c->hblocks[block];
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const char* src = (const char*)c->pool + (size_t)(d.foff + comp * d.csz) * elem_size(c);
+  if (c->prec == SBP_FP64) {
+    std::vector<double> box(d.csz);
+    HIPCHK(c, hipMemcpy(box.data(), src, d.csz * 8, hipMemcpyDeviceToHost));
+    extract(box, d, s, dst);
+  } else {
+    std::vector<float> box(d.csz);
+    HIPCHK(c, hipMemcpy(box.data(), src, d.csz * 4, hipMemcpyDeviceToHost));
+    extract(box, d, s, dst);
+  }
+  return SBP_OK;
+}
+
+sbp_status sbp_write_field(sbp_ctx* c, int block, sbp_comp comp, const double* srcp, size_t count) {
+  if (!c || !srcp) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "write_field before finalize");
+  if (!check_block(c, block) || comp < SBP_EX || comp > SBP_HZ) return fail(c, SBP_EINVAL, "bad block or component");
+  int s[3];
+  sbp_field_shape(c, block, comp, s);
+  if (count < (size_t)s[0] * s[1] * s[2]) return fail(c, SBP_EINVAL, "source too small");
+  const DevBlock& d = c->hblocks[block];
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  char* dstp = (char*)c->pool + (size_t)(d.foff + comp * d.csz) * elem_size(c);
+  if (c->prec == SBP_FP64) {
+    std::vector<double> box(d.csz, 0.0);
+    insert(box, d, s, srcp);
+    HIPCHK(c, hipMemcpy(dstp, box.data(), d.csz * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> box(d.csz, 0.0f);
+    insert(box, d, s, srcp);
+    HIPCHK(c, hipMemcpy(dstp, box.data(), d.csz * 4, hipMemcpyHostToDevice));
+  }
+  c->e_energy_dirty = true;
+  return SBP_OK;
+}
+
+sbp_status sbp_read_energy(sbp_ctx* c, long first, long count, double* dst) {
+  if (!c || (!dst && count > 0)) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "read_energy before finalize");
+  if (first < 0 || count < 0 || first + count > c->nstep || first <= c->nstep - c->history)
+    return fail(c, SBP_ERANGE, "energy samples not available");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> ring(c->history);
+  HIPCHK(c, hipMemcpy(ring.data(), c->d_energy, ring.size() * 8, hipMemcpyDeviceToHost));
+  for (long q = 0; q < count; ++q) dst[q] = ring[(first + q) % c->history];
+  StepState st;
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  if (st.flags & 1) return fail(c, SBP_EUNSTABLE, "non-finite energy");
+  return SBP_OK;
+}
+
+sbp_status sbp_read_probe(sbp_ctx* c, int id, long first, long count, double* dst) {
+  if (!c || (!dst && count > 0)) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "read_probe before finalize");
+  if (id < 0 || id >= (int)c->prbs.size()) return fail(c, SBP_EINVAL, "bad probe id");
+  if (first < 0 || count < 0 || first + count > c->nstep || first < c->nstep - c->history)
+    return fail(c, SBP_ERANGE, "probe samples not available");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> ring(c->history);
+  HIPCHK(c, hipMemcpy(ring.data(), c->d_probes + (size_t)c->probe_order[id] * c->history, ring.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (long q = 0; q < count; ++q) dst[q] = ring[(first + q) % c->history];
+  return SBP_OK;
+}
+
+sbp_status sbp_state_bytes(const sbp_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return SBP_EINVAL;
+  if (!c->finalized) return SBP_ESTATE;
+  *bytes = c->pool_elems * elem_size(c) + 256;
+  return SBP_OK;
+}
+
+sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
+  if (!c || !dev_buf) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "save_state before finalize");
+  size_t need;
+  sbp_state_bytes(c, &need);
+  if (bytes < need) return fail(c, SBP_EINVAL, "state buffer too small");
+  HIPCHK(c, hipMemcpyAsync(dev_buf, c->pool, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c), c->d_st, sizeof(StepState),
+                           hipMemcpyDeviceToDevice, c->stream));
+  return SBP_OK;
+}
+
+sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
+  if (!c || !dev_buf) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "load_state before finalize");
+  size_t need;
+  sbp_state_bytes(c, &need);
+  if (bytes < need) return fail(c, SBP_EINVAL, "state buffer too small");
+  HIPCHK(c, hipMemcpyAsync(c->pool, dev_buf, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
+  StepState st;
+  HIPCHK(c, hipMemcpyAsync(&st, (const char*)dev_buf + c->pool_elems * elem_size(c), sizeof(StepState),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st.counter = 0;
+  st.flags = 0;
+  HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->nstep = st.step;
+  c->e_energy_dirty = true;
+  return SBP_OK;
+}
+
+sbp_status sbp_use_graph(sbp_ctx* c, int steps) {
+  if (!c || steps < 0) return SBP_EINVAL;
+  if (steps > 0 && c->stream == nullptr)
+    return fail(c, SBP_EINVAL, "graph capture needs a non-default stream");
+  drop_graph(c);
+  c->graph_steps = steps;
+  return SBP_OK;
+}
+
+sbp_status sbp_last_step_ms(sbp_ctx* c, double* ms) {
+  if (!c || !ms) return SBP_EINVAL;
+  if (!c->timed) return fail(c, SBP_ESTATE, "no timed step yet");
+  HIPCHK(c, hipEventSynchronize(c->ev1));
+  float f = 0.0f;
+  HIPCHK(c, hipEventElapsedTime(&f, c->ev0, c->ev1));
+  *ms = f;
+  return SBP_OK;
+}
+
+sbp_status sbp_profile(sbp_ctx* c, int enable) {
+  if (!c) return SBP_EINVAL;
+  c->profile = enable != 0;
+  return SBP_OK;
+}
+
+sbp_status sbp_kernel_ms(sbp_ctx* c, double out[2]) {
+  if (!c || !out) return SBP_EINVAL;
+  if (!c->profile || c->kev_used < 4) return fail(c, SBP_ESTATE, "no profiled step");
+  HIPCHK(c, hipEventSynchronize(c->kev[c->kev_used - 1]));
+  double h = 0.0, e = 0.0;
+  const int steps = c->kev_used / 4;
+  for (int s = 0; s < steps; ++s) {
+    float a = 0.0f, b = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&a, c->kev[4 * s], c->kev[4 * s + 1]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->kev[4 * s + 2], c->kev[4 * s + 3]));
+    h += a;
+    e += b;
+  }
+  out[0] = h / steps;
+  out[1] = e / steps;
+  return SBP_OK;
+}
+
+sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
+  if (!c) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "autotune before finalize");
+  if (steps_per_trial < 1) steps_per_trial = 5;
+  size_t bytes;
+  sbp_state_bytes(c, &bytes);
+  void* save = dalloc(c, bytes);
+  if (!save) return fail(c, SBP_ENOMEM, "autotune snapshot allocation failed");
+  sbp_status st = sbp_save_state(c, save, bytes);
+  if (st != SBP_OK) return st;
+  const int keep[4] = {c->tx, c->ty, c->cz, c->wgs};
+  const bool prof = c->profile;
+  const int gsteps = c->graph_steps;
+  c->profile = false;
+  drop_graph(c);
+  c->graph_steps = 0;
+  int dev_cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+  struct Cand { int tx, ty, cz, wg; };
+  std::vector<Cand> cand;
+  const int txs[3] = {64, 128, 256};
+  const int ths[2] = {256, 512};
+  const int czs[3] = {8, 16, 32};
+  for (int t : ths)
+    for (int tx : txs)
+      for (int cz : czs) {
+        if (t % tx) continue;
+        cand.push_back({tx, t / tx, cz, 0});
+      }
+  cand.push_back({keep[0], keep[1], keep[2], dev_cus * 4});
+  cand.push_back({keep[0], keep[1], keep[2], dev_cus * 8});
+  double best = 1e300;
+  Cand win{keep[0], keep[1], keep[2], keep[3]};
+  for (const Cand& k : cand) {
+    st = sbp_set_launch(c, k.tx, k.ty, k.cz, k.wg);
+    if (st != SBP_OK) break;
+    if ((st = sbp_load_state(c, save, bytes)) != SBP_OK) break;
+    if ((st = sbp_step(c, 1)) != SBP_OK) break;  // warm-up
+    if ((st = sbp_step(c, steps_per_trial)) != SBP_OK) break;
+    double ms = 0.0;
+    if ((st = sbp_last_step_ms(c, &ms)) != SBP_OK) break;
+    ms /= steps_per_trial;
+    if (ms < best) {
+      best = ms;
+      win = k;
+    }
+  }
+  sbp_status st2 = sbp_set_launch(c, win.tx, win.ty, win.cz, win.wg);
+  sbp_status st3 = sbp_load_state(c, save, bytes);
+  dfree(c, save);
+  c->profile = prof;
+  c->graph_steps = gsteps;
+  if (st != SBP_OK) return st;
+  if (st2 != SBP_OK) return st2;
+  if (st3 != SBP_OK) return st3;
+  if (best_ms) *best_ms = best;
+  return SBP_OK;
+}
+
+const char* sbp_last_error(const sbp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void sbp_destroy(sbp_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  drop_graph(c);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
+  std::vector<void*> a = c->allocs;
+  for (void* p : a) dfree(c, p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device-side plan of the SBP-SAT FDTD step: per-block descriptors, tiles,
+// sources, probes and interface gather jobs.  Plain structs shared by the
+// host plan (api.hip) and the kernels (step.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbp {
+
+enum Comp { EX = 0, EY, EZ, HX, HY, HZ };
+
+// One boundary-closure row of D+ or D- along an axis (Appendix), with the
+// SAT row changes of Section III folded in.  The row reads the three
+// consecutive nodes row+s .. row+s+2 with coefficients c (already / h); on an
+// interface face the own boundary coefficient is zero and cn (already / h)
+// multiplies the neighbour value gathered into the face buffer.
+struct Row {
+  int s;
+  int nbr;  // 1: add cn * neighbour face value
+  double c[3];
+  double cn;
+};
+
+// Rows of D+ held in the table: 0, 1, n-1, n.  Rows of D-: 0, 1, 2, n-1, n, n+1.
+constexpr int DP_ROWS = 4;
+constexpr int DM_ROWS = 6;
+
+enum MatFlags { MAT_EPS = 1, MAT_MU = 2, MAT_SIG = 4 };
+
+struct DevBlock {
+  int n[3];
+  int mat;              // MatFlags: which per-cell arrays exist
+  long long sx, sxy;    // node-box strides: node (i,j,k) at i + sx*j + sxy*k
+  long long csz;        // nodes per component (node box (nx+2)(ny+2)(nz+2))
+  long long foff;       // pool offset of component 0; component c at foff + c*csz
+  long long coff;       // offset of this block's cells in the material arrays
+  double h[3], ih[3];
+  double eps_r0, mu_r0, sig0;  // uniform values where no per-cell array
+  Row dp[3][DP_ROWS];
+  Row dm[3][DM_ROWS];
+  int abc_mask;         // bit f: face f absorbing
+  int iface_mask;       // bit f: face f coupled to another block
+  long long fboff[6];   // face-buffer offset (doubles): E slot 0,1 then H slot 0,1
+  long long fsz[6];     // nodes per slot of the face buffer (node-box face)
+  int src0, nsrc, prb0, nprb;
+};
+
+struct Tile {
+  int block, x0, y0, z0;
+};
+
+struct Source {
+  int comp, i, j, k;
+  int wave, pad;
+  double tw, t0, f0, amp;
+};
+
+struct Probe {
+  int comp, i, j, k;
+};
+
+// Interface gather: fills face-buffer slot `slot` (E or H) of (block, face)
+// from the neighbour's face through per-axis tap tables.
+constexpr int MAX_TAPS = 8;
+struct Taps {
+  int start, count;
+  double w[MAX_TAPS];
+};
+struct FaceJob {
+  int block, face, is_h, slot;
+  int comp;             // component gathered
+  int nb;               // neighbour block
+  int nb_idx;           // face-normal node index of the neighbour face
+  int t_axis[2];        // tangential axes (ascending)
+  int ext[2];           // own face-node extents along the tangential axes
+  long long taps_off[2];  // offsets into the tap table for each tangential axis
+};
+
+struct StepState {
+  long long step;       // index n of the next step
+  unsigned int counter; // completion counter of the last-workgroup reduction
+  int flags;            // bit 0: non-finite energy seen
+};
+
+// Arguments of the step kernels (one struct, passed by value).
+struct KArgs {
+  const DevBlock* blocks;
+  const Tile* tiles;
+  int ntiles;
+  int tx, cz;
+  void* pool;
+  const void* mat_eps;
+  const void* mat_mu;
+  const void* mat_sig;
+  const double* face;
+  const Source* src;
+  const Probe* prb;
+  double* energy;
+  int ecap;
+  double* probes;
+  int pcap;
+  double* partials;
+  StepState* st;
+  double dt, eps0, mu0;
+};
+
+}  // namespace sbp

@@ -119,7 +119,8 @@ def config3(scale=1):
         for b in range(3):
             for a in range(3):
                 fine = (a, b, c) == (1, 1, 1)
-                n = tuple((2 * split[t] if fine else split[t]) for t in range(3))
+                pos = (a, b, c)
+                n = tuple((2 * split[pos[t]] if fine else split[pos[t]]) for t in range(3))
                 hh = hf if fine else hc
                 origin = (starts[a] * hc, starts[b] * hc, starts[c] * hc)
                 faces = []

@@ -1,0 +1,323 @@
+"""GPU parity: the HIP step against the fp64 oracle (both forms), element by element.
+
+Tolerances (relative L2 per component array, probe series and energy series):
+fp64 path 1e-12, fp32 path 1e-5 -- the targets of the build, against fp64
+oracle results.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import (COMPS, FLOOR, block, field_errors, gpu_fields, per_field_errors, random_fields, rel_l2,
+                      write_fields)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def sbp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_00638_amd as p
+    p.lib()
+    return p
+
+
+def _run_gpu(sbp, problem, prec, steps, init=None, launch=None):
+    ctx = sbp.build_problem(problem, prec=prec, launch=launch)
+    if init is not None:
+        write_fields(ctx, init)
+    ctx.step(steps)
+    out = {"fields": gpu_fields(ctx, problem), "energy": ctx.read_energy(0, steps),
+           "probes": np.array([ctx.read_probe(p, 0, steps) for p in range(len(problem.get("probes", [])))])}
+    ctx.close()
+    return out
+
+
+def _mixed_problem(seed, n=(21, 18, 23), faces=("pec", "pmc", "abc", "pec", "abc", "pmc")):
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    b = block(n, (1e-3, 1.2e-3, 0.9e-3), faces, eps_r=rng.uniform(1, 4, shape),
+              mu_r=rng.uniform(1, 2, shape), sigma=rng.uniform(0, 0.2, shape))
+    return {"blocks": [b], "interfaces": [], "cfl": 0.9,
+            "sources": [{"block": 0, "comp": "Ez", "node": (7, 9, 11), "waveform": "modgauss",
+                         "tw": 3e-11, "t0": 3e-11, "f0": 1e10, "amp": 1.0},
+                        {"block": 0, "comp": "Ex", "node": (0, 3, 2), "waveform": "gauss",
+                         "tw": 2e-11, "t0": 2e-11, "f0": 0.0, "amp": 0.5}],
+            "probes": [{"block": 0, "comp": "Ez", "node": (3, 4, 5)},
+                       {"block": 0, "comp": "Hy", "node": (0, 4, 5)},
+                       {"block": 0, "comp": "Ex", "node": (n[0] + 1, 2, 1)}]}
+
+
+# ----------------------------------------------------------- config 1
+def test_config1_pec_cavity_fp64(sbp, oracle_lib):
+    from sbp_inputs import make_config
+    prob = make_config(1)
+    steps = prob["steps"]
+    g = _run_gpu(sbp, prob, "f64", steps)
+    r = oracle_lib.run_block(prob)
+    errs = field_errors(g["fields"], {(0, c): r["fields"][c] for c in COMPS}, FLOOR["f64"])
+    assert max(errs.values()) < TOL["f64"], errs
+    assert rel_l2(g["probes"], r["probes"]) < TOL["f64"]
+    assert rel_l2(g["energy"], r["energy"]) < TOL["f64"]
+    # the source is off after ~100 steps: W^n constant (lossless PEC, E17/E18)
+    w = g["energy"][100:]
+    assert np.abs(w / w[0] - 1).max() < 1e-12
+
+
+# ------------------------------------- one block, every face kind, materials
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("launch", [None, (16, 4, 5, 0), (32, 8, 7, 3)])
+def test_mixed_faces_materials(sbp, oracle_lib, prec, launch):
+    prob = _mixed_problem(1)
+    steps = 30
+    init = random_fields(prob, 11)
+    g = _run_gpu(sbp, prob, prec, steps, init=init, launch=launch)
+    r = oracle_lib.run_block(prob, steps=steps, init={c: init[(0, c)] for c in COMPS})
+    errs = field_errors(g["fields"], {(0, c): r["fields"][c] for c in COMPS}, FLOOR[prec])
+    assert max(errs.values()) < TOL[prec], errs
+    assert rel_l2(g["probes"], r["probes"]) < TOL[prec]
+    assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
+
+
+def test_launch_shape_bitwise_invariance(sbp):
+    prob = _mixed_problem(2, n=(37, 9, 13))
+    init = random_fields(prob, 5)
+    for prec in ("f64", "f32"):
+        ref = _run_gpu(sbp, prob, prec, 12, init=init)
+        for launch in [(16, 4, 3, 0), (64, 8, 40, 0), (128, 1, 9, 2), (32, 2, 1, 7)]:
+            g = _run_gpu(sbp, prob, prec, 12, init=init, launch=launch)
+            for k in ref["fields"]:
+                assert np.array_equal(g["fields"][k], ref["fields"][k]), (prec, launch, k)
+            assert np.array_equal(g["probes"], ref["probes"])
+            assert np.allclose(g["energy"], ref["energy"], rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------- interfaces
+def _two_blocks(kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "1:1x":
+        a = block((7, 8, 6), faces=("pec", "pec", "pmc", "pec", "pec", "pmc"))
+        b = block((9, 8, 6), faces=("pec", "pmc", "pmc", "pec", "pec", "pmc"))
+        b["origin"] = (7e-3, 0.0, 0.0)
+        b["eps_r"] = rng.uniform(1, 3, (6, 8, 9))
+        ifc = [(0, 1, 1, 0, 1)]
+    elif kind == "1:2y":   # a coarse below, b fine above in y
+        a = block((6, 5, 7), faces=("pec", "pmc", "pec", "pec", "abc", "pec"))
+        b = block((12, 10, 14), (5e-4, 5e-4, 5e-4), faces=("pec", "pec", "pec", "pmc", "pec", "pec"))
+        b["origin"] = (0.0, 5e-3, 0.0)
+        a["sigma"] = rng.uniform(0, 0.3, (7, 5, 6))
+        ifc = [(0, 3, 1, 2, 2)]
+    else:                  # "1:2z": fine below coarse in z
+        a = block((6, 7, 5), faces=("pmc", "pec", "pec", "pec", "pec", "pec"))
+        b = block((12, 14, 9), (5e-4, 5e-4, 5e-4), faces=("pec", "abc", "pec", "pec", "pec", "pec"))
+        a["origin"] = (0.0, 0.0, 4.5e-3)
+        b["eps_r"] = rng.uniform(1, 2, (9, 14, 12))
+        ifc = [(0, 4, 1, 5, 2)]
+    return {"blocks": [a, b], "interfaces": ifc, "cfl": 0.9,
+            "sources": [{"block": 1, "comp": "Ez", "node": (4, 3, 3), "waveform": "gauss",
+                         "tw": 2e-11, "t0": 2e-11, "f0": 0.0, "amp": 1.0}],
+            "probes": [{"block": 0, "comp": "Ey", "node": (3, 2, 2)},
+                       {"block": 1, "comp": "Hx", "node": (2, 3, 4)}]}
+
+
+@pytest.mark.parametrize("kind", ["1:1x", "1:2y", "1:2z"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_interfaces(sbp, kind, prec):
+    from oracle import system as S
+    prob = _two_blocks(kind, 3)
+    steps = 25
+    init = random_fields(prob, 9)
+    g = _run_gpu(sbp, prob, prec, steps, init=init)
+    r = S.run(prob, steps=steps, init=init)
+    errs = field_errors(g["fields"], r["fields"], FLOOR[prec])
+    assert max(errs.values()) < TOL[prec], errs
+    assert max(per_field_errors(g["fields"], r["fields"]).values()) < TOL[prec]
+    assert rel_l2(g["probes"], r["probes"]) < TOL[prec]
+    assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
+
+
+def test_config3_reduced(sbp):
+    from oracle import system as S
+    from sbp_inputs import make_config
+    prob = make_config(3, scale=8)       # 27 blocks, coarse 24^3 around a fine 12^3
+    steps = 60
+    init = random_fields(prob, 4, scale=1e-3)
+    r = S.run(prob, steps=steps, init=init)
+    for prec in ("f64", "f32"):
+        g = _run_gpu(sbp, prob, prec, steps, init=init)
+        errs = field_errors(g["fields"], r["fields"], FLOOR[prec])
+        assert max(errs.values()) < TOL[prec], (prec, max(errs.items(), key=lambda kv: kv[1]))
+        assert max(per_field_errors(g["fields"], r["fields"]).values()) < TOL[prec]
+        assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
+        assert rel_l2(g["probes"], r["probes"]) < TOL[prec]
+
+
+# ------------------------------------------------------------- config 2
+def test_config2_reduced_fp32(sbp, oracle_lib):
+    from sbp_inputs import make_config
+    prob = make_config(2, scale=8)       # 32^3, 125 steps, same recipe
+    steps = prob["steps"]
+    g = _run_gpu(sbp, prob, "f32", steps)
+    r = oracle_lib.run_block(prob)
+    ref = {(0, c): r["fields"][c] for c in COMPS}
+    errs = field_errors(g["fields"], ref, FLOOR["f32"])
+    print("config2 reduced fp32 errors:", {k[1]: f"{v:.3e}" for k, v in errs.items()},
+          "per field", per_field_errors(g["fields"], ref),
+          "probes", rel_l2(g["probes"], r["probes"]), "energy", rel_l2(g["energy"], r["energy"]),
+          "norms", {c: float(np.linalg.norm(r["fields"][c])) for c in COMPS})
+    assert max(errs.values()) < TOL["f32"], str(errs)
+    assert rel_l2(g["probes"], r["probes"]) < TOL["f32"]
+    assert rel_l2(g["energy"], r["energy"]) < TOL["f32"]
+
+
+def test_config2_full_size_fp32_sampled(sbp, oracle_lib):
+    """256^3 in the benchmark's launch shape, 40 steps from seeded random fields:
+    every node compared with the loop oracle."""
+    from sbp_inputs import make_config
+    prob = make_config(2)
+    steps = 40
+    init = random_fields(prob, 21)
+    ctx = sbp.build_problem(prob, prec="f32")
+    write_fields(ctx, init)
+    ctx.step(steps)
+    g = gpu_fields(ctx, prob)
+    e = ctx.read_energy(0, steps)
+    ctx.close()
+    r = oracle_lib.run_block(prob, steps=steps, init={c: init[(0, c)] for c in COMPS})
+    ref = {(0, c): r["fields"][c] for c in COMPS}
+    errs = field_errors(g, ref, FLOOR["f32"])
+    assert max(errs.values()) < TOL["f32"], errs
+    assert max(per_field_errors(g, ref).values()) < TOL["f32"]
+    assert rel_l2(e, r["energy"]) < TOL["f32"]
+
+
+# -------------------------------------------------- energy, state, graphs
+def test_energy_conserved_lossless_fp64(sbp):
+    prob = {"blocks": [block((14, 12, 16), (1e-3, 1.1e-3, 0.9e-3),
+                             ("pec", "pmc", "pec", "pmc", "pmc", "pec"),
+                             eps_r=np.random.default_rng(0).uniform(1, 4, (16, 12, 14)))],
+            "interfaces": [], "cfl": 0.95, "sources": [], "probes": []}
+    init = random_fields(prob, 3)
+    ctx = sbp.build_problem(prob, prec="f64")
+    write_fields(ctx, init)
+    ctx.step(400)
+    w = ctx.read_energy(0, 400)
+    ctx.close()
+    assert np.abs(w / w[0] - 1).max() < 1e-12
+
+
+def test_energy_nonincreasing_lossy_fp32(sbp):
+    prob = _mixed_problem(4)
+    prob["sources"] = []
+    init = random_fields(prob, 8)
+    ctx = sbp.build_problem(prob, prec="f32")
+    write_fields(ctx, init)
+    ctx.step(200)
+    w = ctx.read_energy(0, 200)
+    ctx.close()
+    assert (np.diff(w) <= 1e-6 * w[:-1]).all()
+    assert w[-1] < w[0]
+
+
+def test_save_load_resume_bitwise(sbp):
+    import torch
+    prob = _mixed_problem(5)
+    init = random_fields(prob, 2)
+    for prec in ("f64", "f32"):
+        a = sbp.build_problem(prob, prec=prec)
+        write_fields(a, init)
+        a.step(20)
+        nb = a.state_bytes()
+        buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        a.save_state(buf.data_ptr(), nb)
+        a.step(15)
+        ref = gpu_fields(a, prob)
+        e_ref = a.read_energy(20, 15)
+        a.load_state(buf.data_ptr(), nb)
+        assert a.steps_done() == 20
+        a.step(15)
+        got = gpu_fields(a, prob)
+        e_got = a.read_energy(20, 15)
+        a.close()
+        for k in ref:
+            assert np.array_equal(ref[k], got[k])
+        assert np.allclose(e_got, e_ref, rtol=1e-14, atol=0)
+
+
+def test_graph_replay_bitwise(sbp):
+    import torch
+    stream = torch.cuda.Stream()
+    prob = _mixed_problem(6)
+    init = random_fields(prob, 1)
+    for prec in ("f64", "f32"):
+        a = sbp.build_problem(prob, prec=prec)
+        write_fields(a, init)
+        a.step(47)
+        ref = gpu_fields(a, prob)
+        e_ref = a.read_energy(0, 47)
+        p_ref = a.read_probe(0, 0, 47)
+        a.close()
+        b = sbp.build_problem(prob, prec=prec, stream=stream)
+        write_fields(b, init)
+        b.use_graph(10)
+        b.step(3)     # eager
+        b.step(44)    # 4 graph replays + 4 eager steps
+        got = gpu_fields(b, prob)
+        e_got = b.read_energy(0, 47)
+        p_got = b.read_probe(0, 0, 47)
+        b.close()
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), (prec, k)
+        assert np.array_equal(p_ref, p_got)
+        assert np.allclose(e_got, e_ref, rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- errors
+def test_error_statuses(sbp):
+    from paper_2206_00638_amd.binding import SBP_EINVAL, SBP_ESTATE, SBP_EUNSTABLE, SBP_ERANGE, Context, SbpError
+    ctx = Context("f64")
+    with pytest.raises(SbpError) as e:
+        ctx.add_block((3, 8, 8), (1e-3,) * 3)
+    assert e.value.status == SBP_EINVAL
+    with pytest.raises(SbpError) as e:
+        ctx.step(1)
+    assert e.value.status == SBP_ESTATE
+    a = ctx.add_block((8, 8, 8), (1e-3,) * 3)
+    b = ctx.add_block((8, 8, 8), (1e-3,) * 3, origin=(8e-3, 0, 0))
+    with pytest.raises(SbpError) as e:
+        ctx.connect(a, 1, b, 0, 3)
+    assert e.value.status == SBP_EINVAL
+    with pytest.raises(SbpError) as e:
+        ctx.connect(a, 1, b, 1, 1)
+    assert e.value.status == SBP_EINVAL
+    with pytest.raises(SbpError) as e:
+        ctx.connect(a, 1, b, 0, 2)           # extents do not match the ratio
+    assert e.value.status == SBP_EINVAL
+    ctx.connect(a, 1, b, 0, 1)
+    with pytest.raises(SbpError) as e:
+        ctx.finalize(1.05)
+    assert e.value.status == SBP_EUNSTABLE
+    ctx.finalize(0.9, history=16)
+    ctx.step(20)
+    with pytest.raises(SbpError) as e:
+        ctx.read_energy(0, 5)                # overwritten in the 16-entry ring
+    assert e.value.status == SBP_ERANGE
+    assert len(ctx.read_energy(10, 10)) == 10
+    ctx.close()
+
+
+def test_unstable_step_flagged(sbp):
+    from paper_2206_00638_amd.binding import SBP_EUNSTABLE, SbpError
+    prob = {"blocks": [block((8, 8, 8))], "interfaces": [], "cfl": 1.6, "sources": [], "probes": []}
+    ctx = sbp.build_problem(prob, prec="f64", force=True)
+    write_fields(ctx, random_fields(prob, 0))
+    ctx.step(3000)
+    with pytest.raises(SbpError) as e:
+        ctx.read_energy(2990, 10)
+    assert e.value.status == SBP_EUNSTABLE
+    ctx.close()
