@@ -130,9 +130,10 @@ sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
 sbp_status sbp_save_state(sbp_ctx *ctx, void *dev_buf, size_t bytes);
 sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
 
-/* Launch shape of the step kernels: tile tx*ty nodes in x*y, cz planes in z
- * per tile, `workgroups` resident workgroups looping over the tile list (0 =
- * one workgroup per tile).  tx*ty must be 64, 128, 256 or 512. */
+/* Launch shape of the step kernels: a tile is tx*ty consecutive nodes of a
+ * block's xy node plane (i fastest) over cz planes, one node per thread and
+ * plane; `workgroups` resident workgroups loop over the tile list (0 = one
+ * workgroup per tile).  tx*ty must be 64, 128 or 256. */
 sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
 sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
 

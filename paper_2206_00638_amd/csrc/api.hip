@@ -20,9 +20,10 @@
 #include "plan.h"
 
 namespace sbp {
-template <typename T> hipError_t launch_h(const KArgs&, int, int, hipStream_t);
-template <typename T> hipError_t launch_e(const KArgs&, int, int, hipStream_t);
+template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream_t);
+template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_e_energy(const KArgs&, int, int, hipStream_t);
+hipError_t launch_finish(const KArgs&, int, int, int, hipStream_t);
 template <typename T>
 hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*,
                          hipStream_t);
@@ -84,6 +85,7 @@ struct sbp_ctx {
   std::vector<DevBlock> hblocks;
   Tile* d_tiles = nullptr;
   int ntiles = 0;
+  int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
   size_t tiles_cap = 0;
   Source* d_src = nullptr;
   Probe* d_prb = nullptr;
@@ -98,7 +100,7 @@ struct sbp_ctx {
   FaceJob* d_jobs_h = nullptr;
   int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
   Taps* d_taps = nullptr;
-  int tx = 64, ty = 4, cz = 16, wgs = 0;
+  int tx = 256, ty = 1, cz = 1, wgs = 0;
   bool e_energy_dirty = true;
   std::string err;
   int graph_steps = 0;
@@ -401,13 +403,50 @@ void drop_graph(sbp_ctx* c) {
   c->graph = nullptr;
 }
 
+int round8(size_t v) { return (int)((v + 7) / 8 * 8); }
+
+// Workgroups of a step launch: one per tile (or the resident count set by
+// sbp_set_launch), rounded up to a multiple of the 8 XCDs so the kernels can
+// hand each XCD a contiguous range of tiles.
+int grid_of(const sbp_ctx* c, int ntiles) {
+  const int g = c->wgs > 0 ? std::min(c->wgs, ntiles) : ntiles;
+  return round8((size_t)std::max(g, 1));
+}
+
+// Kind of a block for the step kernels: bit 0 = per-cell permittivity,
+// bit 1 = general (conductivity, absorbing faces, per-cell permeability or
+// interface faces); plain PEC/PMC blocks take the lean kernels.
+int block_kind(const HostBlock& b) {
+  bool gen = !b.mu.empty() || !b.sig.empty();
+  for (int f = 0; f < 6; ++f) gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
+  return (b.eps.empty() ? 0 : 1) | (gen ? 2 : 0);
+}
+
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
-  for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
-    const HostBlock& b = c->blocks[bi];
-    for (int z0 = 0; z0 < b.n[2] + 2; z0 += c->cz)
-      for (int y0 = 0; y0 < b.n[1] + 2; y0 += c->ty)
-        for (int x0 = 0; x0 < b.n[0] + 2; x0 += c->tx) tl.push_back(Tile{(int)bi, x0, y0, z0});
+  const int threads = c->tx * c->ty;
+  for (int kind = 0; kind < 4; ++kind) {
+    c->kind_t0[kind] = (int)tl.size();
+    for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+      const HostBlock& b = c->blocks[bi];
+      if (block_kind(b) != kind) continue;
+      const int sx = b.n[0] + 2, nplane = sx * (b.n[1] + 2);
+      for (int z0 = 0; z0 < b.n[2] + 2; z0 += c->cz)
+        for (int q0 = 0; q0 < nplane; q0 += threads) {
+          // flags: bit 0 = a source, bit 1 = a probe lies in the tile
+          int flags = 0;
+          auto inside = [&](int i, int j, int k) {
+            const int q = i + sx * j;
+            return q >= q0 && q < q0 + threads && k >= z0 && k < z0 + c->cz;
+          };
+          for (auto& sr : c->srcs)
+            if (sr.block == (int)bi && inside(sr.s.i, sr.s.j, sr.s.k)) flags |= 1;
+          for (auto& pr : c->prbs)
+            if (pr.block == (int)bi && inside(pr.p.i, pr.p.j, pr.p.k)) flags |= 2;
+          tl.push_back(Tile{(int)bi, q0, z0, flags});
+        }
+    }
+    c->kind_t1[kind] = (int)tl.size();
   }
   if (tl.size() > c->tiles_cap) {
     dfree(c, c->d_tiles);
@@ -417,7 +456,11 @@ sbp_status build_tiles(sbp_ctx* c) {
   }
   c->ntiles = (int)tl.size();
   HIPCHK(c, hipMemcpyAsync(c->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
-  const size_t grid = c->wgs > 0 ? std::min<size_t>(c->wgs, tl.size()) : tl.size();
+  size_t grid = (size_t)grid_of(c, c->ntiles);
+  size_t sum = 0;
+  for (int kind = 0; kind < 4; ++kind)
+    if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
+  grid = std::max(grid, sum);
   if (grid > c->partials_cap) {
     dfree(c, c->d_partials);
     c->d_partials = (double*)dalloc(c, grid * sizeof(double));
@@ -434,8 +477,8 @@ KArgs kargs(sbp_ctx* c) {
   a.blocks = c->d_blocks;
   a.tiles = c->d_tiles;
   a.ntiles = c->ntiles;
-  a.tx = c->tx;
   a.cz = c->cz;
+  a.pad_ = 0;
   a.pool = c->pool;
   a.mat_eps = c->mat[0];
   a.mat_mu = c->mat[1];
@@ -452,10 +495,14 @@ KArgs kargs(sbp_ctx* c) {
   a.dt = c->dt;
   a.eps0 = kEps0;
   a.mu0 = kMu0;
+  a.nblocks = (int)c->blocks.size();
+  a.t0 = 0;
+  a.t1 = c->ntiles;
+  a.poff = 0;
   return a;
 }
 
-int grid_size(const sbp_ctx* c) { return c->wgs > 0 ? std::min(c->wgs, c->ntiles) : c->ntiles; }
+int grid_size(const sbp_ctx* c) { return grid_of(c, c->ntiles); }
 
 sbp_status enqueue_e_energy(sbp_ctx* c) {
   const KArgs a = kargs(c);
@@ -463,14 +510,17 @@ sbp_status enqueue_e_energy(sbp_ctx* c) {
   hipError_t e = c->prec == SBP_FP64 ? launch_e_energy<double>(a, grid_size(c), threads, c->stream)
                                      : launch_e_energy<float>(a, grid_size(c), threads, c->stream);
   HIPCHK(c, e);
+  HIPCHK(c, launch_finish(a, grid_size(c), 0, 0, c->stream));  // slot n = E part of W^n
   return SBP_OK;
 }
 
-// One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E update.
+// One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E
+// update, each update one launch per block kind followed by the energy
+// finish: slot n += H part of W^n; slot n+1 = E part of W^{n+1}, and the
+// step index advances.
 sbp_status enqueue_step(sbp_ctx* c, bool events) {
-  const KArgs a = kargs(c);
+  KArgs a = kargs(c);
   const int threads = c->tx * c->ty;
-  const int grid = grid_size(c);
   const bool f64 = c->prec == SBP_FP64;
   hipError_t e;
   if (c->njobs_e) {
@@ -479,8 +529,18 @@ sbp_status enqueue_step(sbp_ctx* c, bool events) {
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
-  e = f64 ? launch_h<double>(a, grid, threads, c->stream) : launch_h<float>(a, grid, threads, c->stream);
-  HIPCHK(c, e);
+  int nparts = 0;
+  for (int kind = 0; kind < 4; ++kind) {
+    if (c->kind_t1[kind] == c->kind_t0[kind]) continue;
+    a.t0 = c->kind_t0[kind];
+    a.t1 = c->kind_t1[kind];
+    a.poff = nparts;
+    const int grid = grid_of(c, a.t1 - a.t0);
+    nparts += grid;
+    e = f64 ? launch_h<double>(a, kind, grid, threads, c->stream) : launch_h<float>(a, kind, grid, threads, c->stream);
+    HIPCHK(c, e);
+  }
+  HIPCHK(c, launch_finish(a, nparts, FIN_ADD, 0, c->stream));  // slot n += H part of W^n
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   if (c->njobs_h) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream)
@@ -488,8 +548,18 @@ sbp_status enqueue_step(sbp_ctx* c, bool events) {
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
-  e = f64 ? launch_e<double>(a, grid, threads, c->stream) : launch_e<float>(a, grid, threads, c->stream);
-  HIPCHK(c, e);
+  nparts = 0;
+  for (int kind = 0; kind < 4; ++kind) {
+    if (c->kind_t1[kind] == c->kind_t0[kind]) continue;
+    a.t0 = c->kind_t0[kind];
+    a.t1 = c->kind_t1[kind];
+    a.poff = nparts;
+    const int grid = grid_of(c, a.t1 - a.t0);
+    nparts += grid;
+    e = f64 ? launch_e<double>(a, kind, grid, threads, c->stream) : launch_e<float>(a, kind, grid, threads, c->stream);
+    HIPCHK(c, e);
+  }
+  HIPCHK(c, launch_finish(a, nparts, FIN_STEP, 1, c->stream));  // slot n+1 = E part of W^{n+1}; n += 1
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   return SBP_OK;
 }
@@ -701,6 +771,14 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
       }
     }
     build_rows(b, d);
+    d.db_u = c->dt / (kMu0 * d.mu_r0);
+    d.cb_u = c->dt / (kEps0 * d.eps_r0);
+    d.dte0x4 = 4.0 * c->dt / kEps0;
+    d.hdte0 = c->dt / (2.0 * kEps0);
+    d.dtm0x2 = 2.0 * c->dt / kMu0;
+    d.ke = 0.5 * kEps0 * b.h[0] * b.h[1] * b.h[2];
+    d.kh = 0.5 * kMu0 * b.h[0] * b.h[1] * b.h[2];
+
     d.src0 = (int)dsrc.size();
     for (auto& s : c->srcs)
       if (s.block == (int)bi) dsrc.push_back(s.s);
@@ -849,7 +927,7 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
 sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
   if (!c) return SBP_EINVAL;
   const int t = tx * ty;
-  if (tx < 1 || ty < 1 || (t != 64 && t != 128 && t != 256 && t != 512)) return fail(c, SBP_EINVAL, "tx*ty must be 64, 128, 256 or 512");
+  if (tx < 1 || ty < 1 || (t != 64 && t != 128 && t != 256)) return fail(c, SBP_EINVAL, "tx*ty must be 64, 128 or 256");
   if (cz < 1 || workgroups < 0) return fail(c, SBP_EINVAL, "bad cz or workgroups");
   c->tx = tx;
   c->ty = ty;
@@ -1108,15 +1186,10 @@ sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
   struct Cand { int tx, ty, cz, wg; };
   std::vector<Cand> cand;
-  const int txs[3] = {64, 128, 256};
-  const int ths[2] = {256, 512};
-  const int czs[3] = {8, 16, 32};
+  const int ths[3] = {64, 128, 256};
+  const int czs[3] = {1, 2, 4};
   for (int t : ths)
-    for (int tx : txs)
-      for (int cz : czs) {
-        if (t % tx) continue;
-        cand.push_back({tx, t / tx, cz, 0});
-      }
+    for (int cz : czs) cand.push_back({t, 1, cz, 0});
   cand.push_back({keep[0], keep[1], keep[2], dev_cus * 4});
   cand.push_back({keep[0], keep[1], keep[2], dev_cus * 8});
   double best = 1e300;

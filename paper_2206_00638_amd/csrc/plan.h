@@ -43,10 +43,19 @@ struct DevBlock {
   long long fboff[6];   // face-buffer offset (doubles): E slot 0,1 then H slot 0,1
   long long fsz[6];     // nodes per slot of the face buffer (node-box face)
   int src0, nsrc, prb0, nprb;
+  // fast-path constants (interior nodes), in fp64; cast to the field type
+  double db_u;    // dt / (mu0 mu_r0): H update with uniform permeability
+  double cb_u;    // dt / (eps0 eps_r0): E update with uniform permittivity, lossless
+  double dte0x4;  // 4 dt / eps0: Cb = dte0x4 / (sum of the four cell eps_r)
+  double hdte0;   // dt / (2 eps0): loss factor b = hdte0 * sigma_sum / eps_sum
+  double dtm0x2;  // 2 dt / mu0: Db = dtm0x2 / (sum of the two cell mu_r)
+  double ke, kh;  // 1/2 eps0 hx hy hz, 1/2 mu0 hx hy hz (energy of an interior node)
 };
 
+// A tile is a run of consecutive nodes q0 .. q0+threads-1 of the flattened
+// (i fastest) xy node plane of one block, over planes z0 .. z0+cz-1.
 struct Tile {
-  int block, x0, y0, z0;
+  int block, q0, z0, pad;
 };
 
 struct Source {
@@ -82,12 +91,16 @@ struct StepState {
   int flags;            // bit 0: non-finite energy seen
 };
 
+// Energy-finish modes: FIN_ADD = add the total to the ring slot instead of
+// storing it; FIN_STEP = advance the step index afterwards.
+enum { FIN_ADD = 2, FIN_STEP = 4 };
+
 // Arguments of the step kernels (one struct, passed by value).
 struct KArgs {
   const DevBlock* blocks;
   const Tile* tiles;
   int ntiles;
-  int tx, cz;
+  int cz, pad_;
   void* pool;
   const void* mat_eps;
   const void* mat_mu;
@@ -102,6 +115,9 @@ struct KArgs {
   double* partials;
   StepState* st;
   double dt, eps0, mu0;
+  int nblocks;
+  int t0, t1;  // tile range of this launch
+  int poff;    // first partial-sum slot of this launch
 };
 
 }  // namespace sbp

@@ -1,23 +1,32 @@
 // Leapfrog step kernels of the 3D SBP-SAT FDTD method for gfx950.
 //
-// Memory-bound staggered stencil: one thread per (i, j) node column of a
-// tile, marching through the tile's z planes so that the z-neighbour of the
-// previous plane stays in registers; x/y neighbours come from the wave's own
-// loads through the L1/L2.  Interior rows are the two-point Yee difference
-// (Section II-A: the interior nodes are Yee's); rows within two (D+) or three
-// (D-) nodes of a block face take the Appendix closure rows with the SAT row
+// Memory-bound staggered stencil, one launch per half step over every node
+// of every block.  A tile is a run of consecutive nodes of the flattened
+// (i fastest) xy node plane of one block; each thread owns one (i, j) node
+// column and marches through the tile's z planes, so the z-neighbour of the
+// previous plane stays in registers and every wave reads 64 contiguous
+// values per array.  Interior rows are the two-point Yee difference (Section
+// II-A: the interior nodes are Yee's); rows within two (D+) or three (D-)
+// nodes of a block face take the Appendix closure rows with the SAT row
 // changes folded in (PEC in the H update, PMC / absorbing in the E update,
-// interface rows reading gathered neighbour values).  Every node update is a
-// pure function of the previous fields, so results do not depend on the
-// tile shape or on how tiles map to workgroups.
+// interface rows adding the gathered neighbour value): per lane for x, per
+// thread for y, per plane (wave-uniform) for z.  All in the field precision;
+// energies and interface interpolation accumulate in fp64.  Every node
+// update is a pure function of the previous fields, so the results do not
+// depend on the tile shape or on how tiles map to workgroups.
 //
-// The discrete energy W^n (E16 with the leapfrog pairing of H) is reduced in
+// The tile list is walked XCD-aware: the workgroups resident on one XCD take
+// a contiguous range of tiles, so the y-neighbour rows a tile re-reads were
+// fetched into the same L2 by the tile before it.
+//
+// The discrete energy W^n (E16 with the leapfrog pairing of H) is summed in
 // fp64 per workgroup and finished by the last workgroup of each launch.
 
 #include "plan.h"
 
 namespace sbp {
 
+constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -42,7 +51,7 @@ __device__ __forceinline__ double face_value(const KArgs& a, const DevBlock& B, 
 }
 
 // D- row r along `axis` applied to u at node offset o (the node with index r
-// on that axis), times 1/h.  Closure rows come from the block's table.
+// on that axis), times 1/h, in fp64.  Closure rows come from the block's table.
 template <typename T>
 __device__ __forceinline__ double dminus(const KArgs& a, const DevBlock& B, int axis, const T* u,
                                          long long o, long long st, int r, int slot, int i, int j,
@@ -57,7 +66,7 @@ __device__ __forceinline__ double dminus(const KArgs& a, const DevBlock& B, int 
   return v;
 }
 
-// D+ row r along `axis`, times 1/h.
+// D+ row r along `axis`, times 1/h, in fp64.
 template <typename T>
 __device__ __forceinline__ double dplus(const KArgs& a, const DevBlock& B, int axis, const T* u,
                                         long long o, long long st, int r, int slot, int i, int j,
@@ -73,9 +82,8 @@ __device__ __forceinline__ double dplus(const KArgs& a, const DevBlock& B, int a
 }
 
 template <typename T>
-__device__ __forceinline__ T cell(const void* arr, long long coff, const DevBlock& B, int ci, int cj,
-                                  int ck) {
-  return ((const T*)arr)[coff + ci + (long long)B.n[0] * (cj + (long long)B.n[1] * ck)];
+__device__ __forceinline__ double cellv(const void* arr, const DevBlock& B, int ci, int cj, int ck) {
+  return (double)((const T*)arr)[B.coff + ci + (long long)B.n[0] * (cj + (long long)B.n[1] * ck)];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -90,13 +98,10 @@ __device__ __forceinline__ double load_coherent(const double* p) {
   return __longlong_as_double((long long)b);
 }
 
-// Reduces `v` over the launch.  The last workgroup to finish writes (E
-// update: slot n+1 = sum) or adds (H update: slot n += sum) the total, flags
-// a non-finite energy, resets the counter and, for the E update, advances
-// the step index.
-__device__ void finish_energy(double v, const KArgs& a, long long nstep, bool e_mode) {
+// Workgroup sum of `v`, stored to partials[poff + blockIdx.x]; the launch's
+// total is formed later by k_finish, in a fixed order (deterministic).
+__device__ void store_partial(double v, const KArgs& a) {
   __shared__ double red[16];
-  __shared__ int last;
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = v;
@@ -104,146 +109,136 @@ __device__ void finish_energy(double v, const KArgs& a, long long nstep, bool e_
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[w];
-    a.partials[blockIdx.x] = s;
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.st->counter, 1u);
-    last = (prev == gridDim.x - 1);
+    a.partials[a.poff + blockIdx.x] = s;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+// Sums partials[0 .. nparts) (one workgroup, fixed order) into the energy
+// ring: slot (step + delta) = total, or += total when `mode` has FIN_ADD;
+// flags a non-finite energy; FIN_STEP advances the step index.
+__global__ __launch_bounds__(1024) void k_finish(double* partials, int nparts, double* energy, int ecap,
+                                                 StepState* st, int mode, int delta) {
+  __shared__ double red[16];
   double s = 0.0;
-  for (int p = threadIdx.x; p < (int)gridDim.x; p += blockDim.x) s += load_coherent(a.partials + p);
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += partials[p];
   s = wave_sum(s);
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < nw; ++w) tot += red[w];
-    if (e_mode) {
-      const int slot = (int)((nstep + 1) % a.ecap);
-      a.energy[slot] = tot;
-    } else {
-      const int slot = (int)(nstep % a.ecap);
-      tot += a.energy[slot];
-      a.energy[slot] = tot;
-    }
-    if (!isfinite(tot)) a.st->flags |= 1;
-    a.st->counter = 0;
-    if (e_mode) a.st->step = nstep + 1;
+    const long long n = st->step;
+    const int slot = (int)((n + delta) % ecap);
+    if (mode & FIN_ADD) tot += energy[slot];
+    energy[slot] = tot;
+    if (!isfinite(tot)) st->flags |= 1;
+    if (mode & FIN_STEP) st->step = n + 1;
   }
 }
 
-// ---------------------------------------------------------------- H update
-// H^{n+1/2} = H^{n-1/2} + dt/mu * (E10-E12 with the PEC/interface rows),
-// plus the H part of W^n: 1/2 mu w H^{n+1/2} H^{n-1/2}.
-template <typename T>
-__global__ __launch_bounds__(512) void k_h_update(KArgs a) {
-  double eacc = 0.0;
-  const long long nstep = a.st->step;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const Tile tl = a.tiles[t];
-    const DevBlock& B = a.blocks[tl.block];
-    const int i = tl.x0 + (int)threadIdx.x % a.tx;
-    const int j = tl.y0 + (int)threadIdx.x / a.tx;
-    const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    if (i > nx + 1 || j > ny + 1) continue;
-    const int k0 = tl.z0, k1 = min(tl.z0 + a.cz, nz + 2);
-    const long long sx = B.sx, sxy = B.sxy;
-    T* base = (T*)a.pool + B.foff;
-    const T* Ex = base;
-    const T* Ey = base + B.csz;
-    const T* Ez = base + 2 * B.csz;
-    T* Hx = base + 3 * B.csz;
-    T* Hy = base + 4 * B.csz;
-    T* Hz = base + 5 * B.csz;
-    const double mu_u = a.mu0 * B.mu_r0;
-    const bool xin = i >= 3 && i <= nx - 2, yin = j >= 3 && j <= ny - 2;
-    const bool has_mu = B.mat & MAT_MU;
-    // probes of this column (H components)
-    int pk[2] = {-1, -1}, pc[2] = {0, 0}, pid[2] = {0, 0};
-    {
-      int q = 0;
-      for (int p = 0; p < B.nprb && q < 2; ++p) {
-        const Probe& P = a.prb[B.prb0 + p];
-        if (P.comp >= HX && P.i == i && P.j == j && P.k >= k0 && P.k < k1) {
-          pk[q] = P.k; pc[q] = P.comp; pid[q] = B.prb0 + p; ++q;
-        }
-      }
-    }
-    const double wxp = wplus(nx, i, B.h[0]), wxm = wminus(nx, i, B.h[0]);
-    const double wyp = wplus(ny, j, B.h[1]), wym = wminus(ny, j, B.h[1]);
-    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-    const int cj0 = clampi(j - 1, 0, ny - 1);
-    const int cj1 = clampi(j, 0, ny - 1);
-    long long o = i + sx * j + sxy * k0;
-    T exm = T(0), eym = T(0);
-    if (k0 > 0) { exm = Ex[o - sxy]; eym = Ey[o - sxy]; }
-    for (int k = k0; k < k1; ++k, o += sxy) {
-      const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
-      const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
-      const bool zin = k >= 3 && k <= nz - 2;
-      // node permeability: mean over the (two) cells containing the H node
-      double mux = mu_u, muy = mu_u, muz = mu_u;
-      if (has_mu) {
-        const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
-        const double A0 = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck0);
-        const double B0 = (double)cell<T>(a.mat_mu, B.coff, B, ci1, cj0, ck0);
-        const double C0 = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj1, ck0);
-        const double A1 = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck1);
-        mux = a.mu0 * (0.5 * (A0 + B0));
-        muy = a.mu0 * (0.5 * (A0 + C0));
-        muz = a.mu0 * (0.5 * (A0 + A1));
-      }
-      const double dbx = a.dt / mux, dby = a.dt / muy, dbz = a.dt / muz;
-      T nhx = hx, nhy = hy, nhz = hz;
-      if (xin && yin && zin) {
-        const T ez_im = Ez[o - 1], ey_im = Ey[o - 1];
-        const T ez_jm = Ez[o - sx], ex_jm = Ex[o - sx];
-        nhx = hx + (T)dbx * ((ey - eym) * (T)B.ih[2] - (ez - ez_jm) * (T)B.ih[1]);
-        nhy = hy + (T)dby * ((ez - ez_im) * (T)B.ih[0] - (ex - exm) * (T)B.ih[2]);
-        nhz = hz + (T)dbz * ((ex - ex_jm) * (T)B.ih[1] - (ey - ey_im) * (T)B.ih[0]);
-      } else {
-        if (i <= nx) {  // Hx (x+, y-, z-): dz Ey - dy Ez
-          const double d = dminus<T>(a, B, 2, Ey, o, sxy, k, 1, i, j, k) -
-                           dminus<T>(a, B, 1, Ez, o, sx, j, 1, i, j, k);
-          nhx = (T)((double)hx + dbx * d);
-        }
-        if (j <= ny) {  // Hy (x-, y+, z-): dx Ez - dz Ex
-          const double d = dminus<T>(a, B, 0, Ez, o, 1, i, 1, i, j, k) -
-                           dminus<T>(a, B, 2, Ex, o, sxy, k, 0, i, j, k);
-          nhy = (T)((double)hy + dby * d);
-        }
-        if (k <= nz) {  // Hz (x-, y-, z+): dy Ex - dx Ey
-          const double d = dminus<T>(a, B, 1, Ex, o, sx, j, 0, i, j, k) -
-                           dminus<T>(a, B, 0, Ey, o, 1, i, 0, i, j, k);
-          nhz = (T)((double)hz + dbz * d);
-        }
-      }
-      const double wzp = wplus(nz, k, B.h[2]), wzm = wminus(nz, k, B.h[2]);
-      if (i <= nx) {
-        Hx[o] = nhx;
-        eacc += 0.5 * mux * wxp * wym * wzm * (double)nhx * (double)hx;
-      }
-      if (j <= ny) {
-        Hy[o] = nhy;
-        eacc += 0.5 * muy * wxm * wyp * wzm * (double)nhy * (double)hy;
-      }
-      if (k <= nz) {
-        Hz[o] = nhz;
-        eacc += 0.5 * muz * wxm * wym * wzp * (double)nhz * (double)hz;
-      }
-      for (int q = 0; q < 2; ++q)
-        if (pk[q] == k) {
-          const T v = pc[q] == HX ? nhx : (pc[q] == HY ? nhy : nhz);
-          a.probes[(long long)pid[q] * a.pcap + nstep % a.pcap] = (double)v;
-        }
-      exm = ex;
-      eym = ey;
+// Walks the tile list so that the workgroups on one XCD (workgroup g sits on
+// XCD g % 8) take a contiguous range of tiles.  The host rounds the grid up
+// to a multiple of 8; surplus workgroups only join the energy reduction.
+struct TileIter {
+  int t, stop, stride;
+  __device__ explicit TileIter(int ntiles) {
+    const int g = blockIdx.x, G = gridDim.x;
+    if (G % kXcds == 0) {
+      const int per = (ntiles + kXcds - 1) / kXcds;
+      const int x = g % kXcds;
+      t = x * per + g / kXcds;
+      stop = min((x + 1) * per, ntiles);
+      stride = G / kXcds;
+    } else {
+      t = g;
+      stop = ntiles;
+      stride = G;
     }
   }
-  finish_energy(eacc, a, nstep, false);
+  __device__ bool next(int& out) {
+    if (t >= stop) return false;
+    out = t;
+    t += stride;
+    return true;
+  }
+};
+
+// ------------------------------------------------------------- rows
+// One row of D+ or D- along an axis at node index r, coefficients in the
+// field precision: interior rows are flagged (two-point difference), closure
+// rows read three consecutive nodes r+s .. r+s+2 (Appendix rows with the
+// Section III SAT row changes), plus cn times the gathered neighbour value on
+// interface faces.  Rows outside the operator's range (components that do
+// not exist there) are zero.
+template <typename T>
+struct TRow {
+  int s, nbr, in;
+  T c0, c1, c2, cn;
+};
+
+template <typename T>
+__device__ __forceinline__ TRow<T> row_of(const DevBlock& B, int axis, int r, bool minus) {
+  TRow<T> R;
+  const int n = B.n[axis];
+  R.nbr = 0;
+  R.cn = T(0);
+  R.in = minus ? (r >= 3 && r <= n - 2) : (r >= 2 && r <= n - 2);
+  if (R.in) {
+    R.s = minus ? -1 : 0;
+    R.c0 = -(T)B.ih[axis];
+    R.c1 = (T)B.ih[axis];
+    R.c2 = T(0);
+  } else if (!minus && r > n) {  // no D+ row: the E component does not exist here
+    R.s = -2;
+    R.c0 = R.c1 = R.c2 = T(0);
+  } else {
+    const Row& X = minus ? B.dm[axis][r < 3 ? r : r - (n - 1) + 3] : B.dp[axis][r < 2 ? r : r - (n - 1) + 2];
+    R.s = X.s;
+    R.c0 = (T)X.c[0];
+    R.c1 = (T)X.c[1];
+    R.c2 = (T)X.c[2];
+    R.nbr = X.nbr;
+    R.cn = (T)X.cn;
+  }
+  return R;
+}
+
+// Closure row applied to u along stride st at node offset o; `face`/`slot`
+// locate the gathered neighbour value of an interface row.
+template <typename T, bool IFACE>
+__device__ __forceinline__ T drow(const KArgs& a, const DevBlock& B, const T* __restrict__ u, long long o,
+                                  long long st, const TRow<T>& R, int face, int is_h, int slot, int i, int j,
+                                  int k) {
+  const T* p = u + o + (long long)R.s * st;
+  T v = R.c0 * p[0] + R.c1 * p[st] + R.c2 * p[2 * st];
+  if constexpr (IFACE) {
+    if (R.nbr) v += R.cn * (T)face_value(a, B, face, is_h, slot, i, j, k);
+  }
+  return v;
+}
+
+// Norm weights / h (Appendix P+, P-) of node r on an axis of n cells.
+__device__ __forceinline__ float wp1(int n, int r) { return (r == 0 || r == n) ? 0.5f : 1.0f; }
+__device__ __forceinline__ float wm1(int n, int r) {
+  if (r == 0 || r == n + 1) return 0.5f;
+  if (r == 1 || r == n) return 0.25f;
+  if (r == 2 || r == n - 1) return 1.25f;
+  return 1.0f;
+}
+
+// Probe samples of node (i, j, k): probes of the given field on that node
+// take the new values (only for tiles flagged as holding a probe).
+template <typename T>
+__device__ __forceinline__ void take_probes(const KArgs& a, const DevBlock& B, int i, int j, int k, bool h_field,
+                                            long long nstep, T v0, T v1, T v2) {
+  for (int p = 0; p < B.nprb; ++p) {
+    const Probe& P = a.prb[B.prb0 + p];
+    if ((P.comp >= HX) == h_field && P.i == i && P.j == j && P.k == k) {
+      const int c = P.comp % 3;
+      a.probes[(long long)(B.prb0 + p) * a.pcap + nstep % a.pcap] = (double)(c == 0 ? v0 : (c == 1 ? v1 : v2));
+    }
+  }
 }
 
 __device__ __forceinline__ double waveform(const Source& s, double t) {
@@ -252,201 +247,358 @@ __device__ __forceinline__ double waveform(const Source& s, double t) {
   return s.wave == 1 ? sin(2.0 * M_PI * s.f0 * t) * g : g;
 }
 
-// ---------------------------------------------------------------- E update
-// E^{n+1} = Ca E^n + Cb (E7-E9 with the PMC/absorbing/interface rows + J),
-// plus the E part of W^{n+1}: 1/2 eps w (E^{n+1})^2.
+// Current density of the block's sources on node (i, j, k) (tiles flagged as holding a source).
 template <typename T>
-__global__ __launch_bounds__(512) void k_e_update(KArgs a) {
+__device__ __forceinline__ void source_terms(const KArgs& a, const DevBlock& B, int i, int j, int k, double t,
+                                             T& jx, T& jy, T& jz) {
+  for (int p = 0; p < B.nsrc; ++p) {
+    const Source& S = a.src[B.src0 + p];
+    if (S.i == i && S.j == j && S.k == k) {
+      const T v = (T)(S.amp * waveform(S, t));
+      if (S.comp == EX) jx += v;
+      else if (S.comp == EY) jy += v;
+      else jz += v;
+    }
+  }
+}
+
+// Read-only tables (block descriptors, tile list) are read through the
+// constant address space so that wave-uniform reads become scalar loads.
+#define SBP_CONST __attribute__((address_space(4)))
+template <typename X>
+__device__ __forceinline__ const SBP_CONST X* as_const(const X* p) {
+  return (const SBP_CONST X*)p;
+}
+
+// Per-tile copy of the block constants the node updates use (registers;
+// the closure tables stay in the descriptor, read by boundary rows only).
+template <typename T>
+struct BC {
+  int nx, ny, nz, mat, abc;
+  long long sx, sxy;
+  T ihx, ihy, ihz;
+  T db_u, dtm0x2, mu_r0;               // H update
+  T cb_u, dte0x4, hdte0, eps_r0, sig0;  // E update
+  long long coff;
+  __device__ explicit BC(const SBP_CONST DevBlock& B) {
+    nx = B.n[0]; ny = B.n[1]; nz = B.n[2]; mat = B.mat; abc = B.abc_mask;
+    sx = B.sx; sxy = B.sxy; coff = B.coff;
+    ihx = (T)B.ih[0]; ihy = (T)B.ih[1]; ihz = (T)B.ih[2];
+    db_u = (T)B.db_u; dtm0x2 = (T)B.dtm0x2; mu_r0 = (T)B.mu_r0;
+    cb_u = (T)B.cb_u; dte0x4 = (T)B.dte0x4; hdte0 = (T)B.hdte0; eps_r0 = (T)B.eps_r0; sig0 = (T)B.sig0;
+  }
+};
+
+// ------------------------------------------------------------- H update
+// H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
+// components, with the closure / PEC / interface rows.  Returns the node's
+// (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
+template <typename T, bool GEN>
+__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const T* __restrict__ Ex,
+                                    const T* __restrict__ Ey, const T* __restrict__ Ez, T* __restrict__ Hx,
+                                    T* __restrict__ Hy, T* __restrict__ Hz, const T* __restrict__ M, int i,
+                                    int j, int k, long long o, T& onx, T& ony, T& onz) {
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const long long sx = c.sx, sxy = c.sxy;
+  const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
+  const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
+  const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
+  const bool xin = i >= 3 && i <= nx - 2, yin = j >= 3 && j <= ny - 2, zin = k >= 3 && k <= nz - 2;
+  T dzEy, dzEx, dyEz, dyEx, dxEz, dxEy;
+  if (zin) {
+    dzEy = (ey - Ey[o - sxy]) * ihz;
+    dzEx = (ex - Ex[o - sxy]) * ihz;
+  } else {
+    const TRow<T> rz = row_of<T>(B, 2, k, true);
+    const int f = k < 3 ? 4 : 5;
+    dzEy = drow<T, GEN>(a, B, Ey, o, sxy, rz, f, 0, 1, i, j, k);
+    dzEx = drow<T, GEN>(a, B, Ex, o, sxy, rz, f, 0, 0, i, j, k);
+  }
+  if (yin) {
+    dyEz = (ez - Ez[o - sx]) * ihy;
+    dyEx = (ex - Ex[o - sx]) * ihy;
+  } else {
+    const TRow<T> ry = row_of<T>(B, 1, j, true);
+    const int f = j < 3 ? 2 : 3;
+    dyEz = drow<T, GEN>(a, B, Ez, o, sx, ry, f, 0, 1, i, j, k);
+    dyEx = drow<T, GEN>(a, B, Ex, o, sx, ry, f, 0, 0, i, j, k);
+  }
+  if (xin) {
+    dxEz = (ez - Ez[o - 1]) * ihx;
+    dxEy = (ey - Ey[o - 1]) * ihx;
+  } else {
+    const TRow<T> rx = row_of<T>(B, 0, i, true);
+    const int f = i < 3 ? 0 : 1;
+    dxEz = drow<T, GEN>(a, B, Ez, o, 1, rx, f, 0, 1, i, j, k);
+    dxEy = drow<T, GEN>(a, B, Ey, o, 1, rx, f, 0, 0, i, j, k);
+  }
+  const T db_u = c.db_u, mu_r0 = c.mu_r0;
+  T dbx = db_u, dby = db_u, dbz = db_u, mx = mu_r0, my = mu_r0, mz = mu_r0;
+  if (GEN && M) {  // node permeability: mean of the (two) cells containing the node
+    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
+    const long long cp = (long long)nx * ny;
+    const long long c0 = c.coff + ci0 + (long long)nx * cj0 + cp * clampi(k - 1, 0, nz - 1);
+    const T A0 = M[c0];
+    mx = T(0.5) * (A0 + M[c0 + (ci1 - ci0)]);
+    my = T(0.5) * (A0 + M[c0 + (long long)(cj1 - cj0) * nx]);
+    mz = T(0.5) * (A0 + M[c.coff + ci0 + (long long)nx * cj0 + cp * clampi(k, 0, nz - 1)]);
+    const T dtm0x2 = c.dtm0x2;
+    dbx = dtm0x2 / (mx + mx);
+    dby = dtm0x2 / (my + my);
+    dbz = dtm0x2 / (mz + mz);
+  }
+  const T nhx = hx + dbx * (dzEy - dyEz);
+  const T nhy = hy + dby * (dxEz - dzEx);
+  const T nhz = hz + dbz * (dyEx - dxEy);
+  const bool vx = i <= nx, vy = j <= ny, vz = k <= nz;
+  if (vx) Hx[o] = nhx;
+  if (vy) Hy[o] = nhy;
+  if (vz) Hz[o] = nhz;
+  onx = nhx;
+  ony = nhy;
+  onz = nhz;
+  if (xin && yin && zin) return mx * (nhx * hx) + my * (nhy * hy) + mz * (nhz * hz);
+  const T wx = vx ? (T)(wp1(nx, i) * wm1(ny, j) * wm1(nz, k)) : T(0);
+  const T wy = vy ? (T)(wm1(nx, i) * wp1(ny, j) * wm1(nz, k)) : T(0);
+  const T wz = vz ? (T)(wm1(nx, i) * wm1(ny, j) * wp1(nz, k)) : T(0);
+  return wx * mx * (nhx * hx) + wy * my * (nhy * hy) + wz * mz * (nhz * hz);
+}
+
+// H half step over the tiles [t0, t1) of the tile list (one kind of block),
+// one node per thread in linear (i, j, k) order, plus the H part of W^n:
+// 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
+template <typename T, bool GEN>
+__global__ __launch_bounds__(256) void k_h_update(KArgs a) {
+  double eacc = 0.0;
+  const long long nstep = a.st->step;
+  TileIter it(a.t1 - a.t0);
+  for (int tv; it.next(tv);) {
+    const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
+    const SBP_CONST Tile& tl = as_const(a.tiles)[t];
+    const int tb = tl.block, tq0 = tl.q0, tz0 = tl.z0, tflags = tl.pad;
+    const DevBlock& B = a.blocks[tb];
+    const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
+    const BC<T> c(Bc);
+    const double kh = Bc.kh;
+    const int sx = (int)c.sx, sy = c.ny + 2;
+    const int q = tq0 + (int)threadIdx.x;
+    const int j = q / sx, i = q - j * sx;
+    if (j >= sy) continue;
+    T* base = (T*)a.pool + Bc.foff;
+    const long long csz = Bc.csz;
+    const T* M = (GEN && (c.mat & MAT_MU)) ? (const T*)a.mat_mu : nullptr;
+    const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
+    double es = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const long long o = (long long)q + c.sxy * k;
+      T v0, v1, v2;
+      es += (double)h_node<T, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
+                           base + 5 * csz, M, i, j, k, o, v0, v1, v2);
+      if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
+    }
+    eacc += kh * es;
+  }
+  store_partial(eacc, a);
+}
+
+// ------------------------------------------------------------- E update
+// E^{n+1} = Ca E^n + Cb (E7-E9 + J) at node (i, j, k), all valid E
+// components, with the closure / PMC / absorbing / interface rows; the
+// absorbing damping 2/(eta h) on tangential face nodes joins the
+// semi-implicit loss.  Returns the node's 4 eps_r (w/h^3) (E^{n+1})^2.
+template <typename T, bool HAS_EPS, bool GEN>
+__device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<T>& c, T* __restrict__ Ex,
+                                    T* __restrict__ Ey,
+                                    T* __restrict__ Ez, const T* __restrict__ Hx, const T* __restrict__ Hy,
+                                    const T* __restrict__ Hz, const T* __restrict__ ME,
+                                    const T* __restrict__ MS, int i, int j, int k, long long o, T jx, T jy,
+                                    T jz, T& onx, T& ony, T& onz) {
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const long long sx = c.sx, sxy = c.sxy;
+  const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
+  const bool xin = i >= 2 && i <= nx - 2, yin = j >= 2 && j <= ny - 2, zin = k >= 2 && k <= nz - 2;
+  const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
+  const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
+  T dzHy, dzHx, dyHz, dyHx, dxHz, dxHy;
+  if (zin) {
+    dzHy = (Hy[o + sxy] - hy) * ihz;
+    dzHx = (Hx[o + sxy] - hx) * ihz;
+  } else if (k <= nz) {
+    const TRow<T> rz = row_of<T>(B, 2, k, false);
+    const int f = k < 2 ? 4 : 5;
+    dzHy = drow<T, GEN>(a, B, Hy, o, sxy, rz, f, 1, 1, i, j, k);
+    dzHx = drow<T, GEN>(a, B, Hx, o, sxy, rz, f, 1, 0, i, j, k);
+  } else {
+    dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
+  }
+  if (yin) {
+    dyHz = (Hz[o + sx] - hz) * ihy;
+    dyHx = (Hx[o + sx] - hx) * ihy;
+  } else {
+    const TRow<T> ry = row_of<T>(B, 1, j, false);
+    const int f = j < 2 ? 2 : 3;
+    dyHz = drow<T, GEN>(a, B, Hz, o, sx, ry, f, 1, 1, i, j, k);
+    dyHx = drow<T, GEN>(a, B, Hx, o, sx, ry, f, 1, 0, i, j, k);
+  }
+  if (xin) {
+    dxHz = (Hz[o + 1] - hz) * ihx;
+    dxHy = (Hy[o + 1] - hy) * ihx;
+  } else {
+    const TRow<T> rx = row_of<T>(B, 0, i, false);
+    const int f = i < 2 ? 0 : 1;
+    dxHz = drow<T, GEN>(a, B, Hz, o, 1, rx, f, 1, 1, i, j, k);
+    dxHy = drow<T, GEN>(a, B, Hy, o, 1, rx, f, 1, 0, i, j, k);
+  }
+  const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
+  // the four cells around the node column at planes k-1 (0) and k (1):
+  // A (i-1, j-1), B (i, j-1), C (i-1, j), D (i, j), clamped to the block
+  const bool inner = i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1 && k >= 1 && k <= nz - 1;
+  const long long cnx = nx, cp = (long long)nx * ny;
+  long long cA, cP0, cP1;
+  int dxc, dyc;
+  if (inner) {
+    cA = c.coff + (i - 1) + cnx * (j - 1);
+    dxc = 1;
+    dyc = nx;
+    cP0 = cp * (k - 1);
+    cP1 = cP0 + cp;
+  } else {
+    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
+    cA = c.coff + ci0 + cnx * cj0;
+    dxc = ci1 - ci0;
+    dyc = (cj1 - cj0) * nx;
+    cP0 = cp * clampi(k - 1, 0, nz - 1);
+    cP1 = cp * clampi(k, 0, nz - 1);
+  }
+  const T eps_r0 = c.eps_r0;
+  T mx = T(4) * eps_r0, my = mx, mz = mx;  // node permittivity x4: sums of the four containing cells
+  if (HAS_EPS) {
+    const T* p0 = ME + cA + cP0;
+    const T* p1 = ME + cA + cP1;
+    const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
+    const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
+    mx = (a0 + c0) + (a1 + c1);
+    my = (a0 + b0) + (a1 + b1);
+    mz = (a0 + b0) + (c0 + d0);
+  }
+  T cax = T(1), cay = T(1), caz = T(1), cbx, cby, cbz;
+  if (HAS_EPS) {
+    const T dte0x4 = c.dte0x4;
+    cbx = dte0x4 / mx;
+    cby = dte0x4 / my;
+    cbz = dte0x4 / mz;
+  } else {
+    cbx = cby = cbz = c.cb_u;
+  }
+  if (GEN) {
+    const int am = c.abc;
+    const T gx = (T)((int)(i == 0 && (am & 1)) + (int)(i == nx && (am & 2))) * ihx;
+    const T gy = (T)((int)(j == 0 && (am & 4)) + (int)(j == ny && (am & 8))) * ihy;
+    const T gz = (T)((int)(k == 0 && (am & 16)) + (int)(k == nz && (am & 32))) * ihz;
+    const T gEx = gy + gz, gEy = gx + gz, gEz = gx + gy;
+    const bool lossy = MS != nullptr || c.sig0 != T(0);
+    if (lossy || gEx != T(0) || gEy != T(0) || gEz != T(0)) {
+      // b = dt (sigma + sigma_abc) / (2 eps), sigma_abc = 2 g / eta, eta = sqrt(mu/eps);
+      // Ca = (1-b)/(1+b), Cb = (dt/eps)/(1+b)
+      const T sig0 = c.sig0;
+      T sx4 = T(4) * sig0, sy4 = sx4, sz4 = sx4;
+      if (MS) {
+        const T* p0 = MS + cA + cP0;
+        const T* p1 = MS + cA + cP1;
+        const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
+        const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
+        sx4 = (a0 + c0) + (a1 + c1);
+        sy4 = (a0 + b0) + (a1 + b1);
+        sz4 = (a0 + b0) + (c0 + d0);
+      }
+      if (gEx != T(0) || gEy != T(0) || gEz != T(0)) {
+        T mux = T(4) * (T)B.mu_r0, muy = mux, muz = mux;  // node mu_r x4
+        if (c.mat & MAT_MU) {
+          const T* MM = (const T*)a.mat_mu;
+          const T* p0 = MM + cA + cP0;
+          const T* p1 = MM + cA + cP1;
+          const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
+          const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
+          mux = (a0 + c0) + (a1 + c1);
+          muy = (a0 + b0) + (a1 + b1);
+          muz = (a0 + b0) + (c0 + d0);
+        }
+        const T me0 = (T)(a.mu0 / a.eps0);
+        if (gEx != T(0)) sx4 += T(8) * gEx / sqrt(me0 * mux / mx);
+        if (gEy != T(0)) sy4 += T(8) * gEy / sqrt(me0 * muy / my);
+        if (gEz != T(0)) sz4 += T(8) * gEz / sqrt(me0 * muz / mz);
+      }
+      const T hdte0 = c.hdte0, dte0x4 = c.dte0x4;
+      const T bx = hdte0 * sx4 / mx, by = hdte0 * sy4 / my, bz = hdte0 * sz4 / mz;
+      const T rxx = T(1) / (T(1) + bx), ryy = T(1) / (T(1) + by), rzz = T(1) / (T(1) + bz);
+      cax = (T(1) - bx) * rxx;
+      cay = (T(1) - by) * ryy;
+      caz = (T(1) - bz) * rzz;
+      cbx = dte0x4 / mx * rxx;
+      cby = dte0x4 / my * ryy;
+      cbz = dte0x4 / mz * rzz;
+    }
+  }
+  const T nex = cax * ex + cbx * (cx + jx);
+  const T ney = cay * ey + cby * (cy + jy);
+  const T nez = caz * ez + cbz * (cz + jz);
+  const bool vz = k <= nz;
+  const bool vEx = j <= ny && vz, vEy = i <= nx && vz, vEz = i <= nx && j <= ny;
+  if (vEx) Ex[o] = nex;
+  if (vEy) Ey[o] = ney;
+  if (vEz) Ez[o] = nez;
+  onx = nex;
+  ony = ney;
+  onz = nez;
+  // norm weights / h: 1 inside, Appendix P+ / P- on the boundary rows
+  const T wx = vEx ? (T)(wm1(nx, i) * wp1(ny, j) * wp1(nz, k)) : T(0);
+  const T wy = vEy ? (T)(wp1(nx, i) * wm1(ny, j) * wp1(nz, k)) : T(0);
+  const T wz = vEz ? (T)(wp1(nx, i) * wp1(ny, j) * wm1(nz, k)) : T(0);
+  return wx * mx * (nex * nex) + wy * my * (ney * ney) + wz * mz * (nez * nez);
+}
+
+// E step over the tiles [t0, t1) of the tile list (one kind of block), one
+// node per thread in linear (i, j, k) order, plus the E part of W^{n+1}:
+// 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
+// index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
+template <typename T, bool HAS_EPS, bool GEN>
+__global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
   const double tsrc = ((double)nstep + 0.5) * a.dt;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const Tile tl = a.tiles[t];
-    const DevBlock& B = a.blocks[tl.block];
-    const int i = tl.x0 + (int)threadIdx.x % a.tx;
-    const int j = tl.y0 + (int)threadIdx.x / a.tx;
-    const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    if (i > nx + 1 || j > ny + 1) continue;
-    const int k0 = tl.z0, k1 = min(tl.z0 + a.cz, nz + 2);
-    const long long sx = B.sx, sxy = B.sxy;
-    T* base = (T*)a.pool + B.foff;
-    T* Ex = base;
-    T* Ey = base + B.csz;
-    T* Ez = base + 2 * B.csz;
-    const T* Hx = base + 3 * B.csz;
-    const T* Hy = base + 4 * B.csz;
-    const T* Hz = base + 5 * B.csz;
-    const bool xin = i >= 2 && i <= nx - 2, yin = j >= 2 && j <= ny - 2;
-    const bool has_eps = B.mat & MAT_EPS, has_sig = B.mat & MAT_SIG;
-    // sources and probes of this column
-    int sk[2] = {-1, -1}, sc[2] = {0, 0};
-    double sv[2] = {0.0, 0.0};
-    int pk[2] = {-1, -1}, pc[2] = {0, 0}, pid[2] = {0, 0};
-    {
-      int q = 0;
-      for (int s = 0; s < B.nsrc && q < 2; ++s) {
-        const Source& S = a.src[B.src0 + s];
-        if (S.i == i && S.j == j && S.k >= k0 && S.k < k1) {
-          sk[q] = S.k; sc[q] = S.comp; sv[q] = S.amp * waveform(S, tsrc); ++q;
-        }
-      }
-      q = 0;
-      for (int p = 0; p < B.nprb && q < 2; ++p) {
-        const Probe& P = a.prb[B.prb0 + p];
-        if (P.comp < HX && P.i == i && P.j == j && P.k >= k0 && P.k < k1) {
-          pk[q] = P.k; pc[q] = P.comp; pid[q] = B.prb0 + p; ++q;
-        }
-      }
+  TileIter it(a.t1 - a.t0);
+  for (int tv; it.next(tv);) {
+    const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
+    const SBP_CONST Tile& tl = as_const(a.tiles)[t];
+    const int tb = tl.block, tq0 = tl.q0, tz0 = tl.z0, tflags = tl.pad;
+    const DevBlock& B = a.blocks[tb];
+    const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
+    const BC<T> c(Bc);
+    const double ke4 = 0.25 * Bc.ke;
+    const int sx = (int)c.sx, sy = c.ny + 2;
+    const int q = tq0 + (int)threadIdx.x;
+    const int j = q / sx, i = q - j * sx;
+    if (j >= sy) continue;
+    T* base = (T*)a.pool + Bc.foff;
+    const long long csz = Bc.csz;
+    const T* ME = (const T*)a.mat_eps;
+    const T* MS = (GEN && (c.mat & MAT_SIG)) ? (const T*)a.mat_sig : nullptr;
+    const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
+    double es = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const long long o = (long long)q + c.sxy * k;
+      T jx = T(0), jy = T(0), jz = T(0);
+      if (tflags & 1) source_terms<T>(a, B, i, j, k, tsrc, jx, jy, jz);
+      T v0, v1, v2;
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
+                                    base + 5 * csz, ME, MS, i, j, k, o, jx, jy, jz, v0, v1, v2);
+      if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
     }
-    const double wxp = wplus(nx, i, B.h[0]), wxm = wminus(nx, i, B.h[0]);
-    const double wyp = wplus(ny, j, B.h[1]), wym = wminus(ny, j, B.h[1]);
-    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
-    // per-cell permittivity / conductivity of the 2x2 cell columns around (i, j)
-    double eA0 = B.eps_r0, eB0 = B.eps_r0, eC0 = B.eps_r0, eD0 = B.eps_r0;
-    double sA0 = B.sig0, sB0 = B.sig0, sC0 = B.sig0, sD0 = B.sig0;
-    {
-      const int ck = clampi(k0 - 1, 0, nz - 1);
-      if (has_eps) {
-        eA0 = (double)cell<T>(a.mat_eps, B.coff, B, ci0, cj0, ck);
-        eB0 = (double)cell<T>(a.mat_eps, B.coff, B, ci1, cj0, ck);
-        eC0 = (double)cell<T>(a.mat_eps, B.coff, B, ci0, cj1, ck);
-        eD0 = (double)cell<T>(a.mat_eps, B.coff, B, ci1, cj1, ck);
-      }
-      if (has_sig) {
-        sA0 = (double)cell<T>(a.mat_sig, B.coff, B, ci0, cj0, ck);
-        sB0 = (double)cell<T>(a.mat_sig, B.coff, B, ci1, cj0, ck);
-        sC0 = (double)cell<T>(a.mat_sig, B.coff, B, ci0, cj1, ck);
-        sD0 = (double)cell<T>(a.mat_sig, B.coff, B, ci1, cj1, ck);
-      }
-    }
-    long long o = i + sx * j + sxy * k0;
-    T hx = Hx[o], hy = Hy[o];
-    for (int k = k0; k < k1; ++k, o += sxy) {
-      const int ck = clampi(k, 0, nz - 1);
-      double eA1 = B.eps_r0, eB1 = B.eps_r0, eC1 = B.eps_r0, eD1 = B.eps_r0;
-      double sA1 = B.sig0, sB1 = B.sig0, sC1 = B.sig0, sD1 = B.sig0;
-      if (has_eps) {
-        eA1 = (double)cell<T>(a.mat_eps, B.coff, B, ci0, cj0, ck);
-        eB1 = (double)cell<T>(a.mat_eps, B.coff, B, ci1, cj0, ck);
-        eC1 = (double)cell<T>(a.mat_eps, B.coff, B, ci0, cj1, ck);
-        eD1 = (double)cell<T>(a.mat_eps, B.coff, B, ci1, cj1, ck);
-      }
-      if (has_sig) {
-        sA1 = (double)cell<T>(a.mat_sig, B.coff, B, ci0, cj0, ck);
-        sB1 = (double)cell<T>(a.mat_sig, B.coff, B, ci1, cj0, ck);
-        sC1 = (double)cell<T>(a.mat_sig, B.coff, B, ci0, cj1, ck);
-        sD1 = (double)cell<T>(a.mat_sig, B.coff, B, ci1, cj1, ck);
-      }
-      // node means over the containing cells
-      const double epx = a.eps0 * (0.25 * ((eA0 + eC0) + (eA1 + eC1)));
-      const double epy = a.eps0 * (0.25 * ((eA0 + eB0) + (eA1 + eB1)));
-      const double epz = a.eps0 * (0.25 * ((eA0 + eB0) + (eC0 + eD0)));
-      double sgx = 0.25 * ((sA0 + sC0) + (sA1 + sC1));
-      double sgy = 0.25 * ((sA0 + sB0) + (sA1 + sB1));
-      double sgz = 0.25 * ((sA0 + sB0) + (sC0 + sD0));
-      const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
-      const T hz = Hz[o];
-      const bool zin = k >= 2 && k <= nz - 2;
-      const T hxn = (k + 1 < nz + 2) ? Hx[o + sxy] : T(0);
-      const T hyn = (k + 1 < nz + 2) ? Hy[o + sxy] : T(0);
-      double cx, cy, cz;  // curl terms (E7-E9), already / h
-      bool fast = xin && yin && zin;
-      T fcx = T(0), fcy = T(0), fcz = T(0);
-      if (fast) {
-        const T hz_ip = Hz[o + 1], hy_ip = Hy[o + 1];
-        const T hz_jp = Hz[o + sx], hx_jp = Hx[o + sx];
-        fcx = (hz_jp - hz) * (T)B.ih[1] - (hyn - hy) * (T)B.ih[2];
-        fcy = (hxn - hx) * (T)B.ih[2] - (hz_ip - hz) * (T)B.ih[0];
-        fcz = (hy_ip - hy) * (T)B.ih[0] - (hx_jp - hx) * (T)B.ih[1];
-        cx = cy = cz = 0.0;
-      } else {
-        cx = cy = cz = 0.0;
-        if (j <= ny && k <= nz)  // Ex (x-, y+, z+): dy Hz - dz Hy
-          cx = dplus<T>(a, B, 1, Hz, o, sx, j, 1, i, j, k) - dplus<T>(a, B, 2, Hy, o, sxy, k, 1, i, j, k);
-        if (i <= nx && k <= nz)  // Ey (x+, y-, z+): dz Hx - dx Hz
-          cy = dplus<T>(a, B, 2, Hx, o, sxy, k, 0, i, j, k) - dplus<T>(a, B, 0, Hz, o, 1, i, 1, i, j, k);
-        if (i <= nx && j <= ny)  // Ez (x+, y+, z-): dx Hy - dy Hx
-          cz = dplus<T>(a, B, 0, Hy, o, 1, i, 0, i, j, k) - dplus<T>(a, B, 1, Hx, o, sx, j, 0, i, j, k);
-        // absorbing faces: damping 2/(eta h) on tangential E nodes of the face
-        if (B.abc_mask) {
-          auto eta_at = [&](int comp) {
-            double mu = B.mu_r0;
-            if (B.mat & MAT_MU) {
-              // node mean of mu over the cells containing the E node
-              const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = ck;
-              double s = 0.0;
-              if (comp == EX) s = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck0) + (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj1, ck0) +
-                                  (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck1) + (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj1, ck1);
-              else if (comp == EY) s = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck0) + (double)cell<T>(a.mat_mu, B.coff, B, ci1, cj0, ck0) +
-                                       (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck1) + (double)cell<T>(a.mat_mu, B.coff, B, ci1, cj0, ck1);
-              else s = (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj0, ck0) + (double)cell<T>(a.mat_mu, B.coff, B, ci1, cj0, ck0) +
-                       (double)cell<T>(a.mat_mu, B.coff, B, ci0, cj1, ck0) + (double)cell<T>(a.mat_mu, B.coff, B, ci1, cj1, ck0);
-              mu = 0.25 * s;
-            }
-            const double ep = comp == EX ? epx : (comp == EY ? epy : epz);
-            return sqrt(a.mu0 * mu / ep);
-          };
-          const int r[3] = {i, j, k};
-          for (int ax = 0; ax < 3; ++ax) {
-            const bool lo = r[ax] == 0 && (B.abc_mask >> (2 * ax) & 1);
-            const bool hi = r[ax] == B.n[ax] && (B.abc_mask >> (2 * ax + 1) & 1);
-            const int m = (int)lo + (int)hi;
-            if (!m) continue;
-            const double g = m * 2.0 * B.ih[ax];
-            if (ax != 0) sgx += g / eta_at(EX);
-            if (ax != 1) sgy += g / eta_at(EY);
-            if (ax != 2) sgz += g / eta_at(EZ);
-          }
-        }
-      }
-      // sources (current density inside the Cb bracket)
-      double jx = 0.0, jy = 0.0, jz = 0.0;
-      for (int q = 0; q < 2; ++q)
-        if (sk[q] == k) {
-          if (sc[q] == EX) jx += sv[q];
-          else if (sc[q] == EY) jy += sv[q];
-          else jz += sv[q];
-        }
-      // semi-implicit loss: Ca = (1-b)/(1+b), Cb = (dt/eps)/(1+b), b = dt sigma/(2 eps)
-      const double bx = a.dt * sgx / (2.0 * epx), by = a.dt * sgy / (2.0 * epy), bz = a.dt * sgz / (2.0 * epz);
-      const double cbx = (a.dt / epx) / (1.0 + bx), cby = (a.dt / epy) / (1.0 + by), cbz = (a.dt / epz) / (1.0 + bz);
-      const double cax = (1.0 - bx) / (1.0 + bx), cay = (1.0 - by) / (1.0 + by), caz = (1.0 - bz) / (1.0 + bz);
-      T nex = ex, ney = ey, nez = ez;
-      if (fast) {
-        nex = (T)cax * ex + (T)cbx * (fcx + (T)jx);
-        ney = (T)cay * ey + (T)cby * (fcy + (T)jy);
-        nez = (T)caz * ez + (T)cbz * (fcz + (T)jz);
-      } else {
-        if (j <= ny && k <= nz) nex = (T)(cax * (double)ex + cbx * (cx + jx));
-        if (i <= nx && k <= nz) ney = (T)(cay * (double)ey + cby * (cy + jy));
-        if (i <= nx && j <= ny) nez = (T)(caz * (double)ez + cbz * (cz + jz));
-      }
-      const double wzp = wplus(nz, k, B.h[2]), wzm = wminus(nz, k, B.h[2]);
-      if (j <= ny && k <= nz) {
-        Ex[o] = nex;
-        eacc += 0.5 * epx * wxm * wyp * wzp * (double)nex * (double)nex;
-      }
-      if (i <= nx && k <= nz) {
-        Ey[o] = ney;
-        eacc += 0.5 * epy * wxp * wym * wzp * (double)ney * (double)ney;
-      }
-      if (i <= nx && j <= ny) {
-        Ez[o] = nez;
-        eacc += 0.5 * epz * wxp * wyp * wzm * (double)nez * (double)nez;
-      }
-      for (int q = 0; q < 2; ++q)
-        if (pk[q] == k) {
-          const T v = pc[q] == EX ? nex : (pc[q] == EY ? ney : nez);
-          a.probes[(long long)pid[q] * a.pcap + nstep % a.pcap] = (double)v;
-        }
-      hx = hxn;
-      hy = hyn;
-      eA0 = eA1; eB0 = eB1; eC0 = eC1; eD0 = eD1;
-      sA0 = sA1; sB0 = sB1; sC0 = sC1; sD0 = sD1;
-    }
+    eacc += ke4 * es;
   }
-  finish_energy(eacc, a, nstep, true);
+  store_partial(eacc, a);
 }
 
 // E part of W^n for the current fields (after a field write or a restore).
@@ -454,13 +606,15 @@ template <typename T>
 __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  TileIter it(a.ntiles);
+  for (int t; it.next(t);) {
     const Tile tl = a.tiles[t];
     const DevBlock& B = a.blocks[tl.block];
-    const int i = tl.x0 + (int)threadIdx.x % a.tx;
-    const int j = tl.y0 + (int)threadIdx.x / a.tx;
     const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    if (i > nx + 1 || j > ny + 1) continue;
+    const int sx = (int)B.sx;
+    const int q = tl.q0 + (int)threadIdx.x;
+    if (q >= sx * (ny + 2)) continue;
+    const int j = q / sx, i = q - j * sx;
     const int k0 = tl.z0, k1 = min(tl.z0 + a.cz, nz + 2);
     const T* base = (const T*)a.pool + B.foff;
     const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
@@ -469,9 +623,7 @@ __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
     for (int k = k0; k < k1; ++k) {
       const long long o = i + B.sx * j + B.sxy * k;
       const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
-      auto ev = [&](int ci, int cj, int ck) {
-        return has_eps ? (double)cell<T>(a.mat_eps, B.coff, B, ci, cj, ck) : B.eps_r0;
-      };
+      auto ev = [&](int ci, int cj, int ck) { return has_eps ? cellv<T>(a.mat_eps, B, ci, cj, ck) : B.eps_r0; };
       const double epx = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci0, cj1, ck0)) + (ev(ci0, cj0, ck1) + ev(ci0, cj1, ck1))));
       const double epy = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci1, cj0, ck0)) + (ev(ci0, cj0, ck1) + ev(ci1, cj0, ck1))));
       const double epz = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci1, cj0, ck0)) + (ev(ci0, cj1, ck0) + ev(ci1, cj1, ck0))));
@@ -483,8 +635,7 @@ __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
       if (i <= nx && j <= ny) { const double v = (double)base[2 * B.csz + o]; eacc += 0.5 * epz * wxp * wyp * wzm * v * v; }
     }
   }
-  // write slot n (not n+1): shift the step seen by finish_energy by one
-  finish_energy(eacc, a, nstep - 1, true);
+  store_partial(eacc, a);
 }
 
 // ------------------------------------------------------- interface gather
@@ -526,19 +677,31 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 }
 
 // ------------------------------------------------------------- launchers
+// kind bit 0: per-cell permittivity; bit 1: general block (loss, absorbing
+// faces, per-cell permeability, interfaces).
 template <typename T>
-hipError_t launch_h(const KArgs& a, int grid, int threads, hipStream_t s) {
-  hipLaunchKernelGGL(k_h_update<T>, dim3(grid), dim3(threads), 0, s, a);
+hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
+  if (kind & 2) hipLaunchKernelGGL((k_h_update<T, true>), dim3(grid), dim3(threads), 0, s, a);
+  else hipLaunchKernelGGL((k_h_update<T, false>), dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_e(const KArgs& a, int grid, int threads, hipStream_t s) {
-  hipLaunchKernelGGL(k_e_update<T>, dim3(grid), dim3(threads), 0, s, a);
+hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
+  switch (kind & 3) {
+    case 0: hipLaunchKernelGGL((k_e_update<T, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_e_update<T, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_e_update<T, false, true>), dim3(grid), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_e_update<T, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_e_energy(const KArgs& a, int grid, int threads, hipStream_t s) {
   hipLaunchKernelGGL(k_e_energy<T>, dim3(grid), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_finish(const KArgs& a, int nparts, int mode, int delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a.partials, nparts, a.energy, a.ecap, a.st, mode, delta);
   return hipGetLastError();
 }
 template <typename T>
@@ -550,10 +713,10 @@ hipError_t launch_gather(const DevBlock* blocks, const FaceJob* jobs, int njobs,
   return hipGetLastError();
 }
 
-template hipError_t launch_h<float>(const KArgs&, int, int, hipStream_t);
-template hipError_t launch_h<double>(const KArgs&, int, int, hipStream_t);
-template hipError_t launch_e<float>(const KArgs&, int, int, hipStream_t);
-template hipError_t launch_e<double>(const KArgs&, int, int, hipStream_t);
+template hipError_t launch_h<float>(const KArgs&, int, int, int, hipStream_t);
+template hipError_t launch_h<double>(const KArgs&, int, int, int, hipStream_t);
+template hipError_t launch_e<float>(const KArgs&, int, int, int, hipStream_t);
+template hipError_t launch_e<double>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_e_energy<float>(const KArgs&, int, int, hipStream_t);
 template hipError_t launch_e_energy<double>(const KArgs&, int, int, hipStream_t);
 template hipError_t launch_gather<float>(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*, hipStream_t);
