@@ -88,6 +88,8 @@ struct sbp_ctx {
   int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
   size_t tiles_cap = 0;
   Source* d_src = nullptr;
+  double* d_srcval = nullptr;
+  int nsrc_total = 0;
   Probe* d_prb = nullptr;
   std::vector<int> probe_order;  // user probe id -> device probe index
   double* d_energy = nullptr;
@@ -436,7 +438,7 @@ sbp_status build_tiles(sbp_ctx* c) {
           // flags: bit 0 = a source, bit 1 = a probe lies in the tile
           int flags = 0;
           auto inside = [&](int i, int j, int k) {
-            const int q = i + sx * j;
+            const int q = plane_index(i, j, b.n[0], b.n[1]);
             return q >= q0 && q < q0 + threads && k >= z0 && k < z0 + c->cz;
           };
           for (auto& sr : c->srcs)
@@ -485,6 +487,8 @@ KArgs kargs(sbp_ctx* c) {
   a.mat_sig = c->mat[2];
   a.face = c->d_face;
   a.src = c->d_src;
+  a.srcval = c->d_srcval;
+  a.nsrc = c->nsrc_total;
   a.prb = c->d_prb;
   a.energy = c->d_energy;
   a.ecap = (int)c->history;
@@ -816,17 +820,20 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->pool = dalloc(c, foff * elem_size(c));
   c->d_blocks = (DevBlock*)dalloc(c, c->hblocks.size() * sizeof(DevBlock));
   c->d_src = (Source*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(Source));
+  c->d_srcval = (double*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(double));
+  c->nsrc_total = (int)dsrc.size();
   c->d_prb = (Probe*)dalloc(c, std::max<size_t>(dprb.size(), 1) * sizeof(Probe));
   c->d_energy = (double*)dalloc(c, (size_t)history * sizeof(double));
   c->d_probes = (double*)dalloc(c, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double));
   c->d_st = (StepState*)dalloc(c, sizeof(StepState));
   c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
-  if (!c->pool || !c->d_blocks || !c->d_src || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
+  if (!c->pool || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
     return fail(c, SBP_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_energy, 0, (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_probes, 0, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_srcval, 0, std::max<size_t>(dsrc.size(), 1) * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_face, 0, std::max<size_t>(fboff, 1) * sizeof(double), c->stream));
   if (!dsrc.empty())
     HIPCHK(c, hipMemcpyAsync(c->d_src, dsrc.data(), dsrc.size() * sizeof(Source), hipMemcpyHostToDevice, c->stream));

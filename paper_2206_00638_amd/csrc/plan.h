@@ -52,8 +52,34 @@ struct DevBlock {
   double ke, kh;  // 1/2 eps0 hx hy hz, 1/2 mu0 hx hy hz (energy of an interior node)
 };
 
-// A tile is a run of consecutive nodes q0 .. q0+threads-1 of the flattened
-// (i fastest) xy node plane of one block, over planes z0 .. z0+cz-1.
+// Thread order of the nodes of an xy node plane ((nx+2) x (ny+2) nodes, i
+// fastest in memory): first the nodes with 3 <= i <= nx-2, row by row, then
+// the six columns i = 0, 1, 2, nx-1, nx, nx+1 of every row.  The waves of
+// the first part all take the two-point interior difference along x, so the
+// closure rows do not split them.
+__host__ __device__ inline void plane_node(int q, int nx, int ny, int& i, int& j) {
+  const int w = nx - 4;  // interior x nodes per row
+  const int ni = w * (ny + 2);
+  if (q < ni) {
+    j = q / w;
+    i = 3 + (q - j * w);
+  } else {
+    const int b = q - ni;
+    j = b / 6;
+    const int r = b - 6 * j;
+    i = r < 3 ? r : nx - 4 + r;
+  }
+}
+
+// Position of node (i, j) in that order.
+__host__ __device__ inline int plane_index(int i, int j, int nx, int ny) {
+  const int w = nx - 4;
+  if (i >= 3 && i <= nx - 2) return j * w + (i - 3);
+  return w * (ny + 2) + 6 * j + (i < 3 ? i : i - w);
+}
+
+// A tile is a run of consecutive positions q0 .. q0+threads-1 of the thread
+// order above in the xy node plane of one block, over planes z0 .. z0+cz-1.
 struct Tile {
   int block, q0, z0, pad;
 };
@@ -107,6 +133,8 @@ struct KArgs {
   const void* mat_sig;
   const double* face;
   const Source* src;
+  double* srcval;  // current density of each source at (n+1/2) dt of the step
+  int nsrc;        // sources over all blocks
   const Probe* prb;
   double* energy;
   int ecap;

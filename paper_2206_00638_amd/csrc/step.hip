@@ -113,27 +113,38 @@ __device__ void store_partial(double v, const KArgs& a) {
   }
 }
 
+__device__ __forceinline__ double waveform(const Source& s, double t) {
+  const double d = t - s.t0;
+  const double g = exp(-4.0 * M_PI * d * d / (s.tw * s.tw));
+  return s.wave == 1 ? sin(2.0 * M_PI * s.f0 * t) * g : g;
+}
+
 // Sums partials[0 .. nparts) (one workgroup, fixed order) into the energy
 // ring: slot (step + delta) = total, or += total when `mode` has FIN_ADD;
-// flags a non-finite energy; FIN_STEP advances the step index.
-__global__ __launch_bounds__(1024) void k_finish(double* partials, int nparts, double* energy, int ecap,
-                                                 StepState* st, int mode, int delta) {
+// flags a non-finite energy; FIN_STEP advances the step index.  The finish
+// between the H and the E pass (FIN_ADD) also evaluates the source
+// waveforms at (n+1/2) dt for the E pass.
+__global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts, int mode, int delta) {
   __shared__ double red[16];
   double s = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += partials[p];
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += a.partials[p];
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
+  const long long n = a.st->step;
+  if (mode & FIN_ADD) {
+    const double t = ((double)n + 0.5) * a.dt;
+    for (int p = threadIdx.x; p < a.nsrc; p += blockDim.x) a.srcval[p] = a.src[p].amp * waveform(a.src[p], t);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < nw; ++w) tot += red[w];
-    const long long n = st->step;
-    const int slot = (int)((n + delta) % ecap);
-    if (mode & FIN_ADD) tot += energy[slot];
-    energy[slot] = tot;
-    if (!isfinite(tot)) st->flags |= 1;
-    if (mode & FIN_STEP) st->step = n + 1;
+    const int slot = (int)((n + delta) % a.ecap);
+    if (mode & FIN_ADD) tot += a.energy[slot];
+    a.energy[slot] = tot;
+    if (!isfinite(tot)) a.st->flags |= 1;
+    if (mode & FIN_STEP) a.st->step = n + 1;
   }
 }
 
@@ -241,23 +252,18 @@ __device__ __forceinline__ void take_probes(const KArgs& a, const DevBlock& B, i
   }
 }
 
-__device__ __forceinline__ double waveform(const Source& s, double t) {
-  const double d = t - s.t0;
-  const double g = exp(-4.0 * M_PI * d * d / (s.tw * s.tw));
-  return s.wave == 1 ? sin(2.0 * M_PI * s.f0 * t) * g : g;
-}
-
-// Current density of the block's sources on node (i, j, k) (tiles flagged as holding a source).
+// Current density of the block's sources on node (i, j, k) (tiles flagged
+// as holding a source), from the values the finish kernel evaluated.
 template <typename T>
-__device__ __forceinline__ void source_terms(const KArgs& a, const DevBlock& B, int i, int j, int k, double t,
-                                             T& jx, T& jy, T& jz) {
+__device__ __forceinline__ void source_terms(const KArgs& a, const DevBlock& B, int i, int j, int k, T& jx, T& jy,
+                                             T& jz) {
   for (int p = 0; p < B.nsrc; ++p) {
     const Source& S = a.src[B.src0 + p];
     if (S.i == i && S.j == j && S.k == k) {
-      const T v = (T)(S.amp * waveform(S, t));
-      if (S.comp == EX) jx += v;
-      else if (S.comp == EY) jy += v;
-      else jz += v;
+      const T v = (T)a.srcval[B.src0 + p];
+      jx += S.comp == EX ? v : T(0);
+      jy += S.comp == EY ? v : T(0);
+      jz += S.comp == EZ ? v : T(0);
     }
   }
 }
@@ -304,29 +310,26 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
   const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
   const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
   const bool xin = i >= 3 && i <= nx - 2, yin = j >= 3 && j <= ny - 2, zin = k >= 3 && k <= nz - 2;
-  T dzEy, dzEx, dyEz, dyEx, dxEz, dxEy;
-  if (zin) {
-    dzEy = (ey - Ey[o - sxy]) * ihz;
-    dzEx = (ex - Ex[o - sxy]) * ihz;
-  } else {
+  // interior two-point differences for every node (neighbour offsets kept
+  // inside the component box), so that all loads issue together; closure
+  // rows then replace them on the boundary rows
+  const long long oz = k > 0 ? sxy : 0, oy = j > 0 ? sx : 0, ox = i > 0 ? 1 : 0;
+  T dzEy = (ey - Ey[o - oz]) * ihz, dzEx = (ex - Ex[o - oz]) * ihz;
+  T dyEz = (ez - Ez[o - oy]) * ihy, dyEx = (ex - Ex[o - oy]) * ihy;
+  T dxEz = (ez - Ez[o - ox]) * ihx, dxEy = (ey - Ey[o - ox]) * ihx;
+  if (!zin) {
     const TRow<T> rz = row_of<T>(B, 2, k, true);
     const int f = k < 3 ? 4 : 5;
     dzEy = drow<T, GEN>(a, B, Ey, o, sxy, rz, f, 0, 1, i, j, k);
     dzEx = drow<T, GEN>(a, B, Ex, o, sxy, rz, f, 0, 0, i, j, k);
   }
-  if (yin) {
-    dyEz = (ez - Ez[o - sx]) * ihy;
-    dyEx = (ex - Ex[o - sx]) * ihy;
-  } else {
+  if (!yin) {
     const TRow<T> ry = row_of<T>(B, 1, j, true);
     const int f = j < 3 ? 2 : 3;
     dyEz = drow<T, GEN>(a, B, Ez, o, sx, ry, f, 0, 1, i, j, k);
     dyEx = drow<T, GEN>(a, B, Ex, o, sx, ry, f, 0, 0, i, j, k);
   }
-  if (xin) {
-    dxEz = (ez - Ez[o - 1]) * ihx;
-    dxEy = (ey - Ey[o - 1]) * ihx;
-  } else {
+  if (!xin) {
     const TRow<T> rx = row_of<T>(B, 0, i, true);
     const int f = i < 3 ? 0 : 1;
     dxEz = drow<T, GEN>(a, B, Ez, o, 1, rx, f, 0, 1, i, j, k);
@@ -381,17 +384,17 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double kh = Bc.kh;
-    const int sx = (int)c.sx, sy = c.ny + 2;
     const int q = tq0 + (int)threadIdx.x;
-    const int j = q / sx, i = q - j * sx;
-    if (j >= sy) continue;
+    if (q >= (int)c.sx * (c.ny + 2)) continue;
+    int i, j;
+    plane_node(q, c.nx, c.ny, i, j);
     T* base = (T*)a.pool + Bc.foff;
     const long long csz = Bc.csz;
     const T* M = (GEN && (c.mat & MAT_MU)) ? (const T*)a.mat_mu : nullptr;
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     double es = 0.0;
     for (int k = k0; k < k1; ++k) {
-      const long long o = (long long)q + c.sxy * k;
+      const long long o = (long long)(i + (int)c.sx * j) + c.sxy * k;
       T v0, v1, v2;
       es += (double)h_node<T, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
                            base + 5 * csz, M, i, j, k, o, v0, v1, v2);
@@ -420,31 +423,29 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
   const bool xin = i >= 2 && i <= nx - 2, yin = j >= 2 && j <= ny - 2, zin = k >= 2 && k <= nz - 2;
   const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
   const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
-  T dzHy, dzHx, dyHz, dyHx, dxHz, dxHy;
-  if (zin) {
-    dzHy = (Hy[o + sxy] - hy) * ihz;
-    dzHx = (Hx[o + sxy] - hx) * ihz;
-  } else if (k <= nz) {
-    const TRow<T> rz = row_of<T>(B, 2, k, false);
-    const int f = k < 2 ? 4 : 5;
-    dzHy = drow<T, GEN>(a, B, Hy, o, sxy, rz, f, 1, 1, i, j, k);
-    dzHx = drow<T, GEN>(a, B, Hx, o, sxy, rz, f, 1, 0, i, j, k);
-  } else {
-    dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
+  // interior two-point differences for every node (neighbour offsets kept
+  // inside the component box), then the closure rows on the boundary rows
+  const long long pz = k <= nz ? sxy : 0, py = j <= ny ? sx : 0, px = i <= nx ? 1 : 0;
+  T dzHy = (Hy[o + pz] - hy) * ihz, dzHx = (Hx[o + pz] - hx) * ihz;
+  T dyHz = (Hz[o + py] - hz) * ihy, dyHx = (Hx[o + py] - hx) * ihy;
+  T dxHz = (Hz[o + px] - hz) * ihx, dxHy = (Hy[o + px] - hy) * ihx;
+  if (!zin) {
+    if (k <= nz) {
+      const TRow<T> rz = row_of<T>(B, 2, k, false);
+      const int f = k < 2 ? 4 : 5;
+      dzHy = drow<T, GEN>(a, B, Hy, o, sxy, rz, f, 1, 1, i, j, k);
+      dzHx = drow<T, GEN>(a, B, Hx, o, sxy, rz, f, 1, 0, i, j, k);
+    } else {
+      dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
+    }
   }
-  if (yin) {
-    dyHz = (Hz[o + sx] - hz) * ihy;
-    dyHx = (Hx[o + sx] - hx) * ihy;
-  } else {
+  if (!yin) {
     const TRow<T> ry = row_of<T>(B, 1, j, false);
     const int f = j < 2 ? 2 : 3;
     dyHz = drow<T, GEN>(a, B, Hz, o, sx, ry, f, 1, 1, i, j, k);
     dyHx = drow<T, GEN>(a, B, Hx, o, sx, ry, f, 1, 0, i, j, k);
   }
-  if (xin) {
-    dxHz = (Hz[o + 1] - hz) * ihx;
-    dxHy = (Hy[o + 1] - hy) * ihx;
-  } else {
+  if (!xin) {
     const TRow<T> rx = row_of<T>(B, 0, i, false);
     const int f = i < 2 ? 0 : 1;
     dxHz = drow<T, GEN>(a, B, Hz, o, 1, rx, f, 1, 1, i, j, k);
@@ -567,7 +568,6 @@ template <typename T, bool HAS_EPS, bool GEN>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
-  const double tsrc = ((double)nstep + 0.5) * a.dt;
   TileIter it(a.t1 - a.t0);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
@@ -577,10 +577,10 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double ke4 = 0.25 * Bc.ke;
-    const int sx = (int)c.sx, sy = c.ny + 2;
     const int q = tq0 + (int)threadIdx.x;
-    const int j = q / sx, i = q - j * sx;
-    if (j >= sy) continue;
+    if (q >= (int)c.sx * (c.ny + 2)) continue;
+    int i, j;
+    plane_node(q, c.nx, c.ny, i, j);
     T* base = (T*)a.pool + Bc.foff;
     const long long csz = Bc.csz;
     const T* ME = (const T*)a.mat_eps;
@@ -588,9 +588,9 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     double es = 0.0;
     for (int k = k0; k < k1; ++k) {
-      const long long o = (long long)q + c.sxy * k;
+      const long long o = (long long)(i + (int)c.sx * j) + c.sxy * k;
       T jx = T(0), jy = T(0), jz = T(0);
-      if (tflags & 1) source_terms<T>(a, B, i, j, k, tsrc, jx, jy, jz);
+      if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
       es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
                                     base + 5 * csz, ME, MS, i, j, k, o, jx, jy, jz, v0, v1, v2);
@@ -614,7 +614,8 @@ __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
     const int sx = (int)B.sx;
     const int q = tl.q0 + (int)threadIdx.x;
     if (q >= sx * (ny + 2)) continue;
-    const int j = q / sx, i = q - j * sx;
+    int i, j;
+    plane_node(q, nx, ny, i, j);
     const int k0 = tl.z0, k1 = min(tl.z0 + a.cz, nz + 2);
     const T* base = (const T*)a.pool + B.foff;
     const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
@@ -701,7 +702,7 @@ hipError_t launch_e_energy(const KArgs& a, int grid, int threads, hipStream_t s)
   return hipGetLastError();
 }
 hipError_t launch_finish(const KArgs& a, int nparts, int mode, int delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a.partials, nparts, a.energy, a.ecap, a.st, mode, delta);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, nparts, mode, delta);
   return hipGetLastError();
 }
 template <typename T>
