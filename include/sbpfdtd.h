@@ -67,7 +67,8 @@ sbp_status sbp_create(sbp_ctx **out, sbp_prec prec, void *hip_stream,
                       sbp_alloc_fn alloc, sbp_free_fn free_fn, void *user);
 
 /* Adds a block of nx*ny*nz cells (each >= 4: the boundary closures of the
- * Appendix need four cells) of size dx*dy*dz metres at origin (x0,y0,z0).
+ * Appendix need four cells; the node box (nx+2)(ny+2)(nz+2) must stay below
+ * 2^31 - 2^20 nodes) of size dx*dy*dz metres at origin (x0,y0,z0).
  * eps_r, mu_r, sigma (S/m): per-cell host arrays of nx*ny*nz doubles, i
  * fastest, or NULL for 1, 1, 0.  The node value is the mean over the cells
  * whose closed box contains the node.  All faces start as PEC. */
@@ -130,10 +131,11 @@ sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
 sbp_status sbp_save_state(sbp_ctx *ctx, void *dev_buf, size_t bytes);
 sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
 
-/* Launch shape of the step kernels: a tile is tx*ty consecutive nodes of a
- * block's xy node plane (i fastest) over cz planes, one node per thread and
- * plane; `workgroups` resident workgroups loop over the tile list (0 = one
- * workgroup per tile).  tx*ty must be 64, 128 or 256. */
+/* Launch shape of the step kernels: a tile is cz runs of tx*ty consecutive
+ * nodes of a block's node box in flat order (i fastest, then j, then k), one
+ * node per thread and run; `workgroups` resident workgroups loop over the
+ * tile list (0 = one workgroup per tile).  tx*ty must be 64, 128 or 256;
+ * 1 <= cz <= 1024. */
 sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
 sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
 

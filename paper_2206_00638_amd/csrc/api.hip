@@ -102,7 +102,7 @@ struct sbp_ctx {
   FaceJob* d_jobs_h = nullptr;
   int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
   Taps* d_taps = nullptr;
-  int tx = 256, ty = 1, cz = 1, wgs = 0;
+  int tx = 128, ty = 1, cz = 8, wgs = 0;  // launch shape (sbp_set_launch); fastest measured on 256^3 fp32
   bool e_energy_dirty = true;
   std::string err;
   int graph_steps = 0;
@@ -432,20 +432,20 @@ sbp_status build_tiles(sbp_ctx* c) {
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
       if (block_kind(b) != kind) continue;
-      const int sx = b.n[0] + 2, nplane = sx * (b.n[1] + 2);
+      const long long sx = b.n[0] + 2, sxy = sx * (b.n[1] + 2);
       for (int z0 = 0; z0 < b.n[2] + 2; z0 += c->cz)
-        for (int q0 = 0; q0 < nplane; q0 += threads) {
+        for (long long q0 = 0; q0 < sxy; q0 += threads) {
           // flags: bit 0 = a source, bit 1 = a probe lies in the tile
           int flags = 0;
           auto inside = [&](int i, int j, int k) {
-            const int q = plane_index(i, j, b.n[0], b.n[1]);
+            const long long q = i + sx * j;
             return q >= q0 && q < q0 + threads && k >= z0 && k < z0 + c->cz;
           };
           for (auto& sr : c->srcs)
             if (sr.block == (int)bi && inside(sr.s.i, sr.s.j, sr.s.k)) flags |= 1;
           for (auto& pr : c->prbs)
             if (pr.block == (int)bi && inside(pr.p.i, pr.p.j, pr.p.k)) flags |= 2;
-          tl.push_back(Tile{(int)bi, q0, z0, flags});
+          tl.push_back(Tile{(int)bi, (int)q0, z0, flags});
         }
     }
     c->kind_t1[kind] = (int)tl.size();
@@ -619,6 +619,8 @@ sbp_status sbp_add_block(sbp_ctx* c, int nx, int ny, int nz, double dx, double d
   if (nx < 4 || ny < 4 || nz < 4)
     return fail(c, SBP_EINVAL, "a block needs at least 4 cells per axis (Appendix closures)");
   if (!(dx > 0 && dy > 0 && dz > 0)) return fail(c, SBP_EINVAL, "cell sizes must be positive");
+  if ((long long)(nx + 2) * (ny + 2) * (nz + 2) > (1LL << 31) - (1LL << 20))
+    return fail(c, SBP_EINVAL, "a block's node box (nx+2)(ny+2)(nz+2) must stay below 2^31 nodes");
   HostBlock b;
   b.n[0] = nx; b.n[1] = ny; b.n[2] = nz;
   b.h[0] = dx; b.h[1] = dy; b.h[2] = dz;
@@ -748,7 +750,9 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
       d.ih[a] = 1.0 / b.h[a];
     }
     d.sx = b.n[0] + 2;
-    d.sxy = d.sx * (b.n[1] + 2);
+    // planes padded to 64 nodes: every wave's centre accesses start on a 256 B
+    // (fp32) boundary when the tiles start on 64-node boundaries
+    d.sxy = (d.sx * (b.n[1] + 2) + 63) / 64 * 64;
     d.csz = d.sxy * (b.n[2] + 2);
     d.foff = (long long)foff;
     foff += 6 * (size_t)d.csz;
@@ -935,7 +939,7 @@ sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
   if (!c) return SBP_EINVAL;
   const int t = tx * ty;
   if (tx < 1 || ty < 1 || (t != 64 && t != 128 && t != 256)) return fail(c, SBP_EINVAL, "tx*ty must be 64, 128 or 256");
-  if (cz < 1 || workgroups < 0) return fail(c, SBP_EINVAL, "bad cz or workgroups");
+  if (cz < 1 || cz > 1024 || workgroups < 0) return fail(c, SBP_EINVAL, "cz must be 1..1024, workgroups >= 0");
   c->tx = tx;
   c->ty = ty;
   c->cz = cz;

@@ -30,8 +30,8 @@ enum MatFlags { MAT_EPS = 1, MAT_MU = 2, MAT_SIG = 4 };
 struct DevBlock {
   int n[3];
   int mat;              // MatFlags: which per-cell arrays exist
-  long long sx, sxy;    // node-box strides: node (i,j,k) at i + sx*j + sxy*k
-  long long csz;        // nodes per component (node box (nx+2)(ny+2)(nz+2))
+  long long sx, sxy;    // node-box strides: node (i,j,k) at i + sx*j + sxy*k; sxy = sx(ny+2) rounded up to 64
+  long long csz;        // component stride sxy (nz+2)
   long long foff;       // pool offset of component 0; component c at foff + c*csz
   long long coff;       // offset of this block's cells in the material arrays
   double h[3], ih[3];
@@ -52,34 +52,10 @@ struct DevBlock {
   double ke, kh;  // 1/2 eps0 hx hy hz, 1/2 mu0 hx hy hz (energy of an interior node)
 };
 
-// Thread order of the nodes of an xy node plane ((nx+2) x (ny+2) nodes, i
-// fastest in memory): first the nodes with 3 <= i <= nx-2, row by row, then
-// the six columns i = 0, 1, 2, nx-1, nx, nx+1 of every row.  The waves of
-// the first part all take the two-point interior difference along x, so the
-// closure rows do not split them.
-__host__ __device__ inline void plane_node(int q, int nx, int ny, int& i, int& j) {
-  const int w = nx - 4;  // interior x nodes per row
-  const int ni = w * (ny + 2);
-  if (q < ni) {
-    j = q / w;
-    i = 3 + (q - j * w);
-  } else {
-    const int b = q - ni;
-    j = b / 6;
-    const int r = b - 6 * j;
-    i = r < 3 ? r : nx - 4 + r;
-  }
-}
-
-// Position of node (i, j) in that order.
-__host__ __device__ inline int plane_index(int i, int j, int nx, int ny) {
-  const int w = nx - 4;
-  if (i >= 3 && i <= nx - 2) return j * w + (i - 3);
-  return w * (ny + 2) + 6 * j + (i < 3 ? i : i - w);
-}
-
-// A tile is a run of consecutive positions q0 .. q0+threads-1 of the thread
-// order above in the xy node plane of one block, over planes z0 .. z0+cz-1.
+// A tile is `threads` consecutive nodes q0 .. q0+threads-1 of the flattened
+// (i fastest) xy node plane of one block, over the planes z0 .. z0+cz-1: each
+// thread walks one node column through the cz planes.  pad holds flags:
+// bit 0 = a source, bit 1 = a probe lies in the tile.
 struct Tile {
   int block, q0, z0, pad;
 };

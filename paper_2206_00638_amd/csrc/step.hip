@@ -296,27 +296,54 @@ struct BC {
 };
 
 // ------------------------------------------------------------- H update
+// Field values one H node update reads at interior rows: E and H at the
+// node, E one node back along y and x (offsets kept inside the component
+// box on the first row / column) and Ex, Ey one plane back.  A thread walks
+// a column of planes: the plane-back values are the previous plane's centre
+// values, carried in registers, and the next plane is loaded before the
+// current one is computed.
+template <typename T>
+struct HIn {
+  T ex, ey, ez, hx, hy, hz;
+  T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
+};
+
+template <typename T>
+__device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __restrict__ Ex,
+                                       const T* __restrict__ Ey, const T* __restrict__ Ez,
+                                       const T* __restrict__ Hx, const T* __restrict__ Hy,
+                                       const T* __restrict__ Hz, int i, int j, long long o) {
+  const long long oy = j > 0 ? c.sx : 0, ox = i > 0 ? 1 : 0;
+  v.ex = Ex[o];
+  v.ey = Ey[o];
+  v.ez = Ez[o];
+  v.hx = Hx[o];
+  v.hy = Hy[o];
+  v.hz = Hz[o];
+  v.ez_y = Ez[o - oy];
+  v.ex_y = Ex[o - oy];
+  v.ez_x = Ez[o - ox];
+  v.ey_x = Ey[o - ox];
+}
+
 // H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
-// components, with the closure / PEC / interface rows.  Returns the node's
+// components, with the closure / PEC / interface rows replacing the interior
+// differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
 template <typename T, bool GEN>
-__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const T* __restrict__ Ex,
-                                    const T* __restrict__ Ey, const T* __restrict__ Ez, T* __restrict__ Hx,
-                                    T* __restrict__ Hy, T* __restrict__ Hz, const T* __restrict__ M, int i,
-                                    int j, int k, long long o, T& onx, T& ony, T& onz) {
+__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const HIn<T>& v,
+                                    const T* __restrict__ Ex, const T* __restrict__ Ey,
+                                    const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
+                                    T* __restrict__ Hz, const T* __restrict__ M, int i, int j, int k,
+                                    long long o, T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
-  const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
-  const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
+  const T hx = v.hx, hy = v.hy, hz = v.hz;
   const bool xin = i >= 3 && i <= nx - 2, yin = j >= 3 && j <= ny - 2, zin = k >= 3 && k <= nz - 2;
-  // interior two-point differences for every node (neighbour offsets kept
-  // inside the component box), so that all loads issue together; closure
-  // rows then replace them on the boundary rows
-  const long long oz = k > 0 ? sxy : 0, oy = j > 0 ? sx : 0, ox = i > 0 ? 1 : 0;
-  T dzEy = (ey - Ey[o - oz]) * ihz, dzEx = (ex - Ex[o - oz]) * ihz;
-  T dyEz = (ez - Ez[o - oy]) * ihy, dyEx = (ex - Ex[o - oy]) * ihy;
-  T dxEz = (ez - Ez[o - ox]) * ihx, dxEy = (ey - Ey[o - ox]) * ihx;
+  T dzEy = (v.ey - v.ey_z) * ihz, dzEx = (v.ex - v.ex_z) * ihz;
+  T dyEz = (v.ez - v.ez_y) * ihy, dyEx = (v.ex - v.ex_y) * ihy;
+  T dxEz = (v.ez - v.ez_x) * ihx, dxEy = (v.ey - v.ey_x) * ihx;
   if (!zin) {
     const TRow<T> rz = row_of<T>(B, 2, k, true);
     const int f = k < 3 ? 4 : 5;
@@ -369,7 +396,7 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
 }
 
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
-// one node per thread in linear (i, j, k) order, plus the H part of W^n:
+// one node per thread in flat (i, j, k) order, plus the H part of W^n:
 // 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
 template <typename T, bool GEN>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
@@ -384,21 +411,39 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double kh = Bc.kh;
-    const int q = tq0 + (int)threadIdx.x;
-    if (q >= (int)c.sx * (c.ny + 2)) continue;
-    int i, j;
-    plane_node(q, c.nx, c.ny, i, j);
     T* base = (T*)a.pool + Bc.foff;
     const long long csz = Bc.csz;
     const T* M = (GEN && (c.mat & MAT_MU)) ? (const T*)a.mat_mu : nullptr;
+    const int q = tq0 + (int)threadIdx.x;
+    if (q >= (int)c.sx * (c.ny + 2)) continue;
+    const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
+    T* Ex = base;
+    T* Ey = base + csz;
+    T* Ez = base + 2 * csz;
+    T* Hx = base + 3 * csz;
+    T* Hy = base + 4 * csz;
+    T* Hz = base + 5 * csz;
     double es = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      const long long o = (long long)(i + (int)c.sx * j) + c.sxy * k;
+    long long o = (long long)q + c.sxy * k0;
+    HIn<T> cur;
+    {
+      const long long ob = k0 > 0 ? o - c.sxy : o;
+      cur.ex_z = Ex[ob];
+      cur.ey_z = Ey[ob];
+      h_load<T>(cur, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
+    }
+    for (int k = k0; k < k1; ++k, o += c.sxy) {
+      HIn<T> nxt;
+      if (k + 1 < k1) {  // next plane first: its loads overlap this plane's arithmetic
+        nxt.ex_z = cur.ex;
+        nxt.ey_z = cur.ey;
+        h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
+      }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
-                           base + 5 * csz, M, i, j, k, o, v0, v1, v2);
+      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, Hx, Hy, Hz, M, i, j, k, o, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
+      cur = nxt;
     }
     eacc += kh * es;
   }
@@ -406,29 +451,125 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
 }
 
 // ------------------------------------------------------------- E update
+// The four cells around an E node column at planes k-1 (P0) and k (P1):
+// A (i-1, j-1), B (i, j-1), C (i-1, j), D (i, j), clamped to the block; cell
+// X of plane P is at index A + P + (offset of X from A).
+struct Cells {
+  long long A, P0, P1;
+  int dx, dy;
+};
+
+template <typename T>
+__device__ __forceinline__ Cells cells_of(const BC<T>& c, int i, int j, int k) {
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const long long cp = (long long)nx * ny;
+  Cells r;
+  if (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1 && k >= 1 && k <= nz - 1) {
+    r.A = c.coff + (i - 1) + (long long)nx * (j - 1);
+    r.dx = 1;
+    r.dy = nx;
+    r.P0 = cp * (k - 1);
+    r.P1 = r.P0 + cp;
+  } else {
+    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
+    r.A = c.coff + ci0 + (long long)nx * cj0;
+    r.dx = ci1 - ci0;
+    r.dy = (cj1 - cj0) * nx;
+    r.P0 = cp * clampi(k - 1, 0, nz - 1);
+    r.P1 = cp * clampi(k, 0, nz - 1);
+  }
+  return r;
+}
+
+// Sums of a per-cell quantity over the cells containing an Ex, Ey, Ez node
+// (four each; the node value is a quarter of the sum).
+template <typename T>
+struct Sum4 {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ Sum4<T> cell_sums(const T* __restrict__ M, const Cells& q) {
+  const T* p0 = M + q.A + q.P0;
+  const T* p1 = M + q.A + q.P1;
+  const T a0 = p0[0], b0 = p0[q.dx], c0 = p0[q.dy], d0 = p0[q.dx + q.dy];
+  const T a1 = p1[0], b1 = p1[q.dx], c1 = p1[q.dy];
+  return Sum4<T>{(a0 + c0) + (a1 + c1), (a0 + b0) + (a1 + b1), (a0 + b0) + (c0 + d0)};
+}
+
+// Values one E node update reads at interior rows: E and H at the node, H
+// one node ahead along y and x (offsets kept inside the component box on the
+// last row / column), Hx, Hy one plane ahead and the permittivity cells of
+// planes k-1 (e0*) and k (e1*).  Walking a column of planes, the centre Hx,
+// Hy and the plane k-1 cells are the previous plane's values, carried in
+// registers; e1d is loaded for the next plane's e0d.
+template <typename T>
+struct EIn {
+  T ex, ey, ez, hx, hy, hz;
+  T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
+  T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
+};
+
+// Cell offsets of a node column (i, j): cell A (i-1, j-1) clamped, and the
+// offsets of B (+x) and C (+y); plane P of cells starts at P * nx * ny.
+struct ColCells {
+  long long A, cp;
+  int dx, dy;
+};
+template <typename T>
+__device__ __forceinline__ ColCells col_cells(const BC<T>& c, int i, int j) {
+  const int nx = c.nx, ny = c.ny;
+  const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+  const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
+  return ColCells{c.coff + ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
+}
+
+template <typename T, bool HAS_EPS>
+__device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __restrict__ Ex,
+                                       const T* __restrict__ Ey, const T* __restrict__ Ez,
+                                       const T* __restrict__ Hz, const T* __restrict__ Hx,
+                                       const T* __restrict__ Hy, const T* __restrict__ ME, const ColCells& q,
+                                       int i, int j, int k, long long o) {
+  const long long pz = k <= c.nz ? c.sxy : 0, py = j <= c.ny ? c.sx : 0, px = i <= c.nx ? 1 : 0;
+  v.ex = Ex[o];
+  v.ey = Ey[o];
+  v.ez = Ez[o];
+  v.hz = Hz[o];
+  v.hy_z = Hy[o + pz];
+  v.hx_z = Hx[o + pz];
+  v.hz_y = Hz[o + py];
+  v.hx_y = Hx[o + py];
+  v.hz_x = Hz[o + px];
+  v.hy_x = Hy[o + px];
+  if (HAS_EPS) {
+    const T* p1 = ME + q.A + q.cp * clampi(k, 0, c.nz - 1);
+    v.e1a = p1[0];
+    v.e1b = p1[q.dx];
+    v.e1c = p1[q.dy];
+    v.e1d = p1[q.dx + q.dy];
+  }
+}
+
 // E^{n+1} = Ca E^n + Cb (E7-E9 + J) at node (i, j, k), all valid E
-// components, with the closure / PMC / absorbing / interface rows; the
-// absorbing damping 2/(eta h) on tangential face nodes joins the
-// semi-implicit loss.  Returns the node's 4 eps_r (w/h^3) (E^{n+1})^2.
+// components, with the closure / PMC / absorbing / interface rows replacing
+// the interior differences on the boundary rows; the absorbing damping
+// 2/(eta h) on tangential face nodes joins the semi-implicit loss.  Returns
+// the node's 4 eps_r (w/h^3) (E^{n+1})^2.
 template <typename T, bool HAS_EPS, bool GEN>
-__device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<T>& c, T* __restrict__ Ex,
-                                    T* __restrict__ Ey,
-                                    T* __restrict__ Ez, const T* __restrict__ Hx, const T* __restrict__ Hy,
-                                    const T* __restrict__ Hz, const T* __restrict__ ME,
-                                    const T* __restrict__ MS, int i, int j, int k, long long o, T jx, T jy,
-                                    T jz, T& onx, T& ony, T& onz) {
+__device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const EIn<T>& v,
+                                    T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
+                                    const T* __restrict__ Hx, const T* __restrict__ Hy,
+                                    const T* __restrict__ Hz, const T* __restrict__ MS, int i, int j, int k,
+                                    long long o, T jx, T jy, T jz, T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
   const bool xin = i >= 2 && i <= nx - 2, yin = j >= 2 && j <= ny - 2, zin = k >= 2 && k <= nz - 2;
-  const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
-  const T hx = Hx[o], hy = Hy[o], hz = Hz[o];
-  // interior two-point differences for every node (neighbour offsets kept
-  // inside the component box), then the closure rows on the boundary rows
-  const long long pz = k <= nz ? sxy : 0, py = j <= ny ? sx : 0, px = i <= nx ? 1 : 0;
-  T dzHy = (Hy[o + pz] - hy) * ihz, dzHx = (Hx[o + pz] - hx) * ihz;
-  T dyHz = (Hz[o + py] - hz) * ihy, dyHx = (Hx[o + py] - hx) * ihy;
-  T dxHz = (Hz[o + px] - hz) * ihx, dxHy = (Hy[o + px] - hy) * ihx;
+  const T ex = v.ex, ey = v.ey, ez = v.ez;
+  const T hx = v.hx, hy = v.hy, hz = v.hz;
+  T dzHy = (v.hy_z - hy) * ihz, dzHx = (v.hx_z - hx) * ihz;
+  T dyHz = (v.hz_y - hz) * ihy, dyHx = (v.hx_y - hx) * ihy;
+  T dxHz = (v.hz_x - hz) * ihx, dxHy = (v.hy_x - hy) * ihx;
   if (!zin) {
     if (k <= nz) {
       const TRow<T> rz = row_of<T>(B, 2, k, false);
@@ -452,37 +593,12 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
     dxHy = drow<T, GEN>(a, B, Hy, o, 1, rx, f, 1, 0, i, j, k);
   }
   const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
-  // the four cells around the node column at planes k-1 (0) and k (1):
-  // A (i-1, j-1), B (i, j-1), C (i-1, j), D (i, j), clamped to the block
-  const bool inner = i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1 && k >= 1 && k <= nz - 1;
-  const long long cnx = nx, cp = (long long)nx * ny;
-  long long cA, cP0, cP1;
-  int dxc, dyc;
-  if (inner) {
-    cA = c.coff + (i - 1) + cnx * (j - 1);
-    dxc = 1;
-    dyc = nx;
-    cP0 = cp * (k - 1);
-    cP1 = cP0 + cp;
-  } else {
-    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
-    cA = c.coff + ci0 + cnx * cj0;
-    dxc = ci1 - ci0;
-    dyc = (cj1 - cj0) * nx;
-    cP0 = cp * clampi(k - 1, 0, nz - 1);
-    cP1 = cp * clampi(k, 0, nz - 1);
-  }
   const T eps_r0 = c.eps_r0;
   T mx = T(4) * eps_r0, my = mx, mz = mx;  // node permittivity x4: sums of the four containing cells
   if (HAS_EPS) {
-    const T* p0 = ME + cA + cP0;
-    const T* p1 = ME + cA + cP1;
-    const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
-    const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
-    mx = (a0 + c0) + (a1 + c1);
-    my = (a0 + b0) + (a1 + b1);
-    mz = (a0 + b0) + (c0 + d0);
+    mx = (v.e0a + v.e0c) + (v.e1a + v.e1c);
+    my = (v.e0a + v.e0b) + (v.e1a + v.e1b);
+    mz = (v.e0a + v.e0b) + (v.e0c + v.e0d);
   }
   T cax = T(1), cay = T(1), caz = T(1), cbx, cby, cbz;
   if (HAS_EPS) {
@@ -506,25 +622,18 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
       const T sig0 = c.sig0;
       T sx4 = T(4) * sig0, sy4 = sx4, sz4 = sx4;
       if (MS) {
-        const T* p0 = MS + cA + cP0;
-        const T* p1 = MS + cA + cP1;
-        const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
-        const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
-        sx4 = (a0 + c0) + (a1 + c1);
-        sy4 = (a0 + b0) + (a1 + b1);
-        sz4 = (a0 + b0) + (c0 + d0);
+        const Sum4<T> q = cell_sums(MS, cells_of(c, i, j, k));
+        sx4 = q.x;
+        sy4 = q.y;
+        sz4 = q.z;
       }
       if (gEx != T(0) || gEy != T(0) || gEz != T(0)) {
         T mux = T(4) * (T)B.mu_r0, muy = mux, muz = mux;  // node mu_r x4
         if (c.mat & MAT_MU) {
-          const T* MM = (const T*)a.mat_mu;
-          const T* p0 = MM + cA + cP0;
-          const T* p1 = MM + cA + cP1;
-          const T a0 = p0[0], b0 = p0[dxc], c0 = p0[dyc], d0 = p0[dxc + dyc];
-          const T a1 = p1[0], b1 = p1[dxc], c1 = p1[dyc];
-          mux = (a0 + c0) + (a1 + c1);
-          muy = (a0 + b0) + (a1 + b1);
-          muz = (a0 + b0) + (c0 + d0);
+          const Sum4<T> q = cell_sums((const T*)a.mat_mu, cells_of(c, i, j, k));
+          mux = q.x;
+          muy = q.y;
+          muz = q.z;
         }
         const T me0 = (T)(a.mu0 / a.eps0);
         if (gEx != T(0)) sx4 += T(8) * gEx / sqrt(me0 * mux / mx);
@@ -561,7 +670,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
 }
 
 // E step over the tiles [t0, t1) of the tile list (one kind of block), one
-// node per thread in linear (i, j, k) order, plus the E part of W^{n+1}:
+// node per thread in flat (i, j, k) order, plus the E part of W^{n+1}:
 // 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
 template <typename T, bool HAS_EPS, bool GEN>
@@ -577,24 +686,52 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double ke4 = 0.25 * Bc.ke;
-    const int q = tq0 + (int)threadIdx.x;
-    if (q >= (int)c.sx * (c.ny + 2)) continue;
-    int i, j;
-    plane_node(q, c.nx, c.ny, i, j);
     T* base = (T*)a.pool + Bc.foff;
     const long long csz = Bc.csz;
     const T* ME = (const T*)a.mat_eps;
     const T* MS = (GEN && (c.mat & MAT_SIG)) ? (const T*)a.mat_sig : nullptr;
+    const int q = tq0 + (int)threadIdx.x;
+    if (q >= (int)c.sx * (c.ny + 2)) continue;
+    const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
+    T* Ex = base;
+    T* Ey = base + csz;
+    T* Ez = base + 2 * csz;
+    T* Hx = base + 3 * csz;
+    T* Hy = base + 4 * csz;
+    T* Hz = base + 5 * csz;
+    const ColCells cc = col_cells(c, i, j);
     double es = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      const long long o = (long long)(i + (int)c.sx * j) + c.sxy * k;
+    long long o = (long long)q + c.sxy * k0;
+    EIn<T> cur;
+    cur.hx = Hx[o];
+    cur.hy = Hy[o];
+    if (HAS_EPS) {
+      const T* p0 = ME + cc.A + cc.cp * clampi(k0 - 1, 0, c.nz - 1);
+      cur.e0a = p0[0];
+      cur.e0b = p0[cc.dx];
+      cur.e0c = p0[cc.dy];
+      cur.e0d = p0[cc.dx + cc.dy];
+    }
+    e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    for (int k = k0; k < k1; ++k, o += c.sxy) {
+      EIn<T> nxt;
+      if (k + 1 < k1) {  // next plane first: its loads overlap this plane's arithmetic
+        nxt.hx = cur.hx_z;
+        nxt.hy = cur.hy_z;
+        nxt.e0a = cur.e1a;
+        nxt.e0b = cur.e1b;
+        nxt.e0c = cur.e1c;
+        nxt.e0d = cur.e1d;
+        e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+      }
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, base, base + csz, base + 2 * csz, base + 3 * csz, base + 4 * csz,
-                                    base + 5 * csz, ME, MS, i, j, k, o, jx, jy, jz, v0, v1, v2);
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, cur, Ex, Ey, Ez, Hx, Hy, Hz, MS, i, j, k, o, jx, jy, jz, v0,
+                                            v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
+      cur = nxt;
     }
     eacc += ke4 * es;
   }
@@ -611,18 +748,15 @@ __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
     const Tile tl = a.tiles[t];
     const DevBlock& B = a.blocks[tl.block];
     const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    const int sx = (int)B.sx;
-    const int q = tl.q0 + (int)threadIdx.x;
-    if (q >= sx * (ny + 2)) continue;
-    int i, j;
-    plane_node(q, nx, ny, i, j);
-    const int k0 = tl.z0, k1 = min(tl.z0 + a.cz, nz + 2);
     const T* base = (const T*)a.pool + B.foff;
-    const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-    const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
     const bool has_eps = B.mat & MAT_EPS;
-    for (int k = k0; k < k1; ++k) {
-      const long long o = i + B.sx * j + B.sxy * k;
+    const int q = tl.q0 + (int)threadIdx.x;
+    if (q >= (int)B.sx * (ny + 2)) continue;
+    const int j = q / (int)B.sx, i = q - j * (int)B.sx;
+    for (int k = tl.z0; k < min(tl.z0 + a.cz, nz + 2); ++k) {
+      const long long o = q + B.sxy * k;
+      const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+      const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
       const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
       auto ev = [&](int ci, int cj, int ck) { return has_eps ? cellv<T>(a.mat_eps, B, ci, cj, ck) : B.eps_r0; };
       const double epx = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci0, cj1, ck0)) + (ev(ci0, cj0, ck1) + ev(ci0, cj1, ck1))));
