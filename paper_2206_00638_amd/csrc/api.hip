@@ -1197,12 +1197,14 @@ sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
   struct Cand { int tx, ty, cz, wg; };
   std::vector<Cand> cand;
+  // threads per tile x planes per tile, one workgroup per tile; then the
+  // kept shape with resident workgroups looping over the tile list
   const int ths[3] = {64, 128, 256};
-  const int czs[3] = {1, 2, 4};
+  const int czs[4] = {2, 4, 8, 16};
   for (int t : ths)
     for (int cz : czs) cand.push_back({t, 1, cz, 0});
-  cand.push_back({keep[0], keep[1], keep[2], dev_cus * 4});
   cand.push_back({keep[0], keep[1], keep[2], dev_cus * 8});
+  cand.push_back({keep[0], keep[1], keep[2], dev_cus * 16});
   double best = 1e300;
   Cand win{keep[0], keep[1], keep[2], keep[3]};
   for (const Cand& k : cand) {

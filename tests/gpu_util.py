@@ -69,6 +69,23 @@ def per_field_errors(gpu, ref):
 
 FLOOR = {"f64": 1e-6, "f32": 1e-1}
 
+EPS0 = 1.0 / (4e-7 * math.pi * 299792458.0 ** 2)
+MU0 = 4e-7 * math.pi
+
+
+def energy_norm_error(gpu, ref):
+    """Relative error of (E, H) together in the vacuum energy norm,
+    sqrt(sum eps0 dE^2 + mu0 dH^2) / sqrt(sum eps0 E^2 + mu0 H^2): the scale
+    the method itself conserves.  Unlike the per-field errors it stays
+    meaningful when one field decays, e.g. H after a Gaussian (non-zero mean)
+    current pulse has ended and left a static E field."""
+    num = den = 0.0
+    for k in ref:
+        w = EPS0 if (k[-1][0] if isinstance(k, tuple) else k[0]) == "E" else MU0
+        num += w * float(np.sum((gpu[k] - ref[k]) ** 2))
+        den += w * float(np.sum(ref[k] ** 2))
+    return math.sqrt(num / den) if den > 0 else math.sqrt(num)
+
 
 def block(n, h=(1e-3, 1e-3, 1e-3), faces=("pec",) * 6, **kw):
     d = {"n": tuple(n), "h": tuple(h), "origin": (0.0, 0.0, 0.0), "eps_r": None, "mu_r": None,

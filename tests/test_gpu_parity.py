@@ -9,8 +9,8 @@ import math
 import numpy as np
 import pytest
 
-from gpu_util import (COMPS, FLOOR, block, field_errors, gpu_fields, per_field_errors, random_fields, rel_l2,
-                      write_fields)
+from gpu_util import (COMPS, FLOOR, block, energy_norm_error, field_errors, gpu_fields, per_field_errors,
+                      random_fields, rel_l2, write_fields)
 
 pytestmark = pytest.mark.gpu
 
@@ -280,6 +280,105 @@ def test_graph_replay_bitwise(sbp):
             assert np.array_equal(ref[k], got[k]), (prec, k)
         assert np.array_equal(p_ref, p_got)
         assert np.allclose(e_got, e_ref, rtol=1e-13, atol=0)
+
+
+# ----------------------------------------------------------- config 4
+def _single(problem, b):
+    """Block b of a batched problem as a problem of its own."""
+    return {"blocks": [problem["blocks"][b]], "interfaces": [], "cfl": problem["cfl"],
+            "sources": [dict(s, block=0) for s in problem["sources"] if s["block"] == b],
+            "probes": [dict(q, block=0) for q in problem["probes"] if q["block"] == b]}
+
+
+def test_config4_batched_matches_single_and_oracle(sbp):
+    """64 uneven cavities in one tile list: every cavity's fields and probes
+    equal those of the cavity stepped alone (bitwise; the nodes of different
+    blocks never interact), the total energy is the sum of the cavities'
+    energies, and sampled cavities match the fp64 loop oracle."""
+    from oracle import loops
+    from sbp_inputs import make_config
+    prob = make_config(4, scale=4)
+    steps = 40
+    batched = sbp.build_problem(prob, prec="f32")
+    batched.step(steps)
+    nb = len(prob["blocks"])
+    fields = {b: {c: batched.read_field(b, c) for c in COMPS} for b in range(nb)}
+    probes = np.array([batched.read_probe(p, 0, steps) for p in range(len(prob["probes"]))])
+    energy = batched.read_energy(0, steps)
+    dt = batched.dt
+    batched.close()
+    e_sum = np.zeros(steps)
+    for b in range(nb):
+        one = _single(prob, b)
+        ctx = sbp.build_problem(one, prec="f32")
+        assert ctx.dt == dt  # all cavities share the mesh size, so the global dt is theirs
+        ctx.step(steps)
+        for c in COMPS:
+            assert np.array_equal(ctx.read_field(0, c), fields[b][c]), (b, c)
+        assert np.array_equal(ctx.read_probe(0, 0, steps), probes[b])
+        e_sum += ctx.read_energy(0, steps)
+        ctx.close()
+    assert np.allclose(energy, e_sum, rtol=1e-12, atol=0)
+    for b in (0, 17, 63):
+        ref = loops.run_block(_single(prob, b), steps=steps, dt=dt)
+        got = {c: fields[b][c] for c in COMPS}
+        err = per_field_errors(got, ref["fields"])
+        assert max(err.values()) <= TOL["f32"], (b, err)
+        assert rel_l2(probes[b], ref["probes"][0]) <= TOL["f32"]
+
+
+def test_config4_full_graph_autotune(sbp):
+    """Config 4 at full size (64 cavities, 32.8 M cells): autotuned launch and
+    100-step graph replays, each replay checked against eager steps of the
+    default launch (fields of sampled cavities bitwise, energies to the fp64
+    reassociation bound), with reads (host synchronisation) between replays;
+    the three smallest cavities against the fp64 loop oracle over 100 steps."""
+    import torch
+    from oracle import loops
+    from sbp_inputs import make_config
+    prob = make_config(4)
+    nb = len(prob["blocks"])
+    sizes = [int(np.prod(b["n"])) for b in prob["blocks"]]
+    sample = sorted(range(nb), key=lambda b: sizes[b])[:3] + [int(np.argmax(sizes))]
+    stream = torch.cuda.Stream()
+    ctx = sbp.build_problem(prob, prec="f32", stream=stream, history=1024)
+    nbytes = ctx.state_bytes()
+    snap = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ctx.save_state(snap.data_ptr(), nbytes)
+    eager = []
+    for r in range(3):
+        ctx.step(100)
+        eager.append(({b: {c: ctx.read_field(b, c) for c in COMPS} for b in sample},
+                      ctx.read_energy(100 * r, 100)))
+    probes_eager = np.array([ctx.read_probe(p, 0, 300) for p in range(nb)])
+    ctx.load_state(snap.data_ptr(), nbytes)
+    ms = ctx.autotune(3)
+    assert ms > 0
+    launch = ctx.get_launch()
+    ctx.use_graph(100)
+    for r in range(3):
+        ctx.step(100)
+        torch.cuda.synchronize()
+        f_eager, e_eager = eager[r]
+        for b in sample:
+            for c in COMPS:
+                assert np.array_equal(ctx.read_field(b, c), f_eager[b][c]), (r, b, c, launch)
+        assert np.allclose(ctx.read_energy(100 * r, 100), e_eager, rtol=1e-12, atol=0), (r, launch)
+    assert np.array_equal(np.array([ctx.read_probe(p, 0, 300) for p in range(nb)]), probes_eager)
+    dt = ctx.dt
+    ctx.close()
+    for b in sample[:3]:
+        ref = loops.run_block(_single(prob, b), steps=100, dt=dt)
+        got = eager[0][0][b]
+        # a Gaussian (non-zero mean) current pulse mostly charges up a static E
+        # field: at step 100 eta0 |H| is about 2 % of |E| in these cavities, so
+        # H's own relative error measures the fp32 rounding of terms of the
+        # size of E; the energy-norm error bounds both fields on the method's
+        # own scale
+        err = per_field_errors(got, ref["fields"])
+        assert err["E"] <= TOL["f32"], (b, err)
+        assert energy_norm_error(got, ref["fields"]) <= TOL["f32"], (b, err)
+        assert err["H"] <= 10 * TOL["f32"], (b, err)
 
 
 # ---------------------------------------------------------------- errors
