@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
 its Python binding) may import, call, link or execute anything in this
 package; only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
-leg of ``bench.py`` use it.  It shares no code, headers, tables or constant
+and ``accuracy`` legs of ``bench.py`` use it.  It shares no code, headers, tables or constant
 generators with the HIP path.
 
 Two independent forms of the same method:
@@ -18,6 +18,11 @@ Two independent forms of the same method:
   host and to run the large single-block workloads.
 
 ``yee`` is a plain Yee FDTD reference, used only to pin the interior.
+
+``adjoint``: the discrete adjoint of the leapfrog step in the matrix form
+(explicit transposes), giving the gradient of a region objective with
+respect to the per-cell permittivity; pinned by central finite differences
+of the forward objective.
 
 Parity pins live in ``tests/test_oracle_*.py``.  Functions whose results no
 pin covers say "parity unpinned" in their docstring.
