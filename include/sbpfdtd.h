@@ -131,6 +131,26 @@ sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
 sbp_status sbp_save_state(sbp_ctx *ctx, void *dev_buf, size_t bytes);
 sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
 
+/* Gradient of a region objective with respect to the per-cell relative
+ * permittivity, by the discrete adjoint of the leapfrog step (Section V):
+ *   J = dt * sum_{n=1..N} sum_{cells c in region} |Ebar_c^n|^2,
+ * with E^n the fields n steps after the current state and Ebar_c, per
+ * component, the mean of the four edges of cell c that carry it.  The
+ * forward run (N = nsteps steps) stores its state every ckpt_every steps
+ * (0 = ceil(sqrt(N))); the reverse sweep recomputes each segment from its
+ * checkpoint and runs the adjoint backwards through it.  region = {i0, i1,
+ * j0, j1, k0, k1}: half-open cell box of `block`.  Writes J to *J_out (host)
+ * and dJ/d eps_r of every cell of `block` to grad_eps_dev (device doubles,
+ * nx*ny*nz, i fastest; the caller owns it).  Blocks must be lossless (no
+ * conductivity, no absorbing faces): SBP_EINVAL otherwise.  Afterwards the
+ * context is at the state after the N forward steps, with their energy and
+ * probe samples, as after sbp_step(ctx, N).  Device memory for
+ * ceil(N/ckpt_every) states plus ckpt_every+1 field pools is taken from the
+ * allocator and returned before the call ends; SBP_ENOMEM if it is not
+ * available. */
+sbp_status sbp_adjoint(sbp_ctx *ctx, int block, long nsteps, const int region[6], long ckpt_every,
+                       double *J_out, double *grad_eps_dev);
+
 /* Launch shape of the step kernels: a tile is cz runs of tx*ty consecutive
  * nodes of a block's node box in flat order (i fastest, then j, then k), one
  * node per thread and run; `workgroups` resident workgroups loop over the

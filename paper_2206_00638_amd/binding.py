@@ -52,6 +52,7 @@ SIGNATURES = {
     "sbp_state_bytes": [_P, ctypes.POINTER(_S)],
     "sbp_save_state": [_P, _P, _S],
     "sbp_load_state": [_P, _P, _S],
+    "sbp_adjoint": [_P, _I, _L, _IP, _L, _DP, _P],
     "sbp_set_launch": [_P, _I, _I, _I, _I],
     "sbp_get_launch": [_P, _IP],
     "sbp_autotune": [_P, _I, _DP],
@@ -229,6 +230,15 @@ class Context:
 
     def load_state(self, dev_ptr, nbytes):
         self._chk(self._lib.sbp_load_state(self.h, ctypes.c_void_p(dev_ptr), nbytes))
+
+    def adjoint(self, block, nsteps, region, grad_ptr, ckpt_every=0):
+        """J and dJ/d eps_r of ``block`` (written to the device doubles at
+        ``grad_ptr``); see sbp_adjoint."""
+        r = (ctypes.c_int * 6)(*[int(v) for v in region])
+        J = ctypes.c_double()
+        self._chk(self._lib.sbp_adjoint(self.h, int(block), int(nsteps), r, int(ckpt_every), ctypes.byref(J),
+                                        ctypes.c_void_p(grad_ptr)))
+        return J.value
 
     def set_launch(self, tx, ty, cz, workgroups=0):
         self._chk(self._lib.sbp_set_launch(self.h, tx, ty, cz, workgroups))

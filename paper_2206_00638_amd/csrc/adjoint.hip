@@ -1,0 +1,285 @@
+// Kernels of the discrete adjoint of the leapfrog step (gradient of a region
+// objective with respect to the per-cell relative permittivity).
+//
+// Objective: J = dt sum_{n=1..N} sum_{cells c in region} |Ebar_c^n|^2, with
+// Ebar_c per component the mean of the four edges of cell c carrying it.
+//
+// For PEC/PMC faces and interfaces the SAT-modified difference operators are
+// skew-adjoint in the norms of Section II (the energy identity behind E16):
+// w_E . (C_e H) = -(w_H . C_h E), with C_e the E-update curl (D+ rows) and C_h
+// the H-update curl (D- rows), w_E, w_H the products of the 1D norm weights.
+// With that identity the adjoint recursion of the leapfrog step,
+//   lam_H^{n+1/2} = lam_H^{n+3/2} + C_e^T (Cb lam_E^{n+1})
+//   lam_E^n       = Ca lam_E^{n+1} + C_h^T (Db lam_H^{n+1/2}) + dJ/dE^n,
+// becomes, for p = Cb lam_E / w_E and r = -Db lam_H / w_H, the forward step
+// itself: r^{n+1/2} = r^{n+3/2} + Db C_h(p^{n+1}),
+// p^n = Ca p^{n+1} + Cb (C_e(r^{n+1/2}) + dJ/dE^n / w_E).  The step kernels
+// therefore run the adjoint on a second state; these kernels add the
+// objective's source, accumulate dJ/dCb = sum_n lam_E^{n+1} (E^{n+1} - E^n)/Cb
+// (lossless: Ca = 1), and chain dJ/dCb to the cells through Cb = 4 dt /
+// (eps0 S), S the sum of the four (clamped) cells around the node.
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace sbp {
+
+struct Region {
+  int lo[3], hi[3];  // half-open cell box
+};
+
+namespace {
+
+// Mean of component c (0 = Ex, 1 = Ey, 2 = Ez) over the four edges of cell
+// (ci, cj, ck) that carry it: the "-" node of the cell centre along c, both
+// "+" nodes of the cell along the other two axes.
+template <typename T>
+__device__ double cell_mean(const T* comp, const DevBlock& B, int c, int ci, int cj, int ck) {
+  int node[3] = {ci, cj, ck};
+  node[c] += 1;
+  const int a1 = c == 0 ? 1 : 0, a2 = c == 2 ? 1 : 2;
+  const long long st[3] = {1, B.sx, B.sxy};
+  const long long o = node[0] + B.sx * node[1] + B.sxy * node[2];
+  return 0.25 * (((double)comp[o] + (double)comp[o + st[a1]]) +
+                 ((double)comp[o + st[a2]] + (double)comp[o + st[a1] + st[a2]]));
+}
+
+// Sum S of eps_r over the four clamped cells around E node (i, j, k) of
+// component c (Ex: {ci0} x {cj0, cj1} x {ck0, ck1}; Ey: {ci0, ci1} x {cj0} x
+// {ck0, ck1}; Ez: {ci0, ci1} x {cj0, cj1} x {ck0}, ci0 = clamp(i-1),
+// ci1 = clamp(i), ...), and the four cells (repeated where clamped).
+struct NodeCells {
+  double S;
+  int cell[4];  // block-local cell indices ci + nx (cj + ny ck)
+};
+
+template <typename T>
+__device__ __forceinline__ const T* cells_of_block(const void* mat_eps, const DevBlock& B) {
+  return mat_eps ? (const T*)mat_eps + B.coff : nullptr;
+}
+
+// Norm weight w_E of E node (i, j, k) of component c: the product of the 1D
+// weights (Appendix P+, P-) with h.  The full geometric weight (not w / h^3)
+// keeps the adjoint variables of blocks of different mesh sizes consistent.
+__device__ __forceinline__ double e_weight(const DevBlock& B, int c, int i, int j, int k) {
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  const double wx = c == 0 ? wm1(nx, i) : wp1(nx, i);
+  const double wy = c == 1 ? wm1(ny, j) : wp1(ny, j);
+  const double wz = c == 2 ? wm1(nz, k) : wp1(nz, k);
+  return (wx * B.h[0]) * (wy * B.h[1]) * (wz * B.h[2]);
+}
+
+// dte0x4 / S: the E-update coefficient Cb of a lossless node (double).
+__device__ __forceinline__ double node_cb(const DevBlock& B, double S) { return B.dte0x4 / S; }
+
+template <typename T>
+__device__ NodeCells node_cells_t(const DevBlock& B, const void* mat_eps, int c, int i, int j, int k) {
+  const T* cv = cells_of_block<T>(mat_eps, B);
+  const bool has_eps = (B.mat & MAT_EPS) && cv;
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  NodeCells r;
+  const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
+  const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
+  const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
+  int q = 0;
+  r.S = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      int ci, cj, ck;
+      if (c == 0) { ci = ci0; cj = a ? cj1 : cj0; ck = b ? ck1 : ck0; }
+      else if (c == 1) { ci = a ? ci1 : ci0; cj = cj0; ck = b ? ck1 : ck0; }
+      else { ci = a ? ci1 : ci0; cj = b ? cj1 : cj0; ck = ck0; }
+      const int cell = ci + nx * (cj + ny * ck);
+      r.cell[q++] = cell;
+      r.S += has_eps ? (double)cv[cell] : B.eps_r0;
+    }
+  return r;
+}
+
+}  // namespace
+
+// J += dt sum_{cells in region} |Ebar|^2 of the state in `pool` (one workgroup).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_objective(const void* pool, const DevBlock* blocks, int block,
+                                                      Region r, double dt, double* J) {
+  __shared__ double red[4];
+  const DevBlock& B = blocks[block];
+  const T* base = (const T*)pool + B.foff;
+  const int ex = r.hi[0] - r.lo[0], ey = r.hi[1] - r.lo[1], ez = r.hi[2] - r.lo[2];
+  const int ncell = ex * ey * ez;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+    const int ci = r.lo[0] + q % ex, cj = r.lo[1] + (q / ex) % ey, ck = r.lo[2] + q / (ex * ey);
+    for (int c = 0; c < 3; ++c) {
+      const double m = cell_mean<T>(base + c * B.csz, B, c, ci, cj, ck);
+      s += m * m;
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += red[w];
+    J[0] += dt * t;
+  }
+}
+
+// p += Cb / w_E * dJ/dE^n on the region's edge nodes; dJ/dE^n from the
+// forward state E^n in `epool` (layout of the field pool).  `apool` is the
+// adjoint state.  One thread per edge node of the region.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_source(void* apool, const void* epool, const DevBlock* blocks,
+                                                   const void* mat_eps, int block, Region r, double dt) {
+  const DevBlock& B = blocks[block];
+  int cnt[3];
+  int ext[3][3];
+  for (int c = 0; c < 3; ++c) {
+    int n = 1;
+    for (int a = 0; a < 3; ++a) {
+      ext[c][a] = (a == c) ? (r.hi[a] - r.lo[a]) : (r.hi[a] - r.lo[a] + 1);
+      n *= ext[c][a];
+    }
+    cnt[c] = n;
+  }
+  const int total = cnt[0] + cnt[1] + cnt[2];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    int c = 0, q = t;
+    while (q >= cnt[c]) q -= cnt[c++];
+    int node[3];
+    node[0] = q % ext[c][0];
+    node[1] = (q / ext[c][0]) % ext[c][1];
+    node[2] = q / (ext[c][0] * ext[c][1]);
+    for (int a = 0; a < 3; ++a) node[a] += (a == c) ? r.lo[a] + 1 : r.lo[a];
+    // cells of the region having this node as one of their four edges
+    const T* e = (const T*)epool + B.foff + c * B.csz;
+    double g = 0.0;
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a == c) {
+        c0[a] = c1[a] = node[a] - 1;
+      } else {
+        c0[a] = max(node[a] - 1, r.lo[a]);
+        c1[a] = min(node[a], r.hi[a] - 1);
+      }
+    }
+    for (int ck = c0[2]; ck <= c1[2]; ++ck)
+      for (int cj = c0[1]; cj <= c1[1]; ++cj)
+        for (int ci = c0[0]; ci <= c1[0]; ++ci) g += cell_mean<T>(e, B, c, ci, cj, ck);
+    g *= 0.5 * dt;  // d/dE (dt Ebar^2) = 2 dt Ebar / 4 per cell
+    const NodeCells nc = node_cells_t<T>(B, mat_eps, c, node[0], node[1], node[2]);
+    const double cb = node_cb(B, nc.S);
+    const long long o = node[0] + B.sx * node[1] + B.sxy * node[2];
+    T* p = (T*)apool + B.foff + c * B.csz;
+    p[o] = (T)((double)p[o] + cb / e_weight(B, c, node[0], node[1], node[2]) * g);
+  }
+}
+
+// G += w_E p (E^{n+1} - E^n) / Cb^2 over the E nodes of the block: dJ/dCb of
+// step n, with p = p^{n+1} in the adjoint state `apool`.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_grad(const void* apool, const void* enew, const void* eold,
+                                                 const DevBlock* blocks, const void* mat_eps, int block,
+                                                 double* G) {
+  const DevBlock& B = blocks[block];
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  const long long sx = B.sx, sxy = B.sxy;
+  const long long plane = sx * (ny + 2);
+  const long long nodes = plane * (nz + 2);
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * nodes;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / nodes);
+    const long long q = t - c * nodes;
+    const int k = (int)(q / plane);
+    const long long rr = q - k * plane;
+    const int j = (int)(rr / sx), i = (int)(rr - j * sx);
+    const bool valid = c == 0 ? (j <= ny && k <= nz) : (c == 1 ? (i <= nx && k <= nz) : (i <= nx && j <= ny));
+    if (!valid) continue;
+    const long long o = i + sx * j + sxy * k;
+    const long long off = B.foff + c * B.csz + o;
+    const double pv = (double)((const T*)apool)[off];
+    const double de = (double)((const T*)enew)[off] - (double)((const T*)eold)[off];
+    const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
+    const double cb = node_cb(B, nc.S);
+    G[c * B.csz + o] += e_weight(B, c, i, j, k) * pv * de / (cb * cb);
+  }
+}
+
+// dJ/d eps_r per cell: sum over the E nodes of dJ/dCb * dCb/d eps_r(cell),
+// dCb/d eps_r = -Cb / S for each occurrence of the cell among the node's four.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, const void* mat_eps, int block,
+                                                  const double* G, double* grad) {
+  const DevBlock& B = blocks[block];
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  const long long sx = B.sx, sxy = B.sxy;
+  const long long plane = sx * (ny + 2);
+  const long long nodes = plane * (nz + 2);
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * nodes;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / nodes);
+    const long long q = t - c * nodes;
+    const int k = (int)(q / plane);
+    const long long rr = q - k * plane;
+    const int j = (int)(rr / sx), i = (int)(rr - j * sx);
+    const bool valid = c == 0 ? (j <= ny && k <= nz) : (c == 1 ? (i <= nx && k <= nz) : (i <= nx && j <= ny));
+    if (!valid) continue;
+    const long long o = i + sx * j + sxy * k;
+    const double gcb = G[c * B.csz + o];
+    if (gcb == 0.0) continue;
+    const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
+    const double d = -gcb * node_cb(B, nc.S) / nc.S;
+    for (int m = 0; m < 4; ++m) atomicAdd(&grad[nc.cell[m]], d);
+  }
+}
+
+template <typename T>
+hipError_t launch_adj_objective(const void* pool, const DevBlock* blocks, int block, const int r[6], double dt,
+                                double* J, hipStream_t s) {
+  Region R{{r[0], r[2], r[4]}, {r[1], r[3], r[5]}};
+  hipLaunchKernelGGL(k_adj_objective<T>, dim3(1), dim3(256), 0, s, pool, blocks, block, R, dt, J);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_adj_source(void* apool, const void* epool, const DevBlock* blocks, const void* mat_eps, int block,
+                             const int r[6], double dt, hipStream_t s) {
+  Region R{{r[0], r[2], r[4]}, {r[1], r[3], r[5]}};
+  long long total = 0;
+  for (int c = 0; c < 3; ++c) {
+    long long n = 1;
+    for (int a = 0; a < 3; ++a) n *= (a == c) ? (R.hi[a] - R.lo[a]) : (R.hi[a] - R.lo[a] + 1);
+    total += n;
+  }
+  const int grid = (int)std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_adj_source<T>, dim3(grid), dim3(256), 0, s, apool, epool, blocks, mat_eps, block, R, dt);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_adj_grad(const void* apool, const void* enew, const void* eold, const DevBlock* blocks,
+                           const void* mat_eps, int block, double* G, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_grad<T>, dim3(4096), dim3(256), 0, s, apool, enew, eold, blocks, mat_eps, block, G);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_adj_cells(const DevBlock* blocks, const void* mat_eps, int block, const double* G, double* grad,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_cells<T>, dim3(4096), dim3(256), 0, s, blocks, mat_eps, block, G, grad);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adj_objective<float>(const void*, const DevBlock*, int, const int*, double, double*,
+                                                hipStream_t);
+template hipError_t launch_adj_objective<double>(const void*, const DevBlock*, int, const int*, double, double*,
+                                                 hipStream_t);
+template hipError_t launch_adj_source<float>(void*, const void*, const DevBlock*, const void*, int, const int*,
+                                             double, hipStream_t);
+template hipError_t launch_adj_source<double>(void*, const void*, const DevBlock*, const void*, int, const int*,
+                                              double, hipStream_t);
+template hipError_t launch_adj_grad<float>(const void*, const void*, const void*, const DevBlock*, const void*, int,
+                                           double*, hipStream_t);
+template hipError_t launch_adj_grad<double>(const void*, const void*, const void*, const DevBlock*, const void*,
+                                            int, double*, hipStream_t);
+template hipError_t launch_adj_cells<float>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
+template hipError_t launch_adj_cells<double>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
+
+}  // namespace sbp

@@ -25,6 +25,15 @@ template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream
 template <typename T> hipError_t launch_e_energy(const KArgs&, int, int, hipStream_t);
 hipError_t launch_finish(const KArgs&, int, int, int, hipStream_t);
 template <typename T>
+hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, double, double*, hipStream_t);
+template <typename T>
+hipError_t launch_adj_source(void*, const void*, const DevBlock*, const void*, int, const int*, double, hipStream_t);
+template <typename T>
+hipError_t launch_adj_grad(const void*, const void*, const void*, const DevBlock*, const void*, int, double*,
+                           hipStream_t);
+template <typename T>
+hipError_t launch_adj_cells(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
+template <typename T>
 hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*,
                          hipStream_t);
 }  // namespace sbp
@@ -84,6 +93,9 @@ struct sbp_ctx {
   DevBlock* d_blocks = nullptr;
   std::vector<DevBlock> hblocks;
   Tile* d_tiles = nullptr;
+  Tile* d_tiles_bare = nullptr;  // same tiles, flags cleared
+  std::vector<Tile> bare;
+  size_t bare_cap = 0;
   int ntiles = 0;
   int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
   size_t tiles_cap = 0;
@@ -98,6 +110,7 @@ struct sbp_ctx {
   size_t partials_cap = 0;
   StepState* d_st = nullptr;
   double* d_face = nullptr;
+  size_t face_elems = 1;
   FaceJob* d_jobs_e = nullptr;
   FaceJob* d_jobs_h = nullptr;
   int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
@@ -458,6 +471,17 @@ sbp_status build_tiles(sbp_ctx* c) {
   }
   c->ntiles = (int)tl.size();
   HIPCHK(c, hipMemcpyAsync(c->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  // the same tiles without source / probe flags, for the adjoint state
+  if (tl.size() > c->bare_cap) {
+    dfree(c, c->d_tiles_bare);
+    c->d_tiles_bare = (Tile*)dalloc(c, tl.size() * sizeof(Tile));
+    if (!c->d_tiles_bare) return fail(c, SBP_ENOMEM, "tile list allocation failed");
+    c->bare_cap = tl.size();
+  }
+  c->bare.assign(tl.begin(), tl.end());
+  for (Tile& t : c->bare) t.pad = 0;
+  HIPCHK(c, hipMemcpyAsync(c->d_tiles_bare, c->bare.data(), c->bare.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                           c->stream));
   size_t grid = (size_t)grid_of(c, c->ntiles);
   size_t sum = 0;
   for (int kind = 0; kind < 4; ++kind)
@@ -522,14 +546,17 @@ sbp_status enqueue_e_energy(sbp_ctx* c) {
 // update, each update one launch per block kind followed by the energy
 // finish: slot n += H part of W^n; slot n+1 = E part of W^{n+1}, and the
 // step index advances.
-sbp_status enqueue_step(sbp_ctx* c, bool events) {
-  KArgs a = kargs(c);
+// One leapfrog step of the state that `a` points at (pool, face buffers,
+// energy / probe rings, step counter): the forward state (kargs(c)) or the
+// adjoint state of sbp_adjoint.
+sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   const int threads = c->tx * c->ty;
   const bool f64 = c->prec == SBP_FP64;
   hipError_t e;
+  double* face = const_cast<double*>(a.face);
   if (c->njobs_e) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a.pool, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a.pool, face, c->stream);
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
@@ -547,8 +574,8 @@ sbp_status enqueue_step(sbp_ctx* c, bool events) {
   HIPCHK(c, launch_finish(a, nparts, FIN_ADD, 0, c->stream));  // slot n += H part of W^n
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   if (c->njobs_h) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, c->pool, c->d_face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a.pool, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a.pool, face, c->stream);
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
@@ -567,6 +594,8 @@ sbp_status enqueue_step(sbp_ctx* c, bool events) {
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   return SBP_OK;
 }
+
+sbp_status enqueue_step(sbp_ctx* c, bool events) { return enqueue_step_on(c, kargs(c), events); }
 
 bool check_block(const sbp_ctx* c, int b) { return b >= 0 && b < (int)c->blocks.size(); }
 
@@ -831,6 +860,7 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->d_probes = (double*)dalloc(c, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double));
   c->d_st = (StepState*)dalloc(c, sizeof(StepState));
   c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
+  c->face_elems = std::max<size_t>(fboff, 1);
   if (!c->pool || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
     return fail(c, SBP_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
@@ -1230,6 +1260,145 @@ sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
   if (st2 != SBP_OK) return st2;
   if (st3 != SBP_OK) return st3;
   if (best_ms) *best_ms = best;
+  return SBP_OK;
+}
+
+sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], long ckpt_every, double* J_out,
+                       double* grad_eps_dev) {
+  if (!c || !region || !J_out || !grad_eps_dev) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "adjoint before finalize");
+  if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
+  if (nsteps < 1) return fail(c, SBP_EINVAL, "nsteps must be >= 1");
+  const HostBlock& hb = c->blocks[block];
+  for (int a = 0; a < 3; ++a)
+    if (region[2 * a] < 0 || region[2 * a + 1] > hb.n[a] || region[2 * a] >= region[2 * a + 1])
+      return fail(c, SBP_EINVAL, "region must be a non-empty cell box inside the block");
+  for (const HostBlock& b : c->blocks) {
+    bool lossy = false;
+    for (double v : b.sig) lossy = lossy || v != 0.0;
+    for (int f = 0; f < 6; ++f) lossy = lossy || (b.iface[f] < 0 && b.faces[f] == SBP_ABC1);
+    if (lossy) return fail(c, SBP_EINVAL, "the adjoint covers lossless blocks (no conductivity, no absorbing faces)");
+  }
+  long K = ckpt_every > 0 ? ckpt_every : (long)std::ceil(std::sqrt((double)nsteps));
+  if (K > nsteps) K = nsteps;
+  const long nck = (nsteps + K - 1) / K;
+  const bool f64 = c->prec == SBP_FP64;
+  const size_t pb = c->pool_elems * elem_size(c);
+  const size_t sb = pb + sizeof(StepState);
+  const DevBlock& d = c->hblocks[block];
+  const size_t gsz = 3 * (size_t)d.csz;
+  const size_t ncell = (size_t)hb.n[0] * hb.n[1] * hb.n[2];
+  HIPCHK(c, hipSetDevice(c->device));
+  drop_graph(c);
+  // buffers: checkpoints, one segment of forward states, the adjoint state
+  // (pool, face buffers, step counter, one-slot energy / probe rings), dJ/dCb
+  std::vector<void*> tmp;
+  auto take = [&](size_t bytes) {
+    void* p = dalloc(c, bytes);
+    if (p) tmp.push_back(p);
+    return p;
+  };
+  char* ck = (char*)take(nck * sb);
+  char* seg = (char*)take((K + 1) * pb);
+  char* fin = (char*)take(sb);
+  void* apool = take(pb);
+  double* aface = (double*)take(c->face_elems * sizeof(double));
+  StepState* ast = (StepState*)take(sizeof(StepState));
+  double* ering = (double*)take(2 * sizeof(double));
+  double* pring = (double*)take(std::max<size_t>(c->prbs.size(), 1) * sizeof(double));
+  double* G = (double*)take(gsz * sizeof(double));
+  double* Jd = (double*)take(sizeof(double));
+  auto release = [&]() {
+    for (void* p : tmp) dfree(c, p);
+  };
+  if (!ck || !seg || !fin || !apool || !aface || !ast || !ering || !pring || !G || !Jd) {
+    release();
+    return fail(c, SBP_ENOMEM, "adjoint buffer allocation failed");
+  }
+  sbp_status st = SBP_OK;
+  auto run = [&]() -> sbp_status {
+    HIPCHK(c, hipMemsetAsync(apool, 0, pb, c->stream));
+    HIPCHK(c, hipMemsetAsync(aface, 0, c->face_elems * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(ast, 0, sizeof(StepState), c->stream));
+    HIPCHK(c, hipMemsetAsync(G, 0, gsz * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(Jd, 0, sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(grad_eps_dev, 0, ncell * sizeof(double), c->stream));
+    if (c->e_energy_dirty) {
+      sbp_status s2 = enqueue_e_energy(c);
+      if (s2 != SBP_OK) return s2;
+      c->e_energy_dirty = false;
+    }
+    // forward: N steps from the current state, checkpoints every K steps, J
+    for (long n = 0; n < nsteps; ++n) {
+      if (n % K == 0) {
+        char* dst = ck + (size_t)(n / K) * sb;
+        HIPCHK(c, hipMemcpyAsync(dst, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dst + pb, c->d_st, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
+      }
+      sbp_status s2 = enqueue_step(c, false);
+      if (s2 != SBP_OK) return s2;
+      HIPCHK(c, f64 ? launch_adj_objective<double>(c->pool, c->d_blocks, block, region, c->dt, Jd, c->stream)
+                    : launch_adj_objective<float>(c->pool, c->d_blocks, block, region, c->dt, Jd, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(fin, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fin + pb, c->d_st, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
+    // adjoint state p^N = Cb / w_E dJ/dE^N, r^{N+1/2} = 0
+    HIPCHK(c, f64 ? launch_adj_source<double>(apool, c->pool, c->d_blocks, c->mat[0], block, region, c->dt, c->stream)
+                  : launch_adj_source<float>(apool, c->pool, c->d_blocks, c->mat[0], block, region, c->dt, c->stream));
+    // the forward replays write their energy / probe samples to one-slot
+    // scratch rings (the context's rings keep the forward samples); the
+    // adjoint state has its own pool, face buffers and step counter, and
+    // tiles without source / probe flags
+    KArgs fwd = kargs(c);
+    fwd.energy = ering;
+    fwd.ecap = 1;
+    fwd.probes = pring;
+    fwd.pcap = 1;
+    KArgs adj = fwd;
+    adj.pool = apool;
+    adj.face = aface;
+    adj.st = ast;
+    adj.tiles = c->d_tiles_bare;
+    adj.nsrc = 0;
+    for (long sgi = nck - 1; sgi >= 0; --sgi) {
+      const long a = sgi * K, b = std::min(a + K, nsteps);
+      const char* src = ck + (size_t)sgi * sb;
+      HIPCHK(c, hipMemcpyAsync(c->pool, src, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(c->d_st, src + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(seg, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+      for (long n = a; n < b; ++n) {
+        sbp_status s2 = enqueue_step_on(c, fwd, false);
+        if (s2 != SBP_OK) return s2;
+        HIPCHK(c, hipMemcpyAsync(seg + (size_t)(n + 1 - a) * pb, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+      }
+      for (long n = b - 1; n >= a; --n) {
+        const char* enew = seg + (size_t)(n + 1 - a) * pb;
+        const char* eold = seg + (size_t)(n - a) * pb;
+        HIPCHK(c, f64 ? launch_adj_grad<double>(apool, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream)
+                      : launch_adj_grad<float>(apool, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream));
+        sbp_status s2 = enqueue_step_on(c, adj, false);
+        if (s2 != SBP_OK) return s2;
+        if (n >= 1)
+          HIPCHK(c, f64 ? launch_adj_source<double>(apool, eold, c->d_blocks, c->mat[0], block, region, c->dt,
+                                                    c->stream)
+                        : launch_adj_source<float>(apool, eold, c->d_blocks, c->mat[0], block, region, c->dt,
+                                                   c->stream));
+      }
+    }
+    HIPCHK(c, f64 ? launch_adj_cells<double>(c->d_blocks, c->mat[0], block, G, grad_eps_dev, c->stream)
+                  : launch_adj_cells<float>(c->d_blocks, c->mat[0], block, G, grad_eps_dev, c->stream));
+    // back to the state after the forward run
+    HIPCHK(c, hipMemcpyAsync(c->pool, fin, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_st, fin + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(J_out, Jd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SBP_OK;
+  };
+  st = run();
+  (void)hipStreamSynchronize(c->stream);
+  release();
+  if (st != SBP_OK) return st;
+  c->nstep += nsteps;
   return SBP_OK;
 }
 

@@ -52,6 +52,24 @@ struct DevBlock {
   double ke, kh;  // 1/2 eps0 hx hy hz, 1/2 mu0 hx hy hz (energy of an interior node)
 };
 
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Norm weights / h (Appendix P+, P-) of node r on an axis of n cells.
+__device__ __forceinline__ float wp1(int n, int r) { return (r == 0 || r == n) ? 0.5f : 1.0f; }
+__device__ __forceinline__ float wm1(int n, int r) {
+  if (r == 0 || r == n + 1) return 0.5f;
+  if (r == 1 || r == n) return 0.25f;
+  if (r == 2 || r == n - 1) return 1.25f;
+  return 1.0f;
+}
+
+// Sum over a wave (64 lanes); lane 0 holds the total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 // A tile is `threads` consecutive nodes q0 .. q0+threads-1 of the flattened
 // (i fastest) xy node plane of one block, over the planes z0 .. z0+cz-1: each
 // thread walks one node column through the cz planes.  pad holds flags:

@@ -28,7 +28,6 @@ namespace sbp {
 
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Norm weight (diagonal of P+ or P- with h) of node r on an axis of n cells.
 __device__ __forceinline__ double wplus(int n, int r, double h) {
@@ -86,11 +85,6 @@ __device__ __forceinline__ double cellv(const void* arr, const DevBlock& B, int 
   return (double)((const T*)arr)[B.coff + ci + (long long)B.n[0] * (cj + (long long)B.n[1] * ck)];
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
 
 __device__ __forceinline__ double load_coherent(const double* p) {
   unsigned long long b = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
@@ -229,14 +223,6 @@ __device__ __forceinline__ T drow(const KArgs& a, const DevBlock& B, const T* __
   return v;
 }
 
-// Norm weights / h (Appendix P+, P-) of node r on an axis of n cells.
-__device__ __forceinline__ float wp1(int n, int r) { return (r == 0 || r == n) ? 0.5f : 1.0f; }
-__device__ __forceinline__ float wm1(int n, int r) {
-  if (r == 0 || r == n + 1) return 0.5f;
-  if (r == 1 || r == n) return 0.25f;
-  if (r == 2 || r == n - 1) return 1.25f;
-  return 1.0f;
-}
 
 // Probe samples of node (i, j, k): probes of the given field on that node
 // take the new values (only for tiles flagged as holding a probe).
