@@ -124,6 +124,74 @@ def batched(steps, warmup):
             "step_hbm_gbs_algorithmic": (hb + eb) / (ms * 1e-3) / 1e9}
 
 
+def subgrid(steps, warmup):
+    """The 1:2 subgrid workload: 27 blocks (coarse 192^3 region at 1 mm around
+    a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box, fp32."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(3)
+    cells = int(sum(np.prod(b["n"]) for b in prob["blocks"]))
+    stream = torch.cuda.Stream()
+    ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(True)
+    ctx.step(20)
+    torch.cuda.synchronize()
+    kern = ctx.kernel_ms()
+    ctx.close()
+    hb, eb = algorithmic_bytes(prob, 4)
+    ms = wall * 1e3 / steps
+    return {"workload": prob["name"], "cells": cells, "blocks": len(prob["blocks"]),
+            "interfaces": len(prob["interfaces"]), "steps": steps, "value": cells * steps / wall / 1e6,
+            "unit": "Mcell-updates/s", "ms_per_step": ms, "kernels_ms": list(kern),
+            "step_hbm_gbs_algorithmic": (hb + eb) / (ms * 1e-3) / 1e9}
+
+
+def adjoint_leg():
+    """The adjoint workload: 96^3 fp32, J over 2000 steps, checkpoints every
+    45 steps; one sbp_adjoint call (forward run, segment replays, reverse
+    sweep) timed."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(5)
+    n = prob["blocks"][0]["n"]
+    cells = int(np.prod(n))
+    steps = prob["steps"]
+    stream = torch.cuda.Stream()
+    ctx = build_problem(prob, prec="f32", stream=stream, history=steps + 8)
+    nb = ctx.state_bytes()
+    snap = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ctx.save_state(snap.data_ptr(), nb)
+    grad = torch.zeros((n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
+    ctx.adjoint(0, steps, prob["region"], grad.data_ptr(), prob["ckpt_every"])  # warm-up
+    ctx.load_state(snap.data_ptr(), nb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = ctx.adjoint(0, steps, prob["region"], grad.data_ptr(), prob["ckpt_every"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.load_state(snap.data_ptr(), nb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": prob["name"], "cells": cells, "steps": steps, "ckpt_every": prob["ckpt_every"],
+            "J": J, "gradient_s": wall, "forward_s": fwd, "gradient_over_forward": wall / fwd,
+            "value": cells * steps / wall / 1e6,
+            "unit": "Mcell-updates/s (forward-step equivalents per second of the gradient)"}
+
+
 def accuracy(scale):
     """Field/probe/energy error of the fp32 and fp64 paths against the fp64
     loop oracle on the same recipe at 256/scale cells per axis."""
@@ -185,6 +253,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-subgrid", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -236,6 +306,10 @@ def main():
                        "step_hbm_gbs_algorithmic": (hb8 + eb8) / (f64["wall_s"] / args.steps) / 1e9}
     if not args.no_batched:
         out["batched"] = batched(args.steps, max(args.warmup, 100))
+    if not args.no_subgrid:
+        out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg()
     if not args.no_accuracy:
         out["accuracy"] = accuracy(4)
     if not args.no_cpu_baseline:
