@@ -22,7 +22,6 @@
 namespace sbp {
 template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
-template <typename T> hipError_t launch_e_energy(const KArgs&, int, int, hipStream_t);
 hipError_t launch_finish(const KArgs&, int, int, int, hipStream_t);
 template <typename T>
 hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, double, double*, hipStream_t);
@@ -34,7 +33,7 @@ hipError_t launch_adj_grad(const void*, const void*, const void*, const DevBlock
 template <typename T>
 hipError_t launch_adj_cells(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
 template <typename T>
-hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*,
+hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int, double*,
                          hipStream_t);
 }  // namespace sbp
 
@@ -86,7 +85,8 @@ struct sbp_ctx {
   long long nstep = 0;
   long history = 0;
   // device buffers
-  void* pool = nullptr;
+  void* pool = nullptr;   // step n reads pool (n even) or pool2 (n odd) and writes the other
+  void* pool2 = nullptr;
   size_t pool_elems = 0;
   void* mat[3] = {nullptr, nullptr, nullptr};
   size_t ncells = 0;
@@ -116,7 +116,6 @@ struct sbp_ctx {
   int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
   Taps* d_taps = nullptr;
   int tx = 128, ty = 1, cz = 8, wgs = 0;  // launch shape (sbp_set_launch); fastest measured on 256^3 fp32
-  bool e_energy_dirty = true;
   std::string err;
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
@@ -506,6 +505,7 @@ KArgs kargs(sbp_ctx* c) {
   a.cz = c->cz;
   a.pad_ = 0;
   a.pool = c->pool;
+  a.pool2 = c->pool2;
   a.mat_eps = c->mat[0];
   a.mat_mu = c->mat[1];
   a.mat_sig = c->mat[2];
@@ -532,15 +532,10 @@ KArgs kargs(sbp_ctx* c) {
 
 int grid_size(const sbp_ctx* c) { return grid_of(c, c->ntiles); }
 
-sbp_status enqueue_e_energy(sbp_ctx* c) {
-  const KArgs a = kargs(c);
-  const int threads = c->tx * c->ty;
-  hipError_t e = c->prec == SBP_FP64 ? launch_e_energy<double>(a, grid_size(c), threads, c->stream)
-                                     : launch_e_energy<float>(a, grid_size(c), threads, c->stream);
-  HIPCHK(c, e);
-  HIPCHK(c, launch_finish(a, grid_size(c), 0, 0, c->stream));  // slot n = E part of W^n
-  return SBP_OK;
-}
+// The pool holding the state (E^n, H^{n-1/2}) at step n, and the other one.
+void* pool_at(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool2 : c->pool; }
+void* pool_other(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool : c->pool2; }
+
 
 // One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E
 // update, each update one launch per block kind followed by the energy
@@ -555,8 +550,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   hipError_t e;
   double* face = const_cast<double*>(a.face);
   if (c->njobs_e) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a.pool, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a.pool, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream);
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
@@ -571,11 +566,11 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     e = f64 ? launch_h<double>(a, kind, grid, threads, c->stream) : launch_h<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
-  HIPCHK(c, launch_finish(a, nparts, FIN_ADD, 0, c->stream));  // slot n += H part of W^n
+  HIPCHK(c, launch_finish(a, nparts, FIN_SRC, 0, c->stream));  // slot n = H part of W^n; sources at (n+1/2) dt
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   if (c->njobs_h) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a.pool, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a.pool, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream);
     HIPCHK(c, e);
   }
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
@@ -590,7 +585,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     e = f64 ? launch_e<double>(a, kind, grid, threads, c->stream) : launch_e<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
-  HIPCHK(c, launch_finish(a, nparts, FIN_STEP, 1, c->stream));  // slot n+1 = E part of W^{n+1}; n += 1
+  HIPCHK(c, launch_finish(a, nparts, FIN_ADD | FIN_STEP, 0, c->stream));  // slot n += E part of W^n; n += 1
   if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
   return SBP_OK;
 }
@@ -851,6 +846,7 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->pool_elems = foff;
   c->ncells = coff;
   c->pool = dalloc(c, foff * elem_size(c));
+  c->pool2 = dalloc(c, foff * elem_size(c));
   c->d_blocks = (DevBlock*)dalloc(c, c->hblocks.size() * sizeof(DevBlock));
   c->d_src = (Source*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(Source));
   c->d_srcval = (double*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(double));
@@ -861,9 +857,10 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->d_st = (StepState*)dalloc(c, sizeof(StepState));
   c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
   c->face_elems = std::max<size_t>(fboff, 1);
-  if (!c->pool || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
+  if (!c->pool || !c->pool2 || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
     return fail(c, SBP_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->pool2, 0, foff * elem_size(c), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_energy, 0, (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_probes, 0, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
@@ -935,7 +932,6 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   st = build_tiles(c);
   if (st != SBP_OK) return st;
   c->nstep = 0;
-  c->e_energy_dirty = true;
   if (dt_out) *dt_out = c->dt;
   return SBP_OK;
 }
@@ -961,7 +957,6 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
   sbp_status st = upload_materials(c);
   if (st != SBP_OK) return st;
   if (old[0] != c->mat[0] || old[1] != c->mat[1] || old[2] != c->mat[2]) drop_graph(c);
-  c->e_energy_dirty = true;
   return SBP_OK;
 }
 
@@ -991,11 +986,6 @@ sbp_status sbp_step(sbp_ctx* c, long nsteps) {
   if (nsteps == 0) return SBP_OK;
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-  if (c->e_energy_dirty) {
-    sbp_status st = enqueue_e_energy(c);
-    if (st != SBP_OK) return st;
-    c->e_energy_dirty = false;
-  }
   long done = 0;
   if (c->graph_steps > 0 && nsteps >= c->graph_steps && !c->profile) {
     if (!c->gexec) {
@@ -1056,7 +1046,7 @@ sbp_status sbp_read_field(sbp_ctx* c, int block, sbp_comp comp, double* dst, siz
   const DevBlock& d = c->hblocks[block];
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  const char* src = (const char*)c->pool + (size_t)(d.foff + comp * d.csz) * elem_size(c);
+  const char* src = (const char*)pool_at(c, c->nstep) + (size_t)(d.foff + comp * d.csz) * elem_size(c);
   if (c->prec == SBP_FP64) {
     std::vector<double> box(d.csz);
     HIPCHK(c, hipMemcpy(box.data(), src, d.csz * 8, hipMemcpyDeviceToHost));
@@ -1079,7 +1069,7 @@ sbp_status sbp_write_field(sbp_ctx* c, int block, sbp_comp comp, const double* s
   const DevBlock& d = c->hblocks[block];
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  char* dstp = (char*)c->pool + (size_t)(d.foff + comp * d.csz) * elem_size(c);
+  char* dstp = (char*)pool_at(c, c->nstep) + (size_t)(d.foff + comp * d.csz) * elem_size(c);
   if (c->prec == SBP_FP64) {
     std::vector<double> box(d.csz, 0.0);
     insert(box, d, s, srcp);
@@ -1089,7 +1079,6 @@ sbp_status sbp_write_field(sbp_ctx* c, int block, sbp_comp comp, const double* s
     insert(box, d, s, srcp);
     HIPCHK(c, hipMemcpy(dstp, box.data(), d.csz * 4, hipMemcpyHostToDevice));
   }
-  c->e_energy_dirty = true;
   return SBP_OK;
 }
 
@@ -1137,7 +1126,8 @@ sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
   size_t need;
   sbp_state_bytes(c, &need);
   if (bytes < need) return fail(c, SBP_EINVAL, "state buffer too small");
-  HIPCHK(c, hipMemcpyAsync(dev_buf, c->pool, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dev_buf, pool_at(c, c->nstep), c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice,
+                           c->stream));
   HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c), c->d_st, sizeof(StepState),
                            hipMemcpyDeviceToDevice, c->stream));
   return SBP_OK;
@@ -1149,17 +1139,17 @@ sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
   size_t need;
   sbp_state_bytes(c, &need);
   if (bytes < need) return fail(c, SBP_EINVAL, "state buffer too small");
-  HIPCHK(c, hipMemcpyAsync(c->pool, dev_buf, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
   StepState st;
   HIPCHK(c, hipMemcpyAsync(&st, (const char*)dev_buf + c->pool_elems * elem_size(c), sizeof(StepState),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpyAsync(pool_at(c, st.step), dev_buf, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice,
+                           c->stream));
   st.counter = 0;
   st.flags = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->nstep = st.step;
-  c->e_energy_dirty = true;
   return SBP_OK;
 }
 
@@ -1302,6 +1292,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   char* seg = (char*)take((K + 1) * pb);
   char* fin = (char*)take(sb);
   void* apool = take(pb);
+  void* apool2 = take(pb);
   double* aface = (double*)take(c->face_elems * sizeof(double));
   StepState* ast = (StepState*)take(sizeof(StepState));
   double* ering = (double*)take(2 * sizeof(double));
@@ -1311,40 +1302,38 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   auto release = [&]() {
     for (void* p : tmp) dfree(c, p);
   };
-  if (!ck || !seg || !fin || !apool || !aface || !ast || !ering || !pring || !G || !Jd) {
+  if (!ck || !seg || !fin || !apool || !apool2 || !aface || !ast || !ering || !pring || !G || !Jd) {
     release();
     return fail(c, SBP_ENOMEM, "adjoint buffer allocation failed");
   }
   sbp_status st = SBP_OK;
   auto run = [&]() -> sbp_status {
     HIPCHK(c, hipMemsetAsync(apool, 0, pb, c->stream));
+    HIPCHK(c, hipMemsetAsync(apool2, 0, pb, c->stream));
     HIPCHK(c, hipMemsetAsync(aface, 0, c->face_elems * sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(ast, 0, sizeof(StepState), c->stream));
     HIPCHK(c, hipMemsetAsync(G, 0, gsz * sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(Jd, 0, sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(grad_eps_dev, 0, ncell * sizeof(double), c->stream));
-    if (c->e_energy_dirty) {
-      sbp_status s2 = enqueue_e_energy(c);
-      if (s2 != SBP_OK) return s2;
-      c->e_energy_dirty = false;
-    }
-    // forward: N steps from the current state, checkpoints every K steps, J
+    // forward: N steps from the current state n0, checkpoints every K steps, J
+    const long long n0 = c->nstep;
     for (long n = 0; n < nsteps; ++n) {
       if (n % K == 0) {
         char* dst = ck + (size_t)(n / K) * sb;
-        HIPCHK(c, hipMemcpyAsync(dst, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dst, pool_at(c, n0 + n), pb, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(dst + pb, c->d_st, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
       }
       sbp_status s2 = enqueue_step(c, false);
       if (s2 != SBP_OK) return s2;
-      HIPCHK(c, f64 ? launch_adj_objective<double>(c->pool, c->d_blocks, block, region, c->dt, Jd, c->stream)
-                    : launch_adj_objective<float>(c->pool, c->d_blocks, block, region, c->dt, Jd, c->stream));
+      void* now = pool_at(c, n0 + n + 1);
+      HIPCHK(c, f64 ? launch_adj_objective<double>(now, c->d_blocks, block, region, c->dt, Jd, c->stream)
+                    : launch_adj_objective<float>(now, c->d_blocks, block, region, c->dt, Jd, c->stream));
     }
-    HIPCHK(c, hipMemcpyAsync(fin, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fin, pool_at(c, n0 + nsteps), pb, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(fin + pb, c->d_st, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
     // adjoint state p^N = Cb / w_E dJ/dE^N, r^{N+1/2} = 0
-    HIPCHK(c, f64 ? launch_adj_source<double>(apool, c->pool, c->d_blocks, c->mat[0], block, region, c->dt, c->stream)
-                  : launch_adj_source<float>(apool, c->pool, c->d_blocks, c->mat[0], block, region, c->dt, c->stream));
+    HIPCHK(c, f64 ? launch_adj_source<double>(apool, fin, c->d_blocks, c->mat[0], block, region, c->dt, c->stream)
+                  : launch_adj_source<float>(apool, fin, c->d_blocks, c->mat[0], block, region, c->dt, c->stream));
     // the forward replays write their energy / probe samples to one-slot
     // scratch rings (the context's rings keep the forward samples); the
     // adjoint state has its own pool, face buffers and step counter, and
@@ -1355,40 +1344,46 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     fwd.probes = pring;
     fwd.pcap = 1;
     KArgs adj = fwd;
-    adj.pool = apool;
+    adj.pool = apool;  // adjoint step m reads apool (m even) or apool2 (m odd)
+    adj.pool2 = apool2;
     adj.face = aface;
     adj.st = ast;
     adj.tiles = c->d_tiles_bare;
     adj.nsrc = 0;
+    long m = 0;  // adjoint steps taken
     for (long sgi = nck - 1; sgi >= 0; --sgi) {
       const long a = sgi * K, b = std::min(a + K, nsteps);
       const char* src = ck + (size_t)sgi * sb;
-      HIPCHK(c, hipMemcpyAsync(c->pool, src, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(pool_at(c, n0 + a), src, pb, hipMemcpyDeviceToDevice, c->stream));
       HIPCHK(c, hipMemcpyAsync(c->d_st, src + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(seg, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(seg, src, pb, hipMemcpyDeviceToDevice, c->stream));
       for (long n = a; n < b; ++n) {
         sbp_status s2 = enqueue_step_on(c, fwd, false);
         if (s2 != SBP_OK) return s2;
-        HIPCHK(c, hipMemcpyAsync(seg + (size_t)(n + 1 - a) * pb, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(seg + (size_t)(n + 1 - a) * pb, pool_at(c, n0 + n + 1), pb,
+                                 hipMemcpyDeviceToDevice, c->stream));
       }
       for (long n = b - 1; n >= a; --n) {
         const char* enew = seg + (size_t)(n + 1 - a) * pb;
         const char* eold = seg + (size_t)(n - a) * pb;
-        HIPCHK(c, f64 ? launch_adj_grad<double>(apool, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream)
-                      : launch_adj_grad<float>(apool, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream));
+        void* acur = (m & 1) ? apool2 : apool;
+        HIPCHK(c, f64 ? launch_adj_grad<double>(acur, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream)
+                      : launch_adj_grad<float>(acur, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream));
         sbp_status s2 = enqueue_step_on(c, adj, false);
         if (s2 != SBP_OK) return s2;
+        ++m;
+        void* anext = (m & 1) ? apool2 : apool;
         if (n >= 1)
-          HIPCHK(c, f64 ? launch_adj_source<double>(apool, eold, c->d_blocks, c->mat[0], block, region, c->dt,
+          HIPCHK(c, f64 ? launch_adj_source<double>(anext, eold, c->d_blocks, c->mat[0], block, region, c->dt,
                                                     c->stream)
-                        : launch_adj_source<float>(apool, eold, c->d_blocks, c->mat[0], block, region, c->dt,
+                        : launch_adj_source<float>(anext, eold, c->d_blocks, c->mat[0], block, region, c->dt,
                                                    c->stream));
       }
     }
     HIPCHK(c, f64 ? launch_adj_cells<double>(c->d_blocks, c->mat[0], block, G, grad_eps_dev, c->stream)
                   : launch_adj_cells<float>(c->d_blocks, c->mat[0], block, G, grad_eps_dev, c->stream));
     // back to the state after the forward run
-    HIPCHK(c, hipMemcpyAsync(c->pool, fin, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(pool_at(c, n0 + nsteps), fin, pb, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_st, fin + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(J_out, Jd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -111,9 +111,10 @@ struct StepState {
   int flags;            // bit 0: non-finite energy seen
 };
 
-// Energy-finish modes: FIN_ADD = add the total to the ring slot instead of
-// storing it; FIN_STEP = advance the step index afterwards.
-enum { FIN_ADD = 2, FIN_STEP = 4 };
+// Energy-finish modes: FIN_SRC = set the ring slot of the step to the total
+// and evaluate the source waveforms (after the H pass); FIN_ADD = add the
+// total to that slot; FIN_STEP = advance the step index (after the E pass).
+enum { FIN_SRC = 1, FIN_ADD = 2, FIN_STEP = 4 };
 
 // Arguments of the step kernels (one struct, passed by value).
 struct KArgs {
@@ -121,7 +122,8 @@ struct KArgs {
   const Tile* tiles;
   int ntiles;
   int cz, pad_;
-  void* pool;
+  void* pool;   // field pools: step n reads pool (n even) or pool2 (n odd)
+  void* pool2;  // and writes the other one
   const void* mat_eps;
   const void* mat_mu;
   const void* mat_sig;
@@ -141,5 +143,11 @@ struct KArgs {
   int t0, t1;  // tile range of this launch
   int poff;    // first partial-sum slot of this launch
 };
+
+// Field pools of step n: the one it reads (the state E^n, H^{n-1/2}) and
+// the one it writes (E^{n+1}, H^{n+1/2}).
+__device__ __forceinline__ void* pool_in(const KArgs& a, long long n) { return (n & 1) ? a.pool2 : a.pool; }
+__device__ __forceinline__ void* pool_out(const KArgs& a, long long n) { return (n & 1) ? a.pool : a.pool2; }
+
 
 }  // namespace sbp

@@ -29,17 +29,6 @@ namespace sbp {
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 
-// Norm weight (diagonal of P+ or P- with h) of node r on an axis of n cells.
-__device__ __forceinline__ double wplus(int n, int r, double h) {
-  return (r == 0 || r == n) ? 0.5 * h : h;
-}
-__device__ __forceinline__ double wminus(int n, int r, double h) {
-  if (r == 0 || r == n + 1) return 0.5 * h;
-  if (r == 1 || r == n) return 0.25 * h;
-  if (r == 2 || r == n - 1) return 1.25 * h;
-  return h;
-}
-
 __device__ __forceinline__ double face_value(const KArgs& a, const DevBlock& B, int face, int is_h,
                                              int slot, int i, int j, int k) {
   const int axis = face >> 1;
@@ -47,49 +36,6 @@ __device__ __forceinline__ double face_value(const KArgs& a, const DevBlock& B, 
                     : axis == 1 ? (long long)i + (long long)(B.n[0] + 2) * k
                                 : (long long)i + (long long)(B.n[0] + 2) * j;
   return a.face[B.fboff[face] + (long long)(is_h * 2 + slot) * B.fsz[face] + t];
-}
-
-// D- row r along `axis` applied to u at node offset o (the node with index r
-// on that axis), times 1/h, in fp64.  Closure rows come from the block's table.
-template <typename T>
-__device__ __forceinline__ double dminus(const KArgs& a, const DevBlock& B, int axis, const T* u,
-                                         long long o, long long st, int r, int slot, int i, int j,
-                                         int k) {
-  const int n = B.n[axis];
-  if (r >= 3 && r <= n - 2) return ((double)u[o] - (double)u[o - st]) * B.ih[axis];
-  const int ci = r < 3 ? r : r - (n - 1) + 3;
-  const Row& R = B.dm[axis][ci];
-  const T* p = u + o + (long long)R.s * st;
-  double v = R.c[0] * (double)p[0] + R.c[1] * (double)p[st] + R.c[2] * (double)p[2 * st];
-  if (R.nbr) v += R.cn * face_value(a, B, 2 * axis + (r >= 3 ? 1 : 0), 0, slot, i, j, k);
-  return v;
-}
-
-// D+ row r along `axis`, times 1/h, in fp64.
-template <typename T>
-__device__ __forceinline__ double dplus(const KArgs& a, const DevBlock& B, int axis, const T* u,
-                                        long long o, long long st, int r, int slot, int i, int j,
-                                        int k) {
-  const int n = B.n[axis];
-  if (r >= 2 && r <= n - 2) return ((double)u[o + st] - (double)u[o]) * B.ih[axis];
-  const int ci = r < 2 ? r : r - (n - 1) + 2;
-  const Row& R = B.dp[axis][ci];
-  const T* p = u + o + (long long)R.s * st;
-  double v = R.c[0] * (double)p[0] + R.c[1] * (double)p[st] + R.c[2] * (double)p[2 * st];
-  if (R.nbr) v += R.cn * face_value(a, B, 2 * axis + (r >= 2 ? 1 : 0), 1, slot, i, j, k);
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ double cellv(const void* arr, const DevBlock& B, int ci, int cj, int ck) {
-  return (double)((const T*)arr)[B.coff + ci + (long long)B.n[0] * (cj + (long long)B.n[1] * ck)];
-}
-
-
-__device__ __forceinline__ double load_coherent(const double* p) {
-  unsigned long long b = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)b);
 }
 
 // Workgroup sum of `v`, stored to partials[poff + blockIdx.x]; the launch's
@@ -116,7 +62,7 @@ __device__ __forceinline__ double waveform(const Source& s, double t) {
 // Sums partials[0 .. nparts) (one workgroup, fixed order) into the energy
 // ring: slot (step + delta) = total, or += total when `mode` has FIN_ADD;
 // flags a non-finite energy; FIN_STEP advances the step index.  The finish
-// between the H and the E pass (FIN_ADD) also evaluates the source
+// between the H and the E pass (FIN_SRC) also evaluates the source
 // waveforms at (n+1/2) dt for the E pass.
 __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts, int mode, int delta) {
   __shared__ double red[16];
@@ -126,7 +72,7 @@ __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts, int mode, 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
   const long long n = a.st->step;
-  if (mode & FIN_ADD) {
+  if (mode & FIN_SRC) {
     const double t = ((double)n + 0.5) * a.dt;
     for (int p = threadIdx.x; p < a.nsrc; p += blockDim.x) a.srcval[p] = a.src[p].amp * waveform(a.src[p], t);
   }
@@ -388,6 +334,8 @@ template <typename T, bool GEN>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
+  const void* pin = pool_in(a, nstep);
+  void* pout = pool_out(a, nstep);
   TileIter it(a.t1 - a.t0);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
@@ -397,19 +345,23 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double kh = Bc.kh;
-    T* base = (T*)a.pool + Bc.foff;
+    const T* base = (const T*)pin + Bc.foff;  // E^n, H^{n-1/2}
+    T* bout = (T*)pout + Bc.foff;             // H^{n+1/2}
     const long long csz = Bc.csz;
     const T* M = (GEN && (c.mat & MAT_MU)) ? (const T*)a.mat_mu : nullptr;
     const int q = tq0 + (int)threadIdx.x;
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
-    T* Ex = base;
-    T* Ey = base + csz;
-    T* Ez = base + 2 * csz;
-    T* Hx = base + 3 * csz;
-    T* Hy = base + 4 * csz;
-    T* Hz = base + 5 * csz;
+    const T* Ex = base;
+    const T* Ey = base + csz;
+    const T* Ez = base + 2 * csz;
+    const T* Hx = base + 3 * csz;
+    const T* Hy = base + 4 * csz;
+    const T* Hz = base + 5 * csz;
+    T* HxO = bout + 3 * csz;
+    T* HyO = bout + 4 * csz;
+    T* HzO = bout + 5 * csz;
     double es = 0.0;
     long long o = (long long)q + c.sxy * k0;
     HIn<T> cur;
@@ -427,7 +379,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, Hx, Hy, Hz, M, i, j, k, o, v0, v1, v2);
+      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -540,7 +492,7 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 // components, with the closure / PMC / absorbing / interface rows replacing
 // the interior differences on the boundary rows; the absorbing damping
 // 2/(eta h) on tangential face nodes joins the semi-implicit loss.  Returns
-// the node's 4 eps_r (w/h^3) (E^{n+1})^2.
+// the node's 4 eps_r (w/h^3) (E^n)^2 (the E part of W^n).
 template <typename T, bool HAS_EPS, bool GEN>
 __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const EIn<T>& v,
                                     T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
@@ -652,7 +604,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
   const T wx = vEx ? (T)(wm1(nx, i) * wp1(ny, j) * wp1(nz, k)) : T(0);
   const T wy = vEy ? (T)(wp1(nx, i) * wm1(ny, j) * wp1(nz, k)) : T(0);
   const T wz = vEz ? (T)(wp1(nx, i) * wp1(ny, j) * wm1(nz, k)) : T(0);
-  return wx * mx * (nex * nex) + wy * my * (ney * ney) + wz * mz * (nez * nez);
+  return wx * mx * (ex * ex) + wy * my * (ey * ey) + wz * mz * (ez * ez);
 }
 
 // E step over the tiles [t0, t1) of the tile list (one kind of block), one
@@ -663,6 +615,8 @@ template <typename T, bool HAS_EPS, bool GEN>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
+  const void* pin = pool_in(a, nstep);
+  void* pout = pool_out(a, nstep);
   TileIter it(a.t1 - a.t0);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
@@ -672,7 +626,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
     const double ke4 = 0.25 * Bc.ke;
-    T* base = (T*)a.pool + Bc.foff;
+    const T* base = (const T*)pin + Bc.foff;  // E^n
+    T* bout = (T*)pout + Bc.foff;             // H^{n+1/2} (read), E^{n+1} (written)
     const long long csz = Bc.csz;
     const T* ME = (const T*)a.mat_eps;
     const T* MS = (GEN && (c.mat & MAT_SIG)) ? (const T*)a.mat_sig : nullptr;
@@ -680,12 +635,15 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
-    T* Ex = base;
-    T* Ey = base + csz;
-    T* Ez = base + 2 * csz;
-    T* Hx = base + 3 * csz;
-    T* Hy = base + 4 * csz;
-    T* Hz = base + 5 * csz;
+    const T* Ex = base;
+    const T* Ey = base + csz;
+    const T* Ez = base + 2 * csz;
+    const T* Hx = bout + 3 * csz;
+    const T* Hy = bout + 4 * csz;
+    const T* Hz = bout + 5 * csz;
+    T* ExO = bout;
+    T* EyO = bout + csz;
+    T* EzO = bout + 2 * csz;
     const ColCells cc = col_cells(c, i, j);
     double es = 0.0;
     long long o = (long long)q + c.sxy * k0;
@@ -714,47 +672,12 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, cur, Ex, Ey, Ez, Hx, Hy, Hz, MS, i, j, k, o, jx, jy, jz, v0,
-                                            v1, v2);
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o, jx, jy, jz,
+                                            v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
     }
     eacc += ke4 * es;
-  }
-  store_partial(eacc, a);
-}
-
-// E part of W^n for the current fields (after a field write or a restore).
-template <typename T>
-__global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
-  double eacc = 0.0;
-  const long long nstep = a.st->step;
-  TileIter it(a.ntiles);
-  for (int t; it.next(t);) {
-    const Tile tl = a.tiles[t];
-    const DevBlock& B = a.blocks[tl.block];
-    const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-    const T* base = (const T*)a.pool + B.foff;
-    const bool has_eps = B.mat & MAT_EPS;
-    const int q = tl.q0 + (int)threadIdx.x;
-    if (q >= (int)B.sx * (ny + 2)) continue;
-    const int j = q / (int)B.sx, i = q - j * (int)B.sx;
-    for (int k = tl.z0; k < min(tl.z0 + a.cz, nz + 2); ++k) {
-      const long long o = q + B.sxy * k;
-      const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-      const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
-      const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
-      auto ev = [&](int ci, int cj, int ck) { return has_eps ? cellv<T>(a.mat_eps, B, ci, cj, ck) : B.eps_r0; };
-      const double epx = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci0, cj1, ck0)) + (ev(ci0, cj0, ck1) + ev(ci0, cj1, ck1))));
-      const double epy = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci1, cj0, ck0)) + (ev(ci0, cj0, ck1) + ev(ci1, cj0, ck1))));
-      const double epz = a.eps0 * (0.25 * ((ev(ci0, cj0, ck0) + ev(ci1, cj0, ck0)) + (ev(ci0, cj1, ck0) + ev(ci1, cj1, ck0))));
-      const double wxp = wplus(nx, i, B.h[0]), wxm = wminus(nx, i, B.h[0]);
-      const double wyp = wplus(ny, j, B.h[1]), wym = wminus(ny, j, B.h[1]);
-      const double wzp = wplus(nz, k, B.h[2]), wzm = wminus(nz, k, B.h[2]);
-      if (j <= ny && k <= nz) { const double v = (double)base[o]; eacc += 0.5 * epx * wxm * wyp * wzp * v * v; }
-      if (i <= nx && k <= nz) { const double v = (double)base[B.csz + o]; eacc += 0.5 * epy * wxp * wym * wzp * v * v; }
-      if (i <= nx && j <= ny) { const double v = (double)base[2 * B.csz + o]; eacc += 0.5 * epz * wxp * wyp * wzm * v * v; }
-    }
   }
   store_partial(eacc, a);
 }
@@ -766,8 +689,11 @@ __global__ __launch_bounds__(512) void k_e_energy(KArgs a) {
 // Accumulated in fp64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, const FaceJob* jobs,
-                                                     const Taps* taps, const void* pool,
-                                                     double* face) {
+                                                     const Taps* taps, const void* pool0, const void* pool1,
+                                                     const StepState* stp, int from_out, double* face) {
+  // E^n lives in the pool step n reads, H^{n+1/2} in the one it writes
+  const long long n = stp->step;
+  const void* pool = ((n & 1) != from_out) ? pool1 : pool0;
   const FaceJob J = jobs[blockIdx.y];
   const DevBlock& B = blocks[J.block];
   const DevBlock& N = blocks[J.nb];
@@ -816,21 +742,17 @@ hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t
   }
   return hipGetLastError();
 }
-template <typename T>
-hipError_t launch_e_energy(const KArgs& a, int grid, int threads, hipStream_t s) {
-  hipLaunchKernelGGL(k_e_energy<T>, dim3(grid), dim3(threads), 0, s, a);
-  return hipGetLastError();
-}
 hipError_t launch_finish(const KArgs& a, int nparts, int mode, int delta, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, nparts, mode, delta);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_gather(const DevBlock* blocks, const FaceJob* jobs, int njobs, int max_nodes,
-                         const Taps* taps, const void* pool, double* face, hipStream_t s) {
+                         const Taps* taps, const KArgs& a, int from_out, double* face, hipStream_t s) {
   if (njobs == 0) return hipSuccess;
   dim3 grid((max_nodes + 255) / 256, njobs);
-  hipLaunchKernelGGL(k_face_gather<T>, grid, dim3(256), 0, s, blocks, jobs, taps, pool, face);
+  hipLaunchKernelGGL(k_face_gather<T>, grid, dim3(256), 0, s, blocks, jobs, taps, a.pool, a.pool2, a.st, from_out,
+                     face);
   return hipGetLastError();
 }
 
@@ -838,9 +760,9 @@ template hipError_t launch_h<float>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_h<double>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_e<float>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_e<double>(const KArgs&, int, int, int, hipStream_t);
-template hipError_t launch_e_energy<float>(const KArgs&, int, int, hipStream_t);
-template hipError_t launch_e_energy<double>(const KArgs&, int, int, hipStream_t);
-template hipError_t launch_gather<float>(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*, hipStream_t);
-template hipError_t launch_gather<double>(const DevBlock*, const FaceJob*, int, int, const Taps*, const void*, double*, hipStream_t);
+template hipError_t launch_gather<float>(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int,
+                                        double*, hipStream_t);
+template hipError_t launch_gather<double>(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int,
+                                         double*, hipStream_t);
 
 }  // namespace sbp
