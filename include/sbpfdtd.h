@@ -159,6 +159,14 @@ sbp_status sbp_adjoint(sbp_ctx *ctx, int block, long nsteps, const int region[6]
 sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
 sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
 
+/* Selects how plain blocks (PEC / PMC faces, no conductivity, no per-cell
+ * permeability, no interfaces) are stepped: enable != 0 runs both half steps
+ * in one pass over the fields (each value read and written once per step),
+ * on windows of 64 x 8 node columns walking `planes` planes (4..4096);
+ * enable = 0 (the default) uses the H pass and the E pass.  Other blocks
+ * always take the two passes.  Both give the same fields up to rounding. */
+sbp_status sbp_set_fused(sbp_ctx *ctx, int enable, int planes);
+
 /* Measures candidate launch shapes on the current state (restored after)
  * and keeps the fastest; writes ms per step of the winner. */
 sbp_status sbp_autotune(sbp_ctx *ctx, int steps_per_trial, double *best_ms);
@@ -171,10 +179,11 @@ sbp_status sbp_use_graph(sbp_ctx *ctx, int steps);
  * valid after the stream has reached the end event. */
 sbp_status sbp_last_step_ms(sbp_ctx *ctx, double *ms);
 
-/* Mean duration (ms) per launch of the H and E kernels over the last
- * sbp_step call, from per-launch HIP events (enabled by sbp_profile(ctx,1)). */
+/* Mean time (ms) per step of the H pass, the E pass and the one-pass
+ * launches over the last sbp_step call, from HIP events around each group of
+ * launches on the context's stream (enabled by sbp_profile(ctx,1)). */
 sbp_status sbp_profile(sbp_ctx *ctx, int enable);
-sbp_status sbp_kernel_ms(sbp_ctx *ctx, double out[2]);
+sbp_status sbp_kernel_ms(sbp_ctx *ctx, double out[3]);
 
 const char *sbp_last_error(const sbp_ctx *ctx);
 void sbp_destroy(sbp_ctx *ctx);

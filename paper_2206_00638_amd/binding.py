@@ -54,6 +54,7 @@ SIGNATURES = {
     "sbp_load_state": [_P, _P, _S],
     "sbp_adjoint": [_P, _I, _L, _IP, _L, _DP, _P],
     "sbp_set_launch": [_P, _I, _I, _I, _I],
+    "sbp_set_fused": [_P, _I, _I],
     "sbp_get_launch": [_P, _IP],
     "sbp_autotune": [_P, _I, _DP],
     "sbp_use_graph": [_P, _I],
@@ -243,6 +244,9 @@ class Context:
     def set_launch(self, tx, ty, cz, workgroups=0):
         self._chk(self._lib.sbp_set_launch(self.h, tx, ty, cz, workgroups))
 
+    def set_fused(self, enable, planes=32):
+        self._chk(self._lib.sbp_set_fused(self.h, int(bool(enable)), int(planes)))
+
     def get_launch(self):
         o = (ctypes.c_int * 4)()
         self._chk(self._lib.sbp_get_launch(self.h, o))
@@ -265,7 +269,7 @@ class Context:
         self._chk(self._lib.sbp_profile(self.h, int(bool(enable))))
 
     def kernel_ms(self):
-        o = (ctypes.c_double * 2)()
+        o = (ctypes.c_double * 3)()
         self._chk(self._lib.sbp_kernel_ms(self.h, o))
         return tuple(o)
 

@@ -22,7 +22,9 @@
 namespace sbp {
 template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
-hipError_t launch_finish(const KArgs&, int, int, int, hipStream_t);
+hipError_t launch_finish(const KArgs&, int, hipStream_t);
+template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
+hipError_t launch_sources(const KArgs&, hipStream_t);
 template <typename T>
 hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, double, double*, hipStream_t);
 template <typename T>
@@ -95,9 +97,16 @@ struct sbp_ctx {
   Tile* d_tiles = nullptr;
   Tile* d_tiles_bare = nullptr;  // same tiles, flags cleared
   std::vector<Tile> bare;
+  std::vector<FTile> fbare;
   size_t bare_cap = 0;
   int ntiles = 0;
   int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
+  // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
+  int fused = 0, fz = 16;  // two passes by default: measured faster on the 256^3 workload
+  FTile* d_ftiles = nullptr;
+  FTile* d_ftiles_bare = nullptr;
+  size_t ftiles_cap = 0;
+  int fk_t0[2] = {0, 0}, fk_t1[2] = {0, 0};
   size_t tiles_cap = 0;
   Source* d_src = nullptr;
   double* d_srcval = nullptr;
@@ -436,6 +445,30 @@ int block_kind(const HostBlock& b) {
   return (b.eps.empty() ? 0 : 1) | (gen ? 2 : 0);
 }
 
+// Windows of W node columns along an axis of s = n+2 nodes for the one-pass
+// step: window t starts at st[t] and owns [lo[t], hi[t]]; all but the last
+// own W-1 columns (the last column of a window only supplies neighbour values
+// of H); the last window is moved back to end at the box edge and owns from
+// n-1 at the latest, so that the D+ closure rows of the far face (which reach
+// up to node n+1) lie inside one window.
+void windows(int s, int n, int W, std::vector<int>& st, std::vector<int>& lo, std::vector<int>& hi) {
+  if (s <= W) {
+    st = {0};
+    lo = {0};
+    hi = {s - 1};
+    return;
+  }
+  const int T = (s + W - 2) / (W - 1);
+  st.resize(T);
+  lo.resize(T);
+  hi.resize(T);
+  for (int t = 0; t < T; ++t) {
+    st[t] = t < T - 1 ? (W - 1) * t : s - W;
+    lo[t] = t < T - 1 ? (W - 1) * t : std::min((W - 1) * (T - 1), n - 1);
+  }
+  for (int t = 0; t < T; ++t) hi[t] = t < T - 1 ? lo[t + 1] - 1 : s - 1;
+}
+
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
   const int threads = c->tx * c->ty;
@@ -481,11 +514,56 @@ sbp_status build_tiles(sbp_ctx* c) {
   for (Tile& t : c->bare) t.pad = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_tiles_bare, c->bare.data(), c->bare.size() * sizeof(Tile), hipMemcpyHostToDevice,
                            c->stream));
-  size_t grid = (size_t)grid_of(c, c->ntiles);
+  // one-pass tiles of the plain kinds
+  std::vector<FTile> ft;
+  for (int kind = 0; kind < 2; ++kind) {
+    c->fk_t0[kind] = (int)ft.size();
+    for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+      const HostBlock& b = c->blocks[bi];
+      if (block_kind(b) != kind) continue;
+      std::vector<int> xs, xl, xh, ys, yl, yh, zl, zh;
+      windows(b.n[0] + 2, b.n[0], FX, xs, xl, xh);
+      windows(b.n[1] + 2, b.n[1], FY, ys, yl, yh);
+      for (int z = 0; z == 0 || z < b.n[2] - 1; z += c->fz) zl.push_back(z);
+      for (size_t q = 0; q < zl.size(); ++q) zh.push_back(q + 1 < zl.size() ? zl[q + 1] - 1 : b.n[2] + 1);
+      for (size_t zq = 0; zq < zl.size(); ++zq)
+        for (size_t yq = 0; yq < ys.size(); ++yq)
+          for (size_t xq = 0; xq < xs.size(); ++xq) {
+            FTile f{(int)bi, xs[xq], ys[yq], xl[xq], xh[xq], yl[yq], yh[yq], zl[zq], zh[zq], 0};
+            auto inside = [&](int i, int j, int k) {
+              return i >= f.olx && i <= f.ohx && j >= f.oly && j <= f.ohy && k >= f.z0 && k <= f.z1;
+            };
+            for (auto& sr : c->srcs)
+              if (sr.block == (int)bi && inside(sr.s.i, sr.s.j, sr.s.k)) f.flags |= 1;
+            for (auto& pr : c->prbs)
+              if (pr.block == (int)bi && inside(pr.p.i, pr.p.j, pr.p.k)) f.flags |= 2;
+            ft.push_back(f);
+          }
+    }
+    c->fk_t1[kind] = (int)ft.size();
+  }
+  if (ft.size() > c->ftiles_cap) {
+    dfree(c, c->d_ftiles);
+    dfree(c, c->d_ftiles_bare);
+    c->d_ftiles = (FTile*)dalloc(c, ft.size() * sizeof(FTile));
+    c->d_ftiles_bare = (FTile*)dalloc(c, ft.size() * sizeof(FTile));
+    if (!c->d_ftiles || !c->d_ftiles_bare) return fail(c, SBP_ENOMEM, "tile list allocation failed");
+    c->ftiles_cap = ft.size();
+  }
+  if (!ft.empty()) {
+    HIPCHK(c, hipMemcpyAsync(c->d_ftiles, ft.data(), ft.size() * sizeof(FTile), hipMemcpyHostToDevice, c->stream));
+    c->fbare.assign(ft.begin(), ft.end());
+    for (FTile& f : c->fbare) f.flags = 0;
+    HIPCHK(c, hipMemcpyAsync(c->d_ftiles_bare, c->fbare.data(), ft.size() * sizeof(FTile), hipMemcpyHostToDevice,
+                             c->stream));
+  }
   size_t sum = 0;
   for (int kind = 0; kind < 4; ++kind)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
-  grid = std::max(grid, sum);
+  size_t fsum = 0;
+  for (int kind = 0; kind < 2; ++kind)
+    if (c->fk_t1[kind] > c->fk_t0[kind]) fsum += (size_t)grid_of(c, c->fk_t1[kind] - c->fk_t0[kind]);
+  const size_t grid = 2 * sum + fsum + 8;  // partial sums of all launches of a step
   if (grid > c->partials_cap) {
     dfree(c, c->d_partials);
     c->d_partials = (double*)dalloc(c, grid * sizeof(double));
@@ -501,6 +579,7 @@ KArgs kargs(sbp_ctx* c) {
   KArgs a;
   a.blocks = c->d_blocks;
   a.tiles = c->d_tiles;
+  a.ftiles = c->d_ftiles;
   a.ntiles = c->ntiles;
   a.cz = c->cz;
   a.pad_ = 0;
@@ -549,15 +628,22 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   const bool f64 = c->prec == SBP_FP64;
   hipError_t e;
   double* face = const_cast<double*>(a.face);
+  auto mark = [&]() -> sbp_status {
+    if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+    return SBP_OK;
+  };
+  // kinds stepped by the two-pass kernels: all, or only the general ones
+  auto two_pass = [&](int kind) { return c->kind_t1[kind] > c->kind_t0[kind] && (!c->fused || (kind & 2)); };
   if (c->njobs_e) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream)
             : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream);
     HIPCHK(c, e);
   }
-  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  sbp_status st = mark();
+  if (st != SBP_OK) return st;
   int nparts = 0;
   for (int kind = 0; kind < 4; ++kind) {
-    if (c->kind_t1[kind] == c->kind_t0[kind]) continue;
+    if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
     a.poff = nparts;
@@ -566,17 +652,15 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     e = f64 ? launch_h<double>(a, kind, grid, threads, c->stream) : launch_h<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
-  HIPCHK(c, launch_finish(a, nparts, FIN_SRC, 0, c->stream));  // slot n = H part of W^n; sources at (n+1/2) dt
-  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream)
             : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream);
     HIPCHK(c, e);
   }
-  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
-  nparts = 0;
+  if ((st = mark()) != SBP_OK) return st;
   for (int kind = 0; kind < 4; ++kind) {
-    if (c->kind_t1[kind] == c->kind_t0[kind]) continue;
+    if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
     a.poff = nparts;
@@ -585,8 +669,22 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     e = f64 ? launch_e<double>(a, kind, grid, threads, c->stream) : launch_e<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
-  HIPCHK(c, launch_finish(a, nparts, FIN_ADD | FIN_STEP, 0, c->stream));  // slot n += E part of W^n; n += 1
-  if (events) HIPCHK(c, hipEventRecord(c->kev[c->kev_used++], c->stream));
+  if ((st = mark()) != SBP_OK) return st;
+  if ((st = mark()) != SBP_OK) return st;
+  if (c->fused) {
+    for (int kind = 0; kind < 2; ++kind) {
+      if (c->fk_t1[kind] == c->fk_t0[kind]) continue;
+      a.t0 = c->fk_t0[kind];
+      a.t1 = c->fk_t1[kind];
+      a.poff = nparts;
+      const int grid = grid_of(c, a.t1 - a.t0);
+      nparts += grid;
+      e = f64 ? launch_fused<double>(a, kind, grid, c->stream) : launch_fused<float>(a, kind, grid, c->stream);
+      HIPCHK(c, e);
+    }
+  }
+  if ((st = mark()) != SBP_OK) return st;
+  HIPCHK(c, launch_finish(a, nparts, c->stream));  // W^n into ring slot n; n += 1; sources of step n+1
   return SBP_OK;
 }
 
@@ -973,6 +1071,16 @@ sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
   return SBP_OK;
 }
 
+sbp_status sbp_set_fused(sbp_ctx* c, int enable, int planes) {
+  if (!c) return SBP_EINVAL;
+  if (planes < 4 || planes > 4096) return fail(c, SBP_EINVAL, "planes per one-pass tile must be 4..4096");
+  c->fused = enable ? 1 : 0;
+  c->fz = planes;
+  drop_graph(c);
+  if (c->finalized) return build_tiles(c);
+  return SBP_OK;
+}
+
 sbp_status sbp_get_launch(const sbp_ctx* c, int out[4]) {
   if (!c || !out) return SBP_EINVAL;
   out[0] = c->tx; out[1] = c->ty; out[2] = c->cz; out[3] = c->wgs;
@@ -986,6 +1094,7 @@ sbp_status sbp_step(sbp_ctx* c, long nsteps) {
   if (nsteps == 0) return SBP_OK;
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, launch_sources(kargs(c), c->stream));  // source values of the current step
   long done = 0;
   if (c->graph_steps > 0 && nsteps >= c->graph_steps && !c->profile) {
     if (!c->gexec) {
@@ -1005,7 +1114,7 @@ sbp_status sbp_step(sbp_ctx* c, long nsteps) {
     }
   }
   if (c->profile) {
-    const size_t need = (size_t)(nsteps - done) * 4;
+    const size_t need = (size_t)(nsteps - done) * 6;
     while (c->kev.size() < need) {
       hipEvent_t e;
       HIPCHK(c, hipEventCreate(&e));
@@ -1178,21 +1287,19 @@ sbp_status sbp_profile(sbp_ctx* c, int enable) {
   return SBP_OK;
 }
 
-sbp_status sbp_kernel_ms(sbp_ctx* c, double out[2]) {
+sbp_status sbp_kernel_ms(sbp_ctx* c, double out[3]) {
   if (!c || !out) return SBP_EINVAL;
-  if (!c->profile || c->kev_used < 4) return fail(c, SBP_ESTATE, "no profiled step");
+  if (!c->profile || c->kev_used < 6) return fail(c, SBP_ESTATE, "no profiled step");
   HIPCHK(c, hipEventSynchronize(c->kev[c->kev_used - 1]));
-  double h = 0.0, e = 0.0;
-  const int steps = c->kev_used / 4;
-  for (int s = 0; s < steps; ++s) {
-    float a = 0.0f, b = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&a, c->kev[4 * s], c->kev[4 * s + 1]));
-    HIPCHK(c, hipEventElapsedTime(&b, c->kev[4 * s + 2], c->kev[4 * s + 3]));
-    h += a;
-    e += b;
-  }
-  out[0] = h / steps;
-  out[1] = e / steps;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int steps = c->kev_used / 6;
+  for (int s = 0; s < steps; ++s)
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->kev[6 * s + 2 * q], c->kev[6 * s + 2 * q + 1]));
+      acc[q] += ms;
+    }
+  for (int q = 0; q < 3; ++q) out[q] = acc[q] / steps;
   return SBP_OK;
 }
 
@@ -1317,6 +1424,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     HIPCHK(c, hipMemsetAsync(grad_eps_dev, 0, ncell * sizeof(double), c->stream));
     // forward: N steps from the current state n0, checkpoints every K steps, J
     const long long n0 = c->nstep;
+    HIPCHK(c, launch_sources(kargs(c), c->stream));
     for (long n = 0; n < nsteps; ++n) {
       if (n % K == 0) {
         char* dst = ck + (size_t)(n / K) * sb;
@@ -1349,6 +1457,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     adj.face = aface;
     adj.st = ast;
     adj.tiles = c->d_tiles_bare;
+    adj.ftiles = c->d_ftiles_bare;
     adj.nsrc = 0;
     long m = 0;  // adjoint steps taken
     for (long sgi = nck - 1; sgi >= 0; --sgi) {
@@ -1357,6 +1466,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
       HIPCHK(c, hipMemcpyAsync(pool_at(c, n0 + a), src, pb, hipMemcpyDeviceToDevice, c->stream));
       HIPCHK(c, hipMemcpyAsync(c->d_st, src + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
       HIPCHK(c, hipMemcpyAsync(seg, src, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, launch_sources(fwd, c->stream));
       for (long n = a; n < b; ++n) {
         sbp_status s2 = enqueue_step_on(c, fwd, false);
         if (s2 != SBP_OK) return s2;

@@ -78,6 +78,16 @@ struct Tile {
   int block, q0, z0, pad;
 };
 
+// A tile of the one-pass step: a 64 x 8 window of node columns of one
+// block's xy plane starting at (i0, j0), on which H^{n+1/2} is formed, and
+// its owned part [olx, ohx] x [oly, ohy] x planes [z0, z1], on which H and E
+// are written (the unowned columns supply neighbour values of H only).
+// flags: bit 0 = a source, bit 1 = a probe lies in the owned part.
+constexpr int FX = 64, FY = 8;
+struct FTile {
+  int block, i0, j0, olx, ohx, oly, ohy, z0, z1, flags;
+};
+
 struct Source {
   int comp, i, j, k;
   int wave, pad;
@@ -111,15 +121,12 @@ struct StepState {
   int flags;            // bit 0: non-finite energy seen
 };
 
-// Energy-finish modes: FIN_SRC = set the ring slot of the step to the total
-// and evaluate the source waveforms (after the H pass); FIN_ADD = add the
-// total to that slot; FIN_STEP = advance the step index (after the E pass).
-enum { FIN_SRC = 1, FIN_ADD = 2, FIN_STEP = 4 };
 
 // Arguments of the step kernels (one struct, passed by value).
 struct KArgs {
   const DevBlock* blocks;
   const Tile* tiles;
+  const FTile* ftiles;
   int ntiles;
   int cz, pad_;
   void* pool;   // field pools: step n reads pool (n even) or pool2 (n odd)

@@ -59,12 +59,20 @@ __device__ __forceinline__ double waveform(const Source& s, double t) {
   return s.wave == 1 ? sin(2.0 * M_PI * s.f0 * t) * g : g;
 }
 
-// Sums partials[0 .. nparts) (one workgroup, fixed order) into the energy
-// ring: slot (step + delta) = total, or += total when `mode` has FIN_ADD;
-// flags a non-finite energy; FIN_STEP advances the step index.  The finish
-// between the H and the E pass (FIN_SRC) also evaluates the source
-// waveforms at (n+1/2) dt for the E pass.
-__global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts, int mode, int delta) {
+// Current density of every source at (n+1/2) dt, n the step index.
+__device__ __forceinline__ void eval_sources(const KArgs& a, long long n) {
+  const double t = ((double)n + 0.5) * a.dt;
+  for (int p = threadIdx.x; p < a.nsrc; p += blockDim.x) a.srcval[p] = a.src[p].amp * waveform(a.src[p], t);
+}
+
+// Source values of the current step (before the first step of a call, or
+// after the state was replaced).
+__global__ __launch_bounds__(256) void k_sources(KArgs a) { eval_sources(a, a.st->step); }
+
+// End of step n: sums partials[0 .. nparts) (one workgroup, fixed order)
+// into energy ring slot n (W^n), flags a non-finite energy, advances the
+// step index and evaluates the source values of step n+1.
+__global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts) {
   __shared__ double red[16];
   double s = 0.0;
   for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += a.partials[p];
@@ -72,19 +80,14 @@ __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts, int mode, 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
   const long long n = a.st->step;
-  if (mode & FIN_SRC) {
-    const double t = ((double)n + 0.5) * a.dt;
-    for (int p = threadIdx.x; p < a.nsrc; p += blockDim.x) a.srcval[p] = a.src[p].amp * waveform(a.src[p], t);
-  }
+  eval_sources(a, n + 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < nw; ++w) tot += red[w];
-    const int slot = (int)((n + delta) % a.ecap);
-    if (mode & FIN_ADD) tot += a.energy[slot];
-    a.energy[slot] = tot;
+    a.energy[(int)(n % a.ecap)] = tot;
     if (!isfinite(tot)) a.st->flags |= 1;
-    if (mode & FIN_STEP) a.st->step = n + 1;
+    a.st->step = n + 1;
   }
 }
 
@@ -267,7 +270,7 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
                                     T* __restrict__ Hz, const T* __restrict__ M, int i, int j, int k,
-                                    long long o, T& onx, T& ony, T& onz) {
+                                    long long o, bool store, T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -314,9 +317,9 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
   const T nhy = hy + dby * (dxEz - dzEx);
   const T nhz = hz + dbz * (dyEx - dxEy);
   const bool vx = i <= nx, vy = j <= ny, vz = k <= nz;
-  if (vx) Hx[o] = nhx;
-  if (vy) Hy[o] = nhy;
-  if (vz) Hz[o] = nhz;
+  if (store && vx) Hx[o] = nhx;
+  if (store && vy) Hy[o] = nhy;
+  if (store && vz) Hz[o] = nhz;
   onx = nhx;
   ony = nhy;
   onz = nhz;
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, v0, v1, v2);
+      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -682,6 +685,235 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   store_partial(eacc, a);
 }
 
+// ------------------------------------------------------------ one-pass step
+// For plain blocks (PEC / PMC faces, per-cell or uniform permittivity) both
+// half steps run in one pass: a workgroup takes a 64 x 8 window of node
+// columns and walks up through the planes.  At plane kh it forms H^{n+1/2}
+// on the whole window (the same rows as k_h_update) and keeps it in LDS; E
+// at plane kh-2 then takes its in-plane neighbours of H^{n+1/2} from LDS and
+// its z neighbours (planes kh-3 .. kh) from registers, so the D+ closure rows
+// (which reach one node back and two ahead) are local too.  Each field value
+// is read once and written once per step; the window's unowned columns (one
+// halo column and row) only supply H neighbours.
+template <typename T>
+__device__ __forceinline__ T lds_h(const T (&hs)[4][3][FY][FX], int slot, int comp, int w, int lane) {
+  return hs[slot][comp][min(max(w, 0), FY - 1)][min(max(lane, 0), FX - 1)];
+}
+
+// D+ closure row along x (axis 0) or y (axis 1) from the LDS plane.
+template <typename T>
+__device__ __forceinline__ T lds_row(const T (&hs)[4][3][FY][FX], int slot, int comp, int w, int lane, int axis,
+                                     const TRow<T>& R) {
+  const int dl = axis == 0 ? 1 : 0, dw = axis == 1 ? 1 : 0;
+  const int l0 = lane + dl * R.s, w0 = w + dw * R.s;
+  return R.c0 * lds_h(hs, slot, comp, w0, l0) + R.c1 * lds_h(hs, slot, comp, w0 + dw, l0 + dl) +
+         R.c2 * lds_h(hs, slot, comp, w0 + 2 * dw, l0 + 2 * dl);
+}
+
+// One of the own-column values H(k-1), H(k), H(k+1), H(k+2) by offset d.
+template <typename T>
+__device__ __forceinline__ T pick4(int d, T m1, T z0, T p1, T p2) {
+  return d <= -1 ? m1 : (d == 0 ? z0 : (d == 1 ? p1 : p2));
+}
+
+template <typename T, bool HAS_EPS>
+__global__ __launch_bounds__(512) void k_fused(KArgs a) {
+  __shared__ T hs[4][3][FY][FX];  // H^{n+1/2} of the last four planes: [plane & 3][comp][row][column]
+  double eacc = 0.0;
+  const long long nstep = a.st->step;
+  const void* pin = pool_in(a, nstep);
+  void* pout = pool_out(a, nstep);
+  const int lane = threadIdx.x & (FX - 1), w = threadIdx.x / FX;
+  TileIter it(a.t1 - a.t0);
+  for (int tv; it.next(tv);) {
+    const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
+    const SBP_CONST FTile& ft = as_const(a.ftiles)[t];
+    const int tb = ft.block, z0 = ft.z0, z1 = ft.z1, tflags = ft.flags;
+    const DevBlock& B = a.blocks[tb];
+    const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
+    const BC<T> c(Bc);
+    const double kh_e = Bc.kh, ke4 = 0.25 * Bc.ke;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int sx = (int)c.sx;
+    const long long sxy = c.sxy, csz = Bc.csz;
+    const T* base = (const T*)pin + Bc.foff;
+    T* bout = (T*)pout + Bc.foff;
+    const T* Ex = base;
+    const T* Ey = base + csz;
+    const T* Ez = base + 2 * csz;
+    const T* Hx = base + 3 * csz;
+    const T* Hy = base + 4 * csz;
+    const T* Hz = base + 5 * csz;
+    T* ExO = bout;
+    T* EyO = bout + csz;
+    T* EzO = bout + 2 * csz;
+    T* HxO = bout + 3 * csz;
+    T* HyO = bout + 4 * csz;
+    T* HzO = bout + 5 * csz;
+    const T* ME = (const T*)a.mat_eps;
+    const int i = ft.i0 + lane, j = ft.j0 + w;
+    const bool col = i < sx && j < ny + 2;
+    const bool own = col && i >= ft.olx && i <= ft.ohx && j >= ft.oly && j <= ft.ohy;
+    const long long oc = col ? (long long)i + (long long)sx * j : 0;
+    const ColCells cc = col_cells(c, col ? i : 0, col ? j : 0);
+    const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
+    // own column: Hx, Hy of H^{n+1/2} at planes kh-3 .. kh, E^n at kh-2, kh-1
+    T hx3 = T(0), hx2 = T(0), hx1 = T(0), hx0 = T(0), hy3 = T(0), hy2 = T(0), hy1 = T(0), hy0 = T(0);
+    T e2x = T(0), e2y = T(0), e2z = T(0), e1x = T(0), e1y = T(0), e1z = T(0);
+    T q0a = T(0), q0b = T(0), q0c = T(0), q0d = T(0);  // permittivity cells of plane ke-1
+    T q1a = T(0), q1b = T(0), q1c = T(0), q1d = T(0);  // and of plane ke
+    if (HAS_EPS && col) {
+      const T* p0 = ME + cc.A + cc.cp * clampi(z0 - 1, 0, nz - 1);
+      q0a = p0[0];
+      q0b = p0[cc.dx];
+      q0c = p0[cc.dy];
+      q0d = p0[cc.dx + cc.dy];
+      const T* p1 = ME + cc.A + cc.cp * clampi(z0, 0, nz - 1);
+      q1a = p1[0];
+      q1b = p1[cc.dx];
+      q1c = p1[cc.dy];
+      q1d = p1[cc.dx + cc.dy];
+    }
+    const int kh_last = min(z1 + 2, nz + 1);  // last H plane of the tile
+    // inputs of the H plane, loaded one plane ahead of its use
+    HIn<T> vn;
+    if (col) {
+      const long long o = oc + sxy * z0;
+      h_load<T>(vn, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
+      vn.ex_z = z0 > 0 ? Ex[o - sxy] : vn.ex;
+      vn.ey_z = z0 > 0 ? Ey[o - sxy] : vn.ey;
+    }
+    for (int kh = z0; kh <= z1 + 2; ++kh) {
+      const int slot = kh & 3;
+      const HIn<T> v = vn;
+      if (col && kh + 1 <= kh_last) {  // next plane's loads overlap this plane's work
+        const long long o = oc + sxy * (kh + 1);
+        h_load<T>(vn, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
+        vn.ex_z = v.ex;
+        vn.ey_z = v.ey;
+      }
+      T nhx = T(0), nhy = T(0), nhz = T(0), ex = T(0), ey = T(0), ez = T(0);
+      if (col && kh <= kh_last) {
+        const long long o = oc + sxy * kh;
+        const bool hown = own && kh <= z1;
+        T v0, v1, v2;
+        const T eh = h_node<T, false>(a, B, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o, hown, v0, v1,
+                                      v2);
+        if (hown) {
+          eacc += kh_e * (double)eh;
+          if (tflags & 2) take_probes<T>(a, B, i, j, kh, true, nstep, v0, v1, v2);
+        }
+        nhx = v0;
+        nhy = v1;
+        nhz = v2;
+        ex = v.ex;
+        ey = v.ey;
+        ez = v.ez;
+      }
+      hx3 = hx2;
+      hx2 = hx1;
+      hx1 = hx0;
+      hx0 = nhx;
+      hy3 = hy2;
+      hy2 = hy1;
+      hy1 = hy0;
+      hy0 = nhy;
+      hs[slot][0][w][lane] = nhx;
+      hs[slot][1][w][lane] = nhy;
+      hs[slot][2][w][lane] = nhz;
+      // permittivity cells of the next E plane (ke + 1 = kh - 1), loaded ahead
+      T r1a = q1a, r1b = q1b, r1c = q1c, r1d = q1d;
+      if (HAS_EPS && col && kh - 1 > z0) {
+        const T* p1 = ME + cc.A + cc.cp * clampi(kh - 1, 0, nz - 1);
+        r1a = p1[0];
+        r1b = p1[cc.dx];
+        r1c = p1[cc.dy];
+        r1d = p1[cc.dx + cc.dy];
+      }
+      __syncthreads();
+      const int ke = kh - 2;
+      if (ke >= z0) {
+        if (own) {
+          const int sl = ke & 3;  // LDS slot of plane ke
+          const T hx = hx2, hy = hy2, hz = hs[sl][2][w][lane];
+          T dyHz = (lds_h(hs, sl, 2, w + 1, lane) - hz) * ihy;
+          T dyHx = (lds_h(hs, sl, 0, w + 1, lane) - hx) * ihy;
+          T dxHz = (lds_h(hs, sl, 2, w, lane + 1) - hz) * ihx;
+          T dxHy = (lds_h(hs, sl, 1, w, lane + 1) - hy) * ihx;
+          T dzHy = (hy1 - hy) * ihz, dzHx = (hx1 - hx) * ihz;
+          const bool xin = i >= 2 && i <= nx - 2, yin = j >= 2 && j <= ny - 2, zin = ke >= 2 && ke <= nz - 2;
+          if (!zin) {
+            if (ke <= nz) {
+              const TRow<T> rz = row_of<T>(B, 2, ke, false);
+              dzHy = rz.c0 * pick4(rz.s, hy3, hy2, hy1, hy0) + rz.c1 * pick4(rz.s + 1, hy3, hy2, hy1, hy0) +
+                     rz.c2 * pick4(rz.s + 2, hy3, hy2, hy1, hy0);
+              dzHx = rz.c0 * pick4(rz.s, hx3, hx2, hx1, hx0) + rz.c1 * pick4(rz.s + 1, hx3, hx2, hx1, hx0) +
+                     rz.c2 * pick4(rz.s + 2, hx3, hx2, hx1, hx0);
+            } else {
+              dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
+            }
+          }
+          if (!yin) {
+            const TRow<T> ry = row_of<T>(B, 1, j, false);
+            dyHz = lds_row(hs, sl, 2, w, lane, 1, ry);
+            dyHx = lds_row(hs, sl, 0, w, lane, 1, ry);
+          }
+          if (!xin) {
+            const TRow<T> rx = row_of<T>(B, 0, i, false);
+            dxHz = lds_row(hs, sl, 2, w, lane, 0, rx);
+            dxHy = lds_row(hs, sl, 1, w, lane, 0, rx);
+          }
+          const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
+          T mx = T(4) * c.eps_r0, my = mx, mz = mx;
+          T cbx, cby, cbz;
+          if (HAS_EPS) {
+            mx = (q0a + q0c) + (q1a + q1c);
+            my = (q0a + q0b) + (q1a + q1b);
+            mz = (q0a + q0b) + (q0c + q0d);
+            cbx = c.dte0x4 / mx;
+            cby = c.dte0x4 / my;
+            cbz = c.dte0x4 / mz;
+          } else {
+            cbx = cby = cbz = c.cb_u;
+          }
+          T jx = T(0), jy = T(0), jz = T(0);
+          if (tflags & 1) source_terms<T>(a, B, i, j, ke, jx, jy, jz);
+          const T nex = e2x + cbx * (cx + jx);
+          const T ney = e2y + cby * (cy + jy);
+          const T nez = e2z + cbz * (cz + jz);
+          const bool vz = ke <= nz;
+          const bool vEx = j <= ny && vz, vEy = i <= nx && vz, vEz = i <= nx && j <= ny;
+          const long long o = oc + sxy * ke;
+          if (vEx) ExO[o] = nex;
+          if (vEy) EyO[o] = ney;
+          if (vEz) EzO[o] = nez;
+          const T wx = vEx ? (T)(wm1(nx, i) * wp1(ny, j) * wp1(nz, ke)) : T(0);
+          const T wy = vEy ? (T)(wp1(nx, i) * wm1(ny, j) * wp1(nz, ke)) : T(0);
+          const T wz = vEz ? (T)(wp1(nx, i) * wp1(ny, j) * wm1(nz, ke)) : T(0);
+          eacc += ke4 * (double)(wx * mx * (e2x * e2x) + wy * my * (e2y * e2y) + wz * mz * (e2z * e2z));
+          if (tflags & 2) take_probes<T>(a, B, i, j, ke, false, nstep, nex, ney, nez);
+        }
+        q0a = q1a;
+        q0b = q1b;
+        q0c = q1c;
+        q0d = q1d;
+        q1a = r1a;
+        q1b = r1b;
+        q1c = r1c;
+        q1d = r1d;
+      }
+      e2x = e1x;
+      e2y = e1y;
+      e2z = e1z;
+      e1x = ex;
+      e1y = ey;
+      e1z = ez;
+    }
+    __syncthreads();  // the next tile rewrites the LDS planes
+  }
+  store_partial(eacc, a);
+}
+
 // ------------------------------------------------------- interface gather
 // Fills the face buffers: for every own face node, the neighbour's
 // tangential field on its coincident face, through the per-axis taps
@@ -742,8 +974,21 @@ hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t
   }
   return hipGetLastError();
 }
-hipError_t launch_finish(const KArgs& a, int nparts, int mode, int delta, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, nparts, mode, delta);
+template <typename T>
+hipError_t launch_fused(const KArgs& a, int kind, int grid, hipStream_t s) {
+  if (kind & 1) hipLaunchKernelGGL((k_fused<T, true>), dim3(grid), dim3(FX * FY), 0, s, a);
+  else hipLaunchKernelGGL((k_fused<T, false>), dim3(grid), dim3(FX * FY), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_fused<float>(const KArgs&, int, int, hipStream_t);
+template hipError_t launch_fused<double>(const KArgs&, int, int, hipStream_t);
+
+hipError_t launch_finish(const KArgs& a, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, nparts);
+  return hipGetLastError();
+}
+hipError_t launch_sources(const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sources, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>

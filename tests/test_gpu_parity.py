@@ -280,6 +280,86 @@ def test_graph_replay_bitwise(sbp):
         assert np.allclose(e_got, e_ref, rtol=1e-13, atol=0)
 
 
+# -------------------------------------------------------- one-pass step
+def _plain_problem(seed, n=(126, 13, 41), faces=("pec", "pmc", "pec", "pmc", "pmc", "pec")):
+    """A plain block (PEC / PMC faces, per-cell eps_r) whose sizes make the
+    one-pass windows shift back at the far x and y faces (126 + 2 nodes: last
+    window owns from n-1; 13 + 2 nodes: likewise in y)."""
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    b = block(n, (1e-3, 1.2e-3, 0.9e-3), faces, eps_r=rng.uniform(1, 4, shape))
+    return {"blocks": [b], "interfaces": [], "cfl": 0.9,
+            "sources": [{"block": 0, "comp": "Ez", "node": (n[0] // 2 - 3, n[1] // 2, n[2] // 2), "waveform": "modgauss",
+                         "tw": 3e-11, "t0": 3e-11, "f0": 1e10, "amp": 1.0},
+                        {"block": 0, "comp": "Ey", "node": (n[0], 1, 5), "waveform": "gauss",
+                         "tw": 2e-11, "t0": 2e-11, "f0": 0.0, "amp": 0.5}],
+            "probes": [{"block": 0, "comp": "Ez", "node": (n[0] // 2 - 1, n[1] // 2 - 1, 3 * n[2] // 4)},
+                       {"block": 0, "comp": "Hx", "node": (n[0], 0, n[2] + 1)},
+                       {"block": 0, "comp": "Ex", "node": (n[0] + 1, n[1], 3)},
+                       {"block": 0, "comp": "Hz", "node": (63, n[1] // 2, n[2] // 2 + 1)}]}
+
+
+def _run_ctx(sbp, prob, prec, steps, init, fused, planes=32):
+    ctx = sbp.build_problem(prob, prec=prec)
+    ctx.set_fused(fused, planes)
+    write_fields(ctx, init)
+    ctx.step(steps)
+    out = {"fields": gpu_fields(ctx, prob), "energy": ctx.read_energy(0, steps),
+           "probes": np.array([ctx.read_probe(p, 0, steps) for p in range(len(prob["probes"]))])}
+    ctx.close()
+    return out
+
+
+def test_one_pass_matches_oracle_and_two_pass(sbp):
+    from oracle import loops
+    prob = _plain_problem(7)
+    init = random_fields(prob, 3)
+    steps = 30
+    ref = loops.run_block(prob, steps=steps, init={c: init[(0, c)] for c in COMPS})
+    ref_f = {(0, c): ref["fields"][c] for c in COMPS}
+    for prec in ("f64", "f32"):
+        two = _run_ctx(sbp, prob, prec, steps, init, False)
+        for planes in (4, 7, 32, 300):
+            one = _run_ctx(sbp, prob, prec, steps, init, True, planes)
+            err = field_errors(one["fields"], ref_f, FLOOR[prec])
+            assert max(err.values()) <= TOL[prec], (prec, planes, err)
+            assert rel_l2(one["probes"], ref["probes"]) <= TOL[prec], (prec, planes)
+            assert rel_l2(one["energy"], ref["energy"]) <= TOL[prec], (prec, planes)
+            tol2 = 1e-13 if prec == "f64" else 1e-6
+            for k in ref_f:
+                assert rel_l2(one["fields"][k], two["fields"][k]) <= tol2, (prec, planes, k)
+            assert np.allclose(one["energy"], two["energy"], rtol=1e-12 if prec == "f64" else 1e-6, atol=0)
+
+
+def test_one_pass_graph_and_restore_bitwise(sbp):
+    import torch
+    stream = torch.cuda.Stream()
+    prob = _plain_problem(8, n=(70, 21, 19))
+    init = random_fields(prob, 4)
+    for prec in ("f64", "f32"):
+        a = sbp.build_problem(prob, prec=prec)
+        write_fields(a, init)
+        a.step(23)
+        ref = gpu_fields(a, prob)
+        e_ref = a.read_energy(0, 23)
+        a.close()
+        b = sbp.build_problem(prob, prec=prec, stream=stream)
+        write_fields(b, init)
+        nb = b.state_bytes()
+        snap = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b.save_state(snap.data_ptr(), nb)
+        b.use_graph(5)
+        for r in range(3):  # replays of the captured graph, restored between them
+            b.load_state(snap.data_ptr(), nb)
+            b.step(23)    # 4 replays + 3 eager steps
+            torch.cuda.synchronize()
+            got = gpu_fields(b, prob)
+            for k in ref:
+                assert np.array_equal(ref[k], got[k]), (prec, r, k)
+            assert np.array_equal(b.read_energy(0, 23), e_ref), (prec, r)
+        b.close()
+
+
 # ----------------------------------------------------------- config 4
 def _single(problem, b):
     """Block b of a batched problem as a problem of its own."""
