@@ -42,7 +42,7 @@ def plain(block):
             and all(f in ("pec", "pmc") for f in block["faces"]))
 
 
-def algorithmic_bytes(problem, elem, fused=True):
+def algorithmic_bytes(problem, elem, fused=False):
     """Bytes each launch group must move per step: every node read once and
     written once per update, the other field read once (two passes) or both
     fields read and written once (one pass), per-cell materials read once.
@@ -80,11 +80,13 @@ def traffic_entry(kernel):
     return t.get("kernels", {}).get(kernel)
 
 
-def run_gpu(problem, prec, steps, warmup, profile_kernels):
+def run_gpu(problem, prec, steps, warmup, profile_kernels, fused=False):
     import torch
     from paper_2206_00638_amd import build_problem
     stream = torch.cuda.Stream()
     ctx = build_problem(problem, prec=prec, stream=stream, history=max(steps + warmup + 8, 64))
+    if fused:
+        ctx.set_fused(True, 16)
     ctx.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -317,6 +319,13 @@ def main():
         out["fp64"] = {"value": cells * args.steps / f64["wall_s"] / 1e6, "unit": "Mcell-updates/s",
                        "ms_per_step": f64["wall_s"] * 1e3 / args.steps, "kernels_ms": list(f64["kernel_ms"]),
                        "step_hbm_gbs_algorithmic": (hb8 + eb8 + fb8) / (f64["wall_s"] / args.steps) / 1e9}
+    if not args.no_fp64:
+        one = run_gpu(prob, "f32", args.steps, args.warmup, profile_kernels=True, fused=True)
+        fb1 = algorithmic_bytes(prob, 4, fused=True)[2]
+        out["one_pass"] = {"value": cells * args.steps / one["wall_s"] / 1e6, "unit": "Mcell-updates/s",
+                           "ms_per_step": one["wall_s"] * 1e3 / args.steps, "kernel_ms": one["kernel_ms"][2],
+                           "algorithmic_bytes_per_launch": fb1,
+                           "achieved_gbs": fb1 / (one["kernel_ms"][2] * 1e-3) / 1e9}
     if not args.no_batched:
         out["batched"] = batched(args.steps, max(args.warmup, 100))
     if not args.no_subgrid:

@@ -87,7 +87,10 @@ struct sbp_ctx {
   long long nstep = 0;
   long history = 0;
   // device buffers
-  void* pool = nullptr;   // step n reads pool (n even) or pool2 (n odd) and writes the other
+  // field pools: with the one-pass step, step n reads pool (n even) or pool2
+  // (n odd) and writes the other; the two-pass step updates in place
+  // (pool2 == pool), which keeps mid-size states within the last-level cache
+  void* pool = nullptr;
   void* pool2 = nullptr;
   size_t pool_elems = 0;
   void* mat[3] = {nullptr, nullptr, nullptr};
@@ -944,7 +947,7 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->pool_elems = foff;
   c->ncells = coff;
   c->pool = dalloc(c, foff * elem_size(c));
-  c->pool2 = dalloc(c, foff * elem_size(c));
+  c->pool2 = c->fused ? dalloc(c, foff * elem_size(c)) : c->pool;
   c->d_blocks = (DevBlock*)dalloc(c, c->hblocks.size() * sizeof(DevBlock));
   c->d_src = (Source*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(Source));
   c->d_srcval = (double*)dalloc(c, std::max<size_t>(dsrc.size(), 1) * sizeof(double));
@@ -958,7 +961,7 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   if (!c->pool || !c->pool2 || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
     return fail(c, SBP_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->pool2, 0, foff * elem_size(c), c->stream));
+  if (c->pool2 != c->pool) HIPCHK(c, hipMemsetAsync(c->pool2, 0, foff * elem_size(c), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_energy, 0, (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_probes, 0, std::max<size_t>(dprb.size(), 1) * (size_t)history * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
@@ -1074,9 +1077,24 @@ sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
 sbp_status sbp_set_fused(sbp_ctx* c, int enable, int planes) {
   if (!c) return SBP_EINVAL;
   if (planes < 4 || planes > 4096) return fail(c, SBP_EINVAL, "planes per one-pass tile must be 4..4096");
-  c->fused = enable ? 1 : 0;
   c->fz = planes;
   drop_graph(c);
+  if (c->finalized) {
+    const size_t pb = c->pool_elems * elem_size(c);
+    HIPCHK(c, hipSetDevice(c->device));
+    if (enable && c->pool2 == c->pool) {  // second pool, holding the state too
+      void* p2 = dalloc(c, pb);
+      if (!p2) return fail(c, SBP_ENOMEM, "second field pool allocation failed");
+      HIPCHK(c, hipMemcpyAsync(p2, c->pool, pb, hipMemcpyDeviceToDevice, c->stream));
+      c->pool2 = p2;
+    } else if (!enable && c->pool2 != c->pool) {  // back to one pool
+      if (c->nstep & 1) HIPCHK(c, hipMemcpyAsync(c->pool, c->pool2, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      dfree(c, c->pool2);
+      c->pool2 = c->pool;
+    }
+  }
+  c->fused = enable ? 1 : 0;
   if (c->finalized) return build_tiles(c);
   return SBP_OK;
 }
@@ -1399,7 +1417,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   char* seg = (char*)take((K + 1) * pb);
   char* fin = (char*)take(sb);
   void* apool = take(pb);
-  void* apool2 = take(pb);
+  void* apool2 = c->pool2 != c->pool ? take(pb) : apool;
   double* aface = (double*)take(c->face_elems * sizeof(double));
   StepState* ast = (StepState*)take(sizeof(StepState));
   double* ering = (double*)take(2 * sizeof(double));
@@ -1416,7 +1434,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   sbp_status st = SBP_OK;
   auto run = [&]() -> sbp_status {
     HIPCHK(c, hipMemsetAsync(apool, 0, pb, c->stream));
-    HIPCHK(c, hipMemsetAsync(apool2, 0, pb, c->stream));
+    if (apool2 != apool) HIPCHK(c, hipMemsetAsync(apool2, 0, pb, c->stream));
     HIPCHK(c, hipMemsetAsync(aface, 0, c->face_elems * sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(ast, 0, sizeof(StepState), c->stream));
     HIPCHK(c, hipMemsetAsync(G, 0, gsz * sizeof(double), c->stream));
