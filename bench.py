@@ -86,7 +86,7 @@ def run_gpu(problem, prec, steps, warmup, profile_kernels, fused=False):
     stream = torch.cuda.Stream()
     ctx = build_problem(problem, prec=prec, stream=stream, history=max(steps + warmup + 8, 64))
     if fused:
-        ctx.set_fused(True, 16)
+        ctx.set_fused(True, 8)
     ctx.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -162,7 +162,7 @@ sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
 /* Selects how plain blocks (PEC / PMC faces, no conductivity, no per-cell
  * permeability, no interfaces) are stepped: enable != 0 runs both half steps
  * in one pass over the fields (each value read and written once per step),
- * on windows of 64 x 8 node columns walking `planes` planes (4..4096);
+ * on windows of 32 x 8 node columns walking `planes` planes (4..4096);
  * enable = 0 (the default) uses the H pass and the E pass.  Other blocks
  * always take the two passes.  Both give the same fields up to rounding. */
 sbp_status sbp_set_fused(sbp_ctx *ctx, int enable, int planes);

@@ -105,7 +105,7 @@ struct sbp_ctx {
   int ntiles = 0;
   int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
-  int fused = 0, fz = 16;  // two passes by default: measured faster on the 256^3 workload
+  int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
   FTile* d_ftiles = nullptr;
   FTile* d_ftiles_bare = nullptr;
   size_t ftiles_cap = 0;

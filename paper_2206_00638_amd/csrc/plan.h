@@ -78,12 +78,12 @@ struct Tile {
   int block, q0, z0, pad;
 };
 
-// A tile of the one-pass step: a 64 x 8 window of node columns of one
+// A tile of the one-pass step: a 32 x 8 window of node columns of one
 // block's xy plane starting at (i0, j0), on which H^{n+1/2} is formed, and
 // its owned part [olx, ohx] x [oly, ohy] x planes [z0, z1], on which H and E
 // are written (the unowned columns supply neighbour values of H only).
 // flags: bit 0 = a source, bit 1 = a probe lies in the owned part.
-constexpr int FX = 64, FY = 8;
+constexpr int FX = 32, FY = 8;
 struct FTile {
   int block, i0, j0, olx, ohx, oly, ohy, z0, z1, flags;
 };

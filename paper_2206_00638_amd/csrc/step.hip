@@ -687,7 +687,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
 
 // ------------------------------------------------------------ one-pass step
 // For plain blocks (PEC / PMC faces, per-cell or uniform permittivity) both
-// half steps run in one pass: a workgroup takes a 64 x 8 window of node
+// half steps run in one pass: a workgroup takes a 32 x 8 window of node
 // columns and walks up through the planes.  At plane kh it forms H^{n+1/2}
 // on the whole window (the same rows as k_h_update) and keeps it in LDS; E
 // at plane kh-2 then takes its in-plane neighbours of H^{n+1/2} from LDS and
@@ -717,7 +717,7 @@ __device__ __forceinline__ T pick4(int d, T m1, T z0, T p1, T p2) {
 }
 
 template <typename T, bool HAS_EPS>
-__global__ __launch_bounds__(512) void k_fused(KArgs a) {
+__global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
   __shared__ T hs[4][3][FY][FX];  // H^{n+1/2} of the last four planes: [plane & 3][comp][row][column]
   double eacc = 0.0;
   const long long nstep = a.st->step;

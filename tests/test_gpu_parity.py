@@ -281,10 +281,11 @@ def test_graph_replay_bitwise(sbp):
 
 
 # -------------------------------------------------------- one-pass step
-def _plain_problem(seed, n=(126, 13, 41), faces=("pec", "pmc", "pec", "pmc", "pmc", "pec")):
+def _plain_problem(seed, n=(123, 13, 41), faces=("pec", "pmc", "pec", "pmc", "pmc", "pec")):
     """A plain block (PEC / PMC faces, per-cell eps_r) whose sizes make the
-    one-pass windows shift back at the far x and y faces (126 + 2 nodes: last
-    window owns from n-1; 13 + 2 nodes: likewise in y)."""
+    one-pass windows (32 x 8 columns, 31 x 7 owned) shift back at the far x
+    and y faces: 123 + 2 = 4 * 31 + 1 nodes and 13 + 2 = 2 * 7 + 1 nodes, so
+    the last window owns from n-1."""
     rng = np.random.default_rng(seed)
     shape = (n[2], n[1], n[0])
     b = block(n, (1e-3, 1.2e-3, 0.9e-3), faces, eps_r=rng.uniform(1, 4, shape))
@@ -358,6 +359,38 @@ def test_one_pass_graph_and_restore_bitwise(sbp):
                 assert np.array_equal(ref[k], got[k]), (prec, r, k)
             assert np.array_equal(b.read_energy(0, 23), e_ref), (prec, r)
         b.close()
+
+
+# -------------------------------------------------------- edge sizes
+@pytest.mark.parametrize("n", [(4, 4, 4), (4, 5, 6), (7, 4, 5), (65, 9, 4)])
+def test_smallest_blocks(sbp, n):
+    """Blocks at the four-cell minimum along some axis, where the closure rows
+    of both faces meet (no interior row), with per-cell materials and mixed
+    faces; both step paths for the plain variant."""
+    from oracle import loops
+    rng = np.random.default_rng(sum(n))
+    shape = (n[2], n[1], n[0])
+    for plain_case in (False, True):
+        if plain_case:
+            faces = ("pec", "pmc", "pmc", "pec", "pec", "pmc")
+            b = block(n, (1e-3, 0.8e-3, 1.3e-3), faces, eps_r=rng.uniform(1, 4, shape))
+        else:
+            faces = ("pmc", "abc", "pec", "abc", "pmc", "pec")
+            b = block(n, (1e-3, 0.8e-3, 1.3e-3), faces, eps_r=rng.uniform(1, 4, shape),
+                      mu_r=rng.uniform(1, 2, shape), sigma=rng.uniform(0, 0.2, shape))
+        prob = {"blocks": [b], "interfaces": [], "cfl": 0.9, "sources": [],
+                "probes": [{"block": 0, "comp": "Ex", "node": (0, 0, 0)},
+                           {"block": 0, "comp": "Hz", "node": (n[0] + 1, n[1] + 1, n[2])}]}
+        init = random_fields(prob, 9)
+        steps = 25
+        ref = loops.run_block(prob, steps=steps, init={c: init[(0, c)] for c in COMPS})
+        ref_f = {(0, c): ref["fields"][c] for c in COMPS}
+        for fused in ((False, True) if plain_case else (False,)):
+            got = _run_ctx(sbp, prob, "f64", steps, init, fused, 4)
+            err = field_errors(got["fields"], ref_f, FLOOR["f64"])
+            assert max(err.values()) <= TOL["f64"], (n, plain_case, fused, err)
+            assert rel_l2(got["probes"], ref["probes"]) <= TOL["f64"]
+            assert rel_l2(got["energy"], ref["energy"]) <= TOL["f64"]
 
 
 # ----------------------------------------------------------- config 4
