@@ -67,8 +67,10 @@ sbp_status sbp_create(sbp_ctx **out, sbp_prec prec, void *hip_stream,
                       sbp_alloc_fn alloc, sbp_free_fn free_fn, void *user);
 
 /* Adds a block of nx*ny*nz cells (each >= 4: the boundary closures of the
- * Appendix need four cells; the node box (nx+2)(ny+2)(nz+2) must stay below
- * 2^31 - 2^20 nodes) of size dx*dy*dz metres at origin (x0,y0,z0).
+ * Appendix need four cells; one component array, the node box
+ * (nx+2)(ny+2)(nz+2) with its xy planes padded to 64 nodes, must stay below
+ * 4 GiB: about 1000^3 cells in fp32, 800^3 in fp64) of size dx*dy*dz metres
+ * at origin (x0,y0,z0).
  * eps_r, mu_r, sigma (S/m): per-cell host arrays of nx*ny*nz doubles, i
  * fastest, or NULL for 1, 1, 0.  The node value is the mean over the cells
  * whose closed box contains the node.  All faces start as PEC. */

@@ -744,8 +744,14 @@ sbp_status sbp_add_block(sbp_ctx* c, int nx, int ny, int nz, double dx, double d
   if (nx < 4 || ny < 4 || nz < 4)
     return fail(c, SBP_EINVAL, "a block needs at least 4 cells per axis (Appendix closures)");
   if (!(dx > 0 && dy > 0 && dz > 0)) return fail(c, SBP_EINVAL, "cell sizes must be positive");
-  if ((long long)(nx + 2) * (ny + 2) * (nz + 2) > (1LL << 31) - (1LL << 20))
-    return fail(c, SBP_EINVAL, "a block's node box (nx+2)(ny+2)(nz+2) must stay below 2^31 nodes");
+  {
+    // each component array (node box, planes padded to 64 nodes) below 4 GiB:
+    // the step kernels address it with 32-bit byte offsets
+    const long long sxy = ((long long)(nx + 2) * (ny + 2) + 63) / 64 * 64;
+    const long long bytes = sxy * (nz + 2) * (c->prec == SBP_FP64 ? 8 : 4);
+    if (bytes >= (1LL << 32) - (1LL << 20))
+      return fail(c, SBP_EINVAL, "a block's component array (node box (nx+2)(ny+2)(nz+2)) must stay below 4 GiB");
+  }
   HostBlock b;
   b.n[0] = nx; b.n[1] = ny; b.n[2] = nz;
   b.h[0] = dx; b.h[1] = dy; b.h[2] = dz;

@@ -211,6 +211,19 @@ __device__ __forceinline__ const SBP_CONST X* as_const(const X* p) {
   return (const SBP_CONST X*)p;
 }
 
+// Element `idx` of a component array addressed as the (wave-uniform) array
+// base plus a 32-bit byte offset, so that an access costs one vector offset
+// instead of a 64-bit address.  Component arrays stay below 4 GiB (checked
+// when a block is added).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, unsigned idx) {
+  return *(const T*)((const char*)base + (size_t)(idx * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned idx, T v) {
+  *(T*)((char*)base + (size_t)(idx * (unsigned)sizeof(T))) = v;
+}
+
 // Per-tile copy of the block constants the node updates use (registers;
 // the closure tables stay in the descriptor, read by boundary rows only).
 template <typename T>
@@ -248,17 +261,17 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
                                        const T* __restrict__ Ey, const T* __restrict__ Ez,
                                        const T* __restrict__ Hx, const T* __restrict__ Hy,
                                        const T* __restrict__ Hz, int i, int j, long long o) {
-  const long long oy = j > 0 ? c.sx : 0, ox = i > 0 ? 1 : 0;
-  v.ex = Ex[o];
-  v.ey = Ey[o];
-  v.ez = Ez[o];
-  v.hx = Hx[o];
-  v.hy = Hy[o];
-  v.hz = Hz[o];
-  v.ez_y = Ez[o - oy];
-  v.ex_y = Ex[o - oy];
-  v.ez_x = Ez[o - ox];
-  v.ey_x = Ey[o - ox];
+  const unsigned u = (unsigned)o, uy = u - (j > 0 ? (unsigned)c.sx : 0u), ux = u - (i > 0 ? 1u : 0u);
+  v.ex = ld32(Ex, u);
+  v.ey = ld32(Ey, u);
+  v.ez = ld32(Ez, u);
+  v.hx = ld32(Hx, u);
+  v.hy = ld32(Hy, u);
+  v.hz = ld32(Hz, u);
+  v.ez_y = ld32(Ez, uy);
+  v.ex_y = ld32(Ex, uy);
+  v.ez_x = ld32(Ez, ux);
+  v.ey_x = ld32(Ey, ux);
 }
 
 // H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
@@ -317,9 +330,9 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
   const T nhy = hy + dby * (dxEz - dzEx);
   const T nhz = hz + dbz * (dyEx - dxEy);
   const bool vx = i <= nx, vy = j <= ny, vz = k <= nz;
-  if (store && vx) Hx[o] = nhx;
-  if (store && vy) Hy[o] = nhy;
-  if (store && vz) Hz[o] = nhz;
+  if (store && vx) st32(Hx, (unsigned)o, nhx);
+  if (store && vy) st32(Hy, (unsigned)o, nhy);
+  if (store && vz) st32(Hz, (unsigned)o, nhz);
   onx = nhx;
   ony = nhy;
   onz = nhz;
@@ -451,8 +464,9 @@ struct EIn {
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
 };
 
-// Cell offsets of a node column (i, j): cell A (i-1, j-1) clamped, and the
-// offsets of B (+x) and C (+y); plane P of cells starts at P * nx * ny.
+// Cell offsets of a node column (i, j) within the block's cells: cell A
+// (i-1, j-1) clamped, and the offsets of B (+x) and C (+y); plane P of cells
+// starts at P * nx * ny.
 struct ColCells {
   long long A, cp;
   int dx, dy;
@@ -462,7 +476,7 @@ __device__ __forceinline__ ColCells col_cells(const BC<T>& c, int i, int j) {
   const int nx = c.nx, ny = c.ny;
   const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
   const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
-  return ColCells{c.coff + ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
+  return ColCells{ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
 }
 
 template <typename T, bool HAS_EPS>
@@ -471,23 +485,25 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
                                        const T* __restrict__ Hz, const T* __restrict__ Hx,
                                        const T* __restrict__ Hy, const T* __restrict__ ME, const ColCells& q,
                                        int i, int j, int k, long long o) {
-  const long long pz = k <= c.nz ? c.sxy : 0, py = j <= c.ny ? c.sx : 0, px = i <= c.nx ? 1 : 0;
-  v.ex = Ex[o];
-  v.ey = Ey[o];
-  v.ez = Ez[o];
-  v.hz = Hz[o];
-  v.hy_z = Hy[o + pz];
-  v.hx_z = Hx[o + pz];
-  v.hz_y = Hz[o + py];
-  v.hx_y = Hx[o + py];
-  v.hz_x = Hz[o + px];
-  v.hy_x = Hy[o + px];
-  if (HAS_EPS) {
-    const T* p1 = ME + q.A + q.cp * clampi(k, 0, c.nz - 1);
-    v.e1a = p1[0];
-    v.e1b = p1[q.dx];
-    v.e1c = p1[q.dy];
-    v.e1d = p1[q.dx + q.dy];
+  const unsigned u = (unsigned)o;
+  const unsigned uz = u + (k <= c.nz ? (unsigned)c.sxy : 0u), uy = u + (j <= c.ny ? (unsigned)c.sx : 0u),
+                 ux = u + (i <= c.nx ? 1u : 0u);
+  v.ex = ld32(Ex, u);
+  v.ey = ld32(Ey, u);
+  v.ez = ld32(Ez, u);
+  v.hz = ld32(Hz, u);
+  v.hy_z = ld32(Hy, uz);
+  v.hx_z = ld32(Hx, uz);
+  v.hz_y = ld32(Hz, uy);
+  v.hx_y = ld32(Hx, uy);
+  v.hz_x = ld32(Hz, ux);
+  v.hy_x = ld32(Hy, ux);
+  if (HAS_EPS) {  // ME: the block's cells; q.A relative to them
+    const unsigned p1 = (unsigned)(q.A + q.cp * clampi(k, 0, c.nz - 1));
+    v.e1a = ld32(ME, p1);
+    v.e1b = ld32(ME, p1 + (unsigned)q.dx);
+    v.e1c = ld32(ME, p1 + (unsigned)q.dy);
+    v.e1d = ld32(ME, p1 + (unsigned)(q.dx + q.dy));
   }
 }
 
@@ -597,9 +613,9 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
   const T nez = caz * ez + cbz * (cz + jz);
   const bool vz = k <= nz;
   const bool vEx = j <= ny && vz, vEy = i <= nx && vz, vEz = i <= nx && j <= ny;
-  if (vEx) Ex[o] = nex;
-  if (vEy) Ey[o] = ney;
-  if (vEz) Ez[o] = nez;
+  if (vEx) st32(Ex, (unsigned)o, nex);
+  if (vEy) st32(Ey, (unsigned)o, ney);
+  if (vEz) st32(Ez, (unsigned)o, nez);
   onx = nex;
   ony = ney;
   onz = nez;
@@ -632,7 +648,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const T* base = (const T*)pin + Bc.foff;  // E^n
     T* bout = (T*)pout + Bc.foff;             // H^{n+1/2} (read), E^{n+1} (written)
     const long long csz = Bc.csz;
-    const T* ME = (const T*)a.mat_eps;
+    const T* ME = HAS_EPS ? (const T*)a.mat_eps + Bc.coff : nullptr;  // the block's permittivity cells
     const T* MS = (GEN && (c.mat & MAT_SIG)) ? (const T*)a.mat_sig : nullptr;
     const int q = tq0 + (int)threadIdx.x;
     if (q >= (int)c.sx * (c.ny + 2)) continue;
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
     T* HxO = bout + 3 * csz;
     T* HyO = bout + 4 * csz;
     T* HzO = bout + 5 * csz;
-    const T* ME = (const T*)a.mat_eps;
+    const T* ME = HAS_EPS ? (const T*)a.mat_eps + Bc.coff : nullptr;  // the block's permittivity cells
     const int i = ft.i0 + lane, j = ft.j0 + w;
     const bool col = i < sx && j < ny + 2;
     const bool own = col && i >= ft.olx && i <= ft.ohx && j >= ft.oly && j <= ft.ohy;
