@@ -158,6 +158,30 @@ def test_config3_reduced(sbp):
         assert rel_l2(g["probes"], r["probes"]) < TOL[prec]
 
 
+def test_config3_full_size_energy_and_blocks(sbp):
+    """The 27-block 1:2 subgrid workload at full size (7.85 M cells, fp32):
+    W^n is non-increasing once the source has ended (the absorbing faces and
+    the lossy box only remove energy, the interfaces conserve it), and a
+    repeated run gives the same bits (fields and energies)."""
+    from sbp_inputs import make_config
+    prob = make_config(3)
+    steps = 900
+    ctx = sbp.build_problem(prob, prec="f32", history=steps + 8)
+    ctx.step(steps)
+    w = ctx.read_energy(0, steps)
+    f1 = ctx.read_field(prob["fine_block"], "Ez")
+    ctx.close()
+    assert np.all(np.isfinite(w)) and w.max() > 0
+    tail = w[600:]  # source (t0 = tw = 0.2 ns, dt = 0.87 ps) below 1e-12 of its peak
+    assert np.all(tail[1:] <= tail[:-1] * (1 + 1e-6)), np.max(tail[1:] / tail[:-1])
+    assert tail[-1] < tail[0]
+    ctx = sbp.build_problem(prob, prec="f32", history=steps + 8)
+    ctx.step(steps)
+    assert np.array_equal(ctx.read_field(prob["fine_block"], "Ez"), f1)
+    assert np.array_equal(ctx.read_energy(0, steps), w)
+    ctx.close()
+
+
 # ------------------------------------------------------------- config 2
 def test_config2_reduced_fp32(sbp, oracle_lib):
     from sbp_inputs import make_config
