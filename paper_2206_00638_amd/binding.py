@@ -114,7 +114,12 @@ class _TorchMemory:
             return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
 
         def _free(p, _user):
-            self.torch.cuda.caching_allocator_delete(p)
+            try:
+                self.torch.cuda.caching_allocator_delete(p)
+            except (AttributeError, TypeError):
+                # a context destroyed during interpreter shutdown, after torch
+                # has been torn down: the device memory goes with the process
+                pass
 
         self.alloc = ALLOC_FN(_alloc)
         self.free = FREE_FN(_free)
