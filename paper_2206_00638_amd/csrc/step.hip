@@ -131,8 +131,8 @@ struct TRow {
   T c0, c1, c2, cn;
 };
 
-template <typename T>
-__device__ __forceinline__ TRow<T> row_of(const DevBlock& B, int axis, int r, bool minus) {
+template <typename T, typename DB>
+__device__ __forceinline__ TRow<T> row_of(const DB& B, int axis, int r, bool minus) {
   TRow<T> R;
   const int n = B.n[axis];
   R.nbr = 0;
@@ -147,7 +147,7 @@ __device__ __forceinline__ TRow<T> row_of(const DevBlock& B, int axis, int r, bo
     R.s = -2;
     R.c0 = R.c1 = R.c2 = T(0);
   } else {
-    const Row& X = minus ? B.dm[axis][r < 3 ? r : r - (n - 1) + 3] : B.dp[axis][r < 2 ? r : r - (n - 1) + 2];
+    const auto& X = minus ? B.dm[axis][r < 3 ? r : r - (n - 1) + 3] : B.dp[axis][r < 2 ? r : r - (n - 1) + 2];
     R.s = X.s;
     R.c0 = (T)X.c[0];
     R.c1 = (T)X.c[1];
@@ -279,7 +279,8 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 // differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
 template <typename T, bool GEN>
-__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const HIn<T>& v,
+__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
+                                    const TRow<T>& rx, const TRow<T>& ry, const BC<T>& c, const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
                                     T* __restrict__ Hz, const T* __restrict__ M, int i, int j, int k,
@@ -293,19 +294,17 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const BC<
   T dyEz = (v.ez - v.ez_y) * ihy, dyEx = (v.ex - v.ex_y) * ihy;
   T dxEz = (v.ez - v.ez_x) * ihx, dxEy = (v.ey - v.ey_x) * ihx;
   if (!zin) {
-    const TRow<T> rz = row_of<T>(B, 2, k, true);
+    const TRow<T> rz = row_of<T>(Bc, 2, k, true);
     const int f = k < 3 ? 4 : 5;
     dzEy = drow<T, GEN>(a, B, Ey, o, sxy, rz, f, 0, 1, i, j, k);
     dzEx = drow<T, GEN>(a, B, Ex, o, sxy, rz, f, 0, 0, i, j, k);
   }
   if (!yin) {
-    const TRow<T> ry = row_of<T>(B, 1, j, true);
     const int f = j < 3 ? 2 : 3;
     dyEz = drow<T, GEN>(a, B, Ez, o, sx, ry, f, 0, 1, i, j, k);
     dyEx = drow<T, GEN>(a, B, Ex, o, sx, ry, f, 0, 0, i, j, k);
   }
   if (!xin) {
-    const TRow<T> rx = row_of<T>(B, 0, i, true);
     const int f = i < 3 ? 0 : 1;
     dxEz = drow<T, GEN>(a, B, Ez, o, 1, rx, f, 0, 1, i, j, k);
     dxEy = drow<T, GEN>(a, B, Ey, o, 1, rx, f, 0, 0, i, j, k);
@@ -368,6 +367,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const int q = tq0 + (int)threadIdx.x;
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
+    const TRow<T> rx = row_of<T>(B, 0, i, true), ry = row_of<T>(B, 1, j, true);  // D- rows of the column
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1, v2);
+      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1,
+                                   v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -513,7 +514,8 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 // 2/(eta h) on tangential face nodes joins the semi-implicit loss.  Returns
 // the node's 4 eps_r (w/h^3) (E^n)^2 (the E part of W^n).
 template <typename T, bool HAS_EPS, bool GEN>
-__device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<T>& c, const EIn<T>& v,
+__device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
+                                    const TRow<T>& rx, const TRow<T>& ry, const BC<T>& c, const EIn<T>& v,
                                     T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
                                     const T* __restrict__ Hx, const T* __restrict__ Hy,
                                     const T* __restrict__ Hz, const T* __restrict__ MS, int i, int j, int k,
@@ -529,7 +531,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
   T dxHz = (v.hz_x - hz) * ihx, dxHy = (v.hy_x - hy) * ihx;
   if (!zin) {
     if (k <= nz) {
-      const TRow<T> rz = row_of<T>(B, 2, k, false);
+      const TRow<T> rz = row_of<T>(Bc, 2, k, false);
       const int f = k < 2 ? 4 : 5;
       dzHy = drow<T, GEN>(a, B, Hy, o, sxy, rz, f, 1, 1, i, j, k);
       dzHx = drow<T, GEN>(a, B, Hx, o, sxy, rz, f, 1, 0, i, j, k);
@@ -538,13 +540,11 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const BC<
     }
   }
   if (!yin) {
-    const TRow<T> ry = row_of<T>(B, 1, j, false);
     const int f = j < 2 ? 2 : 3;
     dyHz = drow<T, GEN>(a, B, Hz, o, sx, ry, f, 1, 1, i, j, k);
     dyHx = drow<T, GEN>(a, B, Hx, o, sx, ry, f, 1, 0, i, j, k);
   }
   if (!xin) {
-    const TRow<T> rx = row_of<T>(B, 0, i, false);
     const int f = i < 2 ? 0 : 1;
     dxHz = drow<T, GEN>(a, B, Hz, o, 1, rx, f, 1, 1, i, j, k);
     dxHy = drow<T, GEN>(a, B, Hy, o, 1, rx, f, 1, 0, i, j, k);
@@ -653,6 +653,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const int q = tq0 + (int)threadIdx.x;
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
+    const TRow<T> rx = row_of<T>(B, 0, i, false), ry = row_of<T>(B, 1, j, false);  // D+ rows of the column
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -691,8 +692,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o, jx, jy, jz,
-                                            v0, v1, v2);
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o,
+                                            jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -772,6 +773,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
     const bool own = col && i >= ft.olx && i <= ft.ohx && j >= ft.oly && j <= ft.ohy;
     const long long oc = col ? (long long)i + (long long)sx * j : 0;
     const ColCells cc = col_cells(c, col ? i : 0, col ? j : 0);
+    const TRow<T> hrx = row_of<T>(B, 0, col ? i : 0, true), hry = row_of<T>(B, 1, col ? j : 0, true);
     const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
     // own column: Hx, Hy of H^{n+1/2} at planes kh-3 .. kh, E^n at kh-2, kh-1
     T hx3 = T(0), hx2 = T(0), hx1 = T(0), hx0 = T(0), hy3 = T(0), hy2 = T(0), hy1 = T(0), hy0 = T(0);
@@ -813,8 +815,8 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false>(a, B, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o, hown, v0, v1,
-                                      v2);
+        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o,
+                                      hown, v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
           if (tflags & 2) take_probes<T>(a, B, i, j, kh, true, nstep, v0, v1, v2);
