@@ -243,6 +243,24 @@ struct BC {
   }
 };
 
+// Norm weights / h^3 of a node column's three components without the z
+// factor (which the plane supplies), zero for components that do not exist
+// in the column.
+template <typename T>
+struct W3 {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ W3<T> h_col_weights(int nx, int ny, int i, int j) {
+  return W3<T>{i <= nx ? (T)(wp1(nx, i) * wm1(ny, j)) : T(0), j <= ny ? (T)(wm1(nx, i) * wp1(ny, j)) : T(0),
+               (T)(wm1(nx, i) * wm1(ny, j))};
+}
+template <typename T>
+__device__ __forceinline__ W3<T> e_col_weights(int nx, int ny, int i, int j) {
+  return W3<T>{j <= ny ? (T)(wm1(nx, i) * wp1(ny, j)) : T(0), i <= nx ? (T)(wp1(nx, i) * wm1(ny, j)) : T(0),
+               (i <= nx && j <= ny) ? (T)(wp1(nx, i) * wp1(ny, j)) : T(0)};
+}
+
 // ------------------------------------------------------------- H update
 // Field values one H node update reads at interior rows: E and H at the
 // node, E one node back along y and x (offsets kept inside the component
@@ -280,7 +298,8 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
 template <typename T, bool GEN>
 __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
-                                    const TRow<T>& rx, const TRow<T>& ry, const BC<T>& c, const HIn<T>& v,
+                                    const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
+                                    const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
                                     T* __restrict__ Hz, const T* __restrict__ M, int i, int j, int k,
@@ -336,10 +355,8 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
   ony = nhy;
   onz = nhz;
   if (xin && yin && zin) return mx * (nhx * hx) + my * (nhy * hy) + mz * (nhz * hz);
-  const T wx = vx ? (T)(wp1(nx, i) * wm1(ny, j) * wm1(nz, k)) : T(0);
-  const T wy = vy ? (T)(wm1(nx, i) * wp1(ny, j) * wm1(nz, k)) : T(0);
-  const T wz = vz ? (T)(wm1(nx, i) * wm1(ny, j) * wp1(nz, k)) : T(0);
-  return wx * mx * (nhx * hx) + wy * my * (nhy * hy) + wz * mz * (nhz * hz);
+  const T kxy = (T)wm1(nz, k), kz = vz ? (T)wp1(nz, k) : T(0);
+  return (lw.x * kxy) * mx * (nhx * hx) + (lw.y * kxy) * my * (nhy * hy) + (lw.z * kz) * mz * (nhz * hz);
 }
 
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
@@ -368,6 +385,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, true), ry = row_of<T>(B, 1, j, true);  // D- rows of the column
+    const W3<T> lw = h_col_weights<T>(c.nx, c.ny, i, j);
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1,
+      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1,
                                    v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
@@ -515,7 +533,8 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 // the node's 4 eps_r (w/h^3) (E^n)^2 (the E part of W^n).
 template <typename T, bool HAS_EPS, bool GEN>
 __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
-                                    const TRow<T>& rx, const TRow<T>& ry, const BC<T>& c, const EIn<T>& v,
+                                    const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
+                                    const EIn<T>& v,
                                     T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
                                     const T* __restrict__ Hx, const T* __restrict__ Hy,
                                     const T* __restrict__ Hz, const T* __restrict__ MS, int i, int j, int k,
@@ -620,10 +639,8 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   ony = ney;
   onz = nez;
   // norm weights / h: 1 inside, Appendix P+ / P- on the boundary rows
-  const T wx = vEx ? (T)(wm1(nx, i) * wp1(ny, j) * wp1(nz, k)) : T(0);
-  const T wy = vEy ? (T)(wp1(nx, i) * wm1(ny, j) * wp1(nz, k)) : T(0);
-  const T wz = vEz ? (T)(wp1(nx, i) * wp1(ny, j) * wm1(nz, k)) : T(0);
-  return wx * mx * (ex * ex) + wy * my * (ey * ey) + wz * mz * (ez * ez);
+  const T kxy = vz ? (T)wp1(nz, k) : T(0), kz = (T)wm1(nz, k);
+  return (lw.x * kxy) * mx * (ex * ex) + (lw.y * kxy) * my * (ey * ey) + (lw.z * kz) * mz * (ez * ez);
 }
 
 // E step over the tiles [t0, t1) of the tile list (one kind of block), one
@@ -654,6 +671,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     if (q >= (int)c.sx * (c.ny + 2)) continue;
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, false), ry = row_of<T>(B, 1, j, false);  // D+ rows of the column
+    const W3<T> lw = e_col_weights<T>(c.nx, c.ny, i, j);
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -692,7 +710,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o,
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o,
                                             jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
@@ -774,6 +792,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
     const long long oc = col ? (long long)i + (long long)sx * j : 0;
     const ColCells cc = col_cells(c, col ? i : 0, col ? j : 0);
     const TRow<T> hrx = row_of<T>(B, 0, col ? i : 0, true), hry = row_of<T>(B, 1, col ? j : 0, true);
+    const W3<T> hlw = h_col_weights<T>(nx, ny, col ? i : 0, col ? j : 0);
     const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
     // own column: Hx, Hy of H^{n+1/2} at planes kh-3 .. kh, E^n at kh-2, kh-1
     T hx3 = T(0), hx2 = T(0), hx1 = T(0), hx0 = T(0), hy3 = T(0), hy2 = T(0), hy1 = T(0), hy0 = T(0);
@@ -815,7 +834,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o,
+        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o,
                                       hown, v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
