@@ -1057,12 +1057,16 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
   for (double x : e) if (!(x > 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "eps_r must be positive");
   for (double x : m) if (!(x > 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "mu_r must be positive");
   for (double x : s) if (!(x >= 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "sigma must be >= 0");
+  const int kind_before = block_kind(b);
   b.eps.swap(e);
   b.mu.swap(m);
   b.sig.swap(s);
   void* old[3] = {c->mat[0], c->mat[1], c->mat[2]};
   sbp_status st = upload_materials(c);
   if (st != SBP_OK) return st;
+  // a block whose set of per-cell materials changed takes other kernels:
+  // rebuild the tile lists (this also drops a captured graph)
+  if (block_kind(b) != kind_before) return build_tiles(c);
   if (old[0] != c->mat[0] || old[1] != c->mat[1] || old[2] != c->mat[2]) drop_graph(c);
   return SBP_OK;
 }

@@ -516,6 +516,35 @@ def test_config4_full_graph_autotune(sbp):
         assert err["H"] <= 10 * TOL["f32"], (b, err)
 
 
+def test_set_materials_changes_block_kind(sbp):
+    """Materials replaced after finalize, turning a uniform plain block into
+    one with per-cell permittivity and conductivity (other kernels): the run
+    equals one built with those materials from the start."""
+    rng = np.random.default_rng(12)
+    n = (19, 23, 17)
+    shape = (n[2], n[1], n[0])
+    eps, sig = rng.uniform(1, 4, shape), rng.uniform(0, 0.2, shape)
+    faces = ("pec", "pmc", "pec", "pec", "pmc", "pec")
+    plain = {"blocks": [block(n, (1e-3,) * 3, faces)], "interfaces": [], "cfl": 0.9, "sources": [], "probes": []}
+    full = {"blocks": [block(n, (1e-3,) * 3, faces, eps_r=eps, sigma=sig)], "interfaces": [], "cfl": 0.9,
+            "sources": [], "probes": []}
+    init = random_fields(plain, 5)
+    for prec in ("f64", "f32"):
+        a = sbp.build_problem(plain, prec=prec)
+        a.step(1)
+        a.set_materials(0, eps, None, sig)
+        b = sbp.build_problem(full, prec=prec)
+        b.step(1)
+        for ctx in (a, b):
+            write_fields(ctx, init)
+            ctx.step(20)
+        fa, fb = gpu_fields(a, plain), gpu_fields(b, full)
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (prec, k)
+        a.close()
+        b.close()
+
+
 # ---------------------------------------------------------------- errors
 def test_error_statuses(sbp):
     from paper_2206_00638_amd.binding import SBP_EINVAL, SBP_ESTATE, SBP_EUNSTABLE, SBP_ERANGE, Context, SbpError
