@@ -16,9 +16,12 @@
 // p^n = Ca p^{n+1} + Cb (C_e(r^{n+1/2}) + dJ/dE^n / w_E).  The step kernels
 // therefore run the adjoint on a second state; these kernels add the
 // objective's source, accumulate dJ/dCb = sum_n lam_E^{n+1} (E^{n+1} - E^n)/Cb
-// (lossless: Ca = 1), and chain dJ/dCb to the cells through Cb = 4 dt /
+// (lossless: Ca = 1; with lam_E = w_E p / Cb that is (w_E / Cb^2) sum_n
+// p^{n+1} (E^{n+1} - E^n)), and chain dJ/dCb to the cells through Cb = 4 dt /
 // (eps0 S), S the sum of the four (clamped) cells around the node.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "plan.h"
 
@@ -175,38 +178,20 @@ __global__ __launch_bounds__(256) void k_adj_source(void* apool, const void* epo
   }
 }
 
-// G += w_E p (E^{n+1} - E^n) / Cb^2 over the E nodes of the block: dJ/dCb of
-// step n, with p = p^{n+1} in the adjoint state `apool`.
+// S += p^{n+1} (E^{n+1} - E^n) over the block's three E component arrays,
+// flat (n = 3 x the component stride; nodes outside a component's grid are
+// skipped in k_adj_cells).  With w_E and Cb constant in time, dJ/dCb of the
+// node is (w_E / Cb^2) S after the sweep; k_adj_cells applies the factor.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_grad(const void* apool, const void* enew, const void* eold,
-                                                 const DevBlock* blocks, const void* mat_eps, int block,
-                                                 double* G) {
-  const DevBlock& B = blocks[block];
-  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-  const long long sx = B.sx, sxy = B.sxy;
-  const long long plane = sx * (ny + 2);
-  const long long nodes = plane * (nz + 2);
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * nodes;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / nodes);
-    const long long q = t - c * nodes;
-    const int k = (int)(q / plane);
-    const long long rr = q - k * plane;
-    const int j = (int)(rr / sx), i = (int)(rr - j * sx);
-    const bool valid = c == 0 ? (j <= ny && k <= nz) : (c == 1 ? (i <= nx && k <= nz) : (i <= nx && j <= ny));
-    if (!valid) continue;
-    const long long o = i + sx * j + sxy * k;
-    const long long off = B.foff + c * B.csz + o;
-    const double pv = (double)((const T*)apool)[off];
-    const double de = (double)((const T*)enew)[off] - (double)((const T*)eold)[off];
-    const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
-    const double cb = node_cb(B, nc.S);
-    G[c * B.csz + o] += e_weight(B, c, i, j, k) * pv * de / (cb * cb);
-  }
+__global__ __launch_bounds__(256) void k_adj_grad(const T* __restrict__ p, const T* __restrict__ enew,
+                                                 const T* __restrict__ eold, long long n, double* __restrict__ S) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    S[t] += (double)p[t] * ((double)enew[t] - (double)eold[t]);
 }
 
 // dJ/d eps_r per cell: sum over the E nodes of dJ/dCb * dCb/d eps_r(cell),
-// dCb/d eps_r = -Cb / S for each occurrence of the cell among the node's four.
+// with dJ/dCb = (w_E / Cb^2) S from k_adj_grad's sums and dCb/d eps_r =
+// -Cb / S_eps for each occurrence of the cell among the node's four.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, const void* mat_eps, int block,
                                                   const double* G, double* grad) {
@@ -225,10 +210,11 @@ __global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, const
     const bool valid = c == 0 ? (j <= ny && k <= nz) : (c == 1 ? (i <= nx && k <= nz) : (i <= nx && j <= ny));
     if (!valid) continue;
     const long long o = i + sx * j + sxy * k;
-    const double gcb = G[c * B.csz + o];
-    if (gcb == 0.0) continue;
+    const double sum = G[c * B.csz + o];
+    if (sum == 0.0) continue;
     const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
-    const double d = -gcb * node_cb(B, nc.S) / nc.S;
+    const double cb = node_cb(B, nc.S);
+    const double d = -(e_weight(B, c, i, j, k) * sum / cb) / nc.S;
     for (int m = 0; m < 4; ++m) atomicAdd(&grad[nc.cell[m]], d);
   }
 }
@@ -255,9 +241,10 @@ hipError_t launch_adj_source(void* apool, const void* epool, const DevBlock* blo
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_adj_grad(const void* apool, const void* enew, const void* eold, const DevBlock* blocks,
-                           const void* mat_eps, int block, double* G, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_grad<T>, dim3(4096), dim3(256), 0, s, apool, enew, eold, blocks, mat_eps, block, G);
+hipError_t launch_adj_grad(const void* p, const void* enew, const void* eold, long long n, double* S,
+                           hipStream_t s) {
+  const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_adj_grad<T>, dim3(grid), dim3(256), 0, s, (const T*)p, (const T*)enew, (const T*)eold, n, S);
   return hipGetLastError();
 }
 template <typename T>
@@ -275,10 +262,8 @@ template hipError_t launch_adj_source<float>(void*, const void*, const DevBlock*
                                              double, hipStream_t);
 template hipError_t launch_adj_source<double>(void*, const void*, const DevBlock*, const void*, int, const int*,
                                               double, hipStream_t);
-template hipError_t launch_adj_grad<float>(const void*, const void*, const void*, const DevBlock*, const void*, int,
-                                           double*, hipStream_t);
-template hipError_t launch_adj_grad<double>(const void*, const void*, const void*, const DevBlock*, const void*,
-                                            int, double*, hipStream_t);
+template hipError_t launch_adj_grad<float>(const void*, const void*, const void*, long long, double*, hipStream_t);
+template hipError_t launch_adj_grad<double>(const void*, const void*, const void*, long long, double*, hipStream_t);
 template hipError_t launch_adj_cells<float>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
 template hipError_t launch_adj_cells<double>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
 

@@ -30,8 +30,7 @@ hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, d
 template <typename T>
 hipError_t launch_adj_source(void*, const void*, const DevBlock*, const void*, int, const int*, double, hipStream_t);
 template <typename T>
-hipError_t launch_adj_grad(const void*, const void*, const void*, const DevBlock*, const void*, int, double*,
-                           hipStream_t);
+hipError_t launch_adj_grad(const void*, const void*, const void*, long long, double*, hipStream_t);
 template <typename T>
 hipError_t launch_adj_cells(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
 template <typename T>
@@ -578,6 +577,16 @@ sbp_status build_tiles(sbp_ctx* c) {
   return SBP_OK;
 }
 
+// Tile walk of the two-pass kernels: dispatch order when the fields and
+// materials exceed the 256 MB last-level cache (the step streams from HBM),
+// contiguous ranges per XCD when they fit (L2 reuse of neighbouring planes).
+int tile_order(const sbp_ctx* c) {
+  size_t bytes = c->pool_elems * elem_size(c);
+  for (int m = 0; m < 3; ++m)
+    if (c->mat[m]) bytes += c->ncells * elem_size(c);
+  return bytes > (size_t(256) << 20) ? 0 : 1;
+}
+
 KArgs kargs(sbp_ctx* c) {
   KArgs a;
   a.blocks = c->d_blocks;
@@ -585,7 +594,7 @@ KArgs kargs(sbp_ctx* c) {
   a.ftiles = c->d_ftiles;
   a.ntiles = c->ntiles;
   a.cz = c->cz;
-  a.pad_ = 0;
+  a.order = tile_order(c);
   a.pool = c->pool;
   a.pool2 = c->pool2;
   a.mat_eps = c->mat[0];
@@ -1448,6 +1457,8 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     HIPCHK(c, hipMemsetAsync(aface, 0, c->face_elems * sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(ast, 0, sizeof(StepState), c->stream));
     HIPCHK(c, hipMemsetAsync(G, 0, gsz * sizeof(double), c->stream));
+    // the step kernels write valid nodes only: the segment's other nodes stay zero
+    HIPCHK(c, hipMemsetAsync(seg, 0, (K + 1) * pb, c->stream));
     HIPCHK(c, hipMemsetAsync(Jd, 0, sizeof(double), c->stream));
     HIPCHK(c, hipMemsetAsync(grad_eps_dev, 0, ncell * sizeof(double), c->stream));
     // forward: N steps from the current state n0, checkpoints every K steps, J
@@ -1491,22 +1502,28 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     for (long sgi = nck - 1; sgi >= 0; --sgi) {
       const long a = sgi * K, b = std::min(a + K, nsteps);
       const char* src = ck + (size_t)sgi * sb;
-      HIPCHK(c, hipMemcpyAsync(pool_at(c, n0 + a), src, pb, hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(c->d_st, src + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
+      // segment slot s holds the state at step a + s: the replay of step n
+      // reads slot n - a and writes slot n + 1 - a (the step kernels take
+      // their input and output pools by the parity of the step index)
       HIPCHK(c, hipMemcpyAsync(seg, src, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(c->d_st, src + pb, sizeof(StepState), hipMemcpyDeviceToDevice, c->stream));
       HIPCHK(c, launch_sources(fwd, c->stream));
       for (long n = a; n < b; ++n) {
-        sbp_status s2 = enqueue_step_on(c, fwd, false);
+        KArgs f = fwd;
+        void* in = seg + (size_t)(n - a) * pb;
+        void* out = seg + (size_t)(n + 1 - a) * pb;
+        f.pool = ((n0 + n) & 1) ? out : in;
+        f.pool2 = ((n0 + n) & 1) ? in : out;
+        sbp_status s2 = enqueue_step_on(c, f, false);
         if (s2 != SBP_OK) return s2;
-        HIPCHK(c, hipMemcpyAsync(seg + (size_t)(n + 1 - a) * pb, pool_at(c, n0 + n + 1), pb,
-                                 hipMemcpyDeviceToDevice, c->stream));
       }
       for (long n = b - 1; n >= a; --n) {
         const char* enew = seg + (size_t)(n + 1 - a) * pb;
         const char* eold = seg + (size_t)(n - a) * pb;
-        void* acur = (m & 1) ? apool2 : apool;
-        HIPCHK(c, f64 ? launch_adj_grad<double>(acur, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream)
-                      : launch_adj_grad<float>(acur, enew, eold, c->d_blocks, c->mat[0], block, G, c->stream));
+        const char* acur = (const char*)((m & 1) ? apool2 : apool);
+        const size_t eoff = (size_t)d.foff * elem_size(c);  // the block's Ex, Ey, Ez: 3 csz values from foff
+        HIPCHK(c, f64 ? launch_adj_grad<double>(acur + eoff, enew + eoff, eold + eoff, 3LL * d.csz, G, c->stream)
+                      : launch_adj_grad<float>(acur + eoff, enew + eoff, eold + eoff, 3LL * d.csz, G, c->stream));
         sbp_status s2 = enqueue_step_on(c, adj, false);
         if (s2 != SBP_OK) return s2;
         ++m;

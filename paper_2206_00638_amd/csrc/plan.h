@@ -128,7 +128,8 @@ struct KArgs {
   const Tile* tiles;
   const FTile* ftiles;
   int ntiles;
-  int cz, pad_;
+  int cz;
+  int order;   // tile walk: 0 = dispatch order, 1 = contiguous ranges per XCD
   void* pool;   // field pools: step n reads pool (n even) or pool2 (n odd)
   void* pool2;  // and writes the other one
   const void* mat_eps;

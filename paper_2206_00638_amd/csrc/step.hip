@@ -91,14 +91,19 @@ __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts) {
   }
 }
 
-// Walks the tile list so that the workgroups on one XCD (workgroup g sits on
-// XCD g % 8) take a contiguous range of tiles.  The host rounds the grid up
-// to a multiple of 8; surplus workgroups only join the energy reduction.
+// Walks the tile list.  order 0: a workgroup per tile takes the tiles in
+// dispatch order, so the workgroups resident at any moment stream through
+// neighbouring addresses (faster for state larger than the last-level cache).
+// order 1, or a persistent grid (fewer workgroups than tiles): the workgroups
+// on one XCD (workgroup g sits on XCD g % 8) take a contiguous range of
+// tiles, which keeps neighbouring planes in that XCD's L2 (faster for
+// cache-resident state).  The host rounds the grid up to a multiple of 8;
+// surplus workgroups only join the energy reduction.
 struct TileIter {
   int t, stop, stride;
-  __device__ explicit TileIter(int ntiles) {
+  __device__ TileIter(int ntiles, int order) {
     const int g = blockIdx.x, G = gridDim.x;
-    if (G % kXcds == 0) {
+    if ((order == 1 || G < ntiles) && G % kXcds == 0) {
       const int per = (ntiles + kXcds - 1) / kXcds;
       const int x = g % kXcds;
       t = x * per + g / kXcds;
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
   const long long nstep = a.st->step;
   const void* pin = pool_in(a, nstep);
   void* pout = pool_out(a, nstep);
-  TileIter it(a.t1 - a.t0);
+  TileIter it(a.t1 - a.t0, a.order);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
     const SBP_CONST Tile& tl = as_const(a.tiles)[t];
@@ -653,7 +658,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   const long long nstep = a.st->step;
   const void* pin = pool_in(a, nstep);
   void* pout = pool_out(a, nstep);
-  TileIter it(a.t1 - a.t0);
+  TileIter it(a.t1 - a.t0, a.order);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
     const SBP_CONST Tile& tl = as_const(a.tiles)[t];
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
   const void* pin = pool_in(a, nstep);
   void* pout = pool_out(a, nstep);
   const int lane = threadIdx.x & (FX - 1), w = threadIdx.x / FX;
-  TileIter it(a.t1 - a.t0);
+  TileIter it(a.t1 - a.t0, 1);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
     const SBP_CONST FTile& ft = as_const(a.ftiles)[t];
