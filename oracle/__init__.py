@@ -19,6 +19,12 @@ Two independent forms of the same method:
 
 ``yee`` is a plain Yee FDTD reference, used only to pin the interior.
 
+``dispersion``: the eigen-procedure of Section IV on a periodic box (the
+amplification matrix of one leapfrog step, numerical wavenumbers, the
+dispersion / dissipation / global errors), for the SBP-SAT scheme with
+periodic faces (EPBC1-EPBC6) and, to pin the procedure, for the classical
+Yee scheme against its closed-form dispersion relation.
+
 ``adjoint``: the discrete adjoint of the leapfrog step in the matrix form
 (explicit transposes), giving the gradient of a region objective with
 respect to the per-cell permittivity; pinned by central finite differences

@@ -11,8 +11,13 @@ Follows the paper section by section:
   sigma of E13-E15 are swapped relative to E17; the energy rate E17 fixes
   which face each sigma belongs to (b/f = -x/+x, l/r = -y/+y, d/t = -z/+z), and
   that assignment is used with the values of E18.
-* EPBC1-EPBC6 with alpha = 0 and sigma = chi = +-1/2 (EPBCP): the penalty
-  pattern used to couple two blocks across a shared face.  Blocks of
+* EPBC1-EPBC6 with sigma = chi = +-1/2 (EPBCP): periodic faces.  The two
+  faces of an axis of one block are penalised with each other's values, the
+  high face's neighbour value being e^{-j alpha} times the low face's and the
+  low face's e^{+j alpha} times the high face's (alpha = k0_axis times the
+  block length along the axis); with alpha != 0 the fields are complex.
+* The same pattern with alpha = 0 couples two blocks across a shared face.
+  Blocks of
   different mesh sizes (1:2) use the same pattern with the neighbour's face
   values interpolated (see ``operators.interp_c2f``); the paper defers that
   construction, so it is a reading.
@@ -196,11 +201,15 @@ class System:
               (per-cell arrays (nz,ny,nx) or None), faces: 6 bc names}
       interfaces: list of (block_a, face_a, block_b, face_b, ratio), ratio =
               cells of b per cell of a (1 or 2)
+      periodic: list of (block, axis, alpha): both faces of the axis are
+              periodic with the phase shift e^{-j alpha} (EPBC1-EPBC6)
     """
 
     def __init__(self, problem):
         self.blocks = problem["blocks"]
         self.interfaces = list(problem.get("interfaces", []))
+        self.periodic = [(int(b), int(a), float(al)) for (b, a, al) in problem.get("periodic", [])]
+        self.complex = any(al != 0.0 for (_, _, al) in self.periodic)
         self._index()
         self._materials()
         self._assemble()
@@ -220,6 +229,18 @@ class System:
         self.ne, self.nh = ne, nh
         # which faces are interfaces, and with whom
         self.face_link = {}
+        self.face_phase = {}  # factor on the neighbour's face values (periodic faces)
+        for (b, axis, alpha) in self.periodic:
+            lo, hi = 2 * axis, 2 * axis + 1
+            if (b, lo) in self.face_link or (b, hi) in self.face_link:
+                raise ValueError("face already coupled")
+            self.face_link[(b, hi)] = (b, lo, "same")
+            self.face_link[(b, lo)] = (b, hi, "same")
+            if alpha == 0.0:
+                self.face_phase[(b, hi)] = self.face_phase[(b, lo)] = 1.0
+            else:
+                self.face_phase[(b, hi)] = complex(math.cos(alpha), -math.sin(alpha))
+                self.face_phase[(b, lo)] = complex(math.cos(alpha), math.sin(alpha))
         for (ba, fa, bb, fb, ratio) in self.interfaces:
             if ratio not in (1, 2):
                 raise ValueError("interface ratio must be 1 or 2")
@@ -301,7 +322,7 @@ class System:
             store.append((coo.data, coo.row + rows_off, coo.col + cols_off))
 
         def build(store, shape):
-            data = np.concatenate([s[0] for s in store])
+            data = np.concatenate([np.asarray(s[0], complex if self.complex else float) for s in store])
             rows = np.concatenate([s[1] for s in store])
             cols = np.concatenate([s[2] for s in store])
             return sp.csr_matrix((data, (rows, cols)), shape=shape)  # duplicates summed
@@ -343,8 +364,8 @@ class System:
                                   0.5 * sigma * sat @ face_select(ec, n, face),
                                   self.nh, self.ne, blocks_he)
                             place(self.h_off[(b, hc)], self.e_off[(nb, ec)],
-                                  -0.5 * sigma * sat @ self._face_interp(b, face, ec)
-                                  @ face_select(ec, nn, fnb),
+                                  -0.5 * sigma * self.face_phase.get((b, face), 1.0) * sat
+                                  @ self._face_interp(b, face, ec) @ face_select(ec, nn, fnb),
                                   self.nh, self.ne, blocks_he)
                 # E equations: tangential H on the face (E19-E21 / EPBC4-6)
                 for ec in E_COMPS:
@@ -373,8 +394,8 @@ class System:
                                   0.5 * chi * sat @ face_select(hc, n, face),
                                   self.ne, self.nh, blocks_eh)
                             place(self.e_off[(b, ec)], self.h_off[(nb, hc)],
-                                  -0.5 * chi * sat @ self._face_interp(b, face, hc)
-                                  @ face_select(hc, nn, fnb),
+                                  -0.5 * chi * self.face_phase.get((b, face), 1.0) * sat
+                                  @ self._face_interp(b, face, hc) @ face_select(hc, nn, fnb),
                                   self.ne, self.nh, blocks_eh)
         self.K_eh = build(blocks_eh, (self.ne, self.nh))
         self.K_he = build(blocks_he, (self.nh, self.ne))
@@ -399,10 +420,12 @@ class System:
         return out
 
     def join(self, fields):
-        e = np.zeros(self.ne)
-        h = np.zeros(self.nh)
+        cplx = self.complex or any(np.iscomplexobj(a) for a in fields.values())
+        dtype = np.complex128 if cplx else np.float64
+        e = np.zeros(self.ne, dtype)
+        h = np.zeros(self.nh, dtype)
         for (b, c), arr in fields.items():
-            arr = np.asarray(arr, np.float64).reshape(-1)
+            arr = np.asarray(arr, dtype).reshape(-1)
             if c in E_COMPS:
                 o = self.e_off[(b, c)]
                 e[o:o + arr.size] = arr
@@ -421,13 +444,16 @@ class System:
 
     # ------------------------------------------------------------ energy
     def energy(self, e, h_new, h_old):
-        """W^n of E16 with the leapfrog pairing of H."""
-        return 0.5 * np.dot(self.eps * self.w_e * e, e) + \
-            0.5 * np.dot(self.mu * self.w_h * h_new, h_old)
+        """W^n of E16 with the leapfrog pairing of H (for complex fields the
+        real part of the Hermitian form: the sum over real and imaginary
+        parts)."""
+        return float(np.real(0.5 * np.vdot(e, self.eps * self.w_e * e) +
+                             0.5 * np.vdot(h_old, self.mu * self.w_h * h_new)))
 
     def energy_instant(self, e, h):
         """E16 with E and H taken at the same time level (oscillates under leapfrog)."""
-        return 0.5 * np.dot(self.eps * self.w_e * e, e) + 0.5 * np.dot(self.mu * self.w_h * h, h)
+        return float(np.real(0.5 * np.vdot(e, self.eps * self.w_e * e) +
+                             0.5 * np.vdot(h, self.mu * self.w_h * h)))
 
     # --------------------------------------------------------- time step
     def coefficients(self, dt):
@@ -462,15 +488,16 @@ def run(problem, steps=None, dt=None, init=None, record_fields_every=0):
     ca, cb = sysm.coefficients(dt)
     inv_mu = 1.0 / sysm.mu
     if init is None:
-        e = np.zeros(sysm.ne)
-        h = np.zeros(sysm.nh)
+        dtype = np.complex128 if sysm.complex else np.float64
+        e = np.zeros(sysm.ne, dtype)
+        h = np.zeros(sysm.nh, dtype)
     else:
         e, h = sysm.join(init)
     srcs = [(sysm.node_index(s["block"], s["comp"], s["node"]), s) for s in problem.get("sources", [])]
     prb = [(p["comp"] in E_COMPS, sysm.node_index(p["block"], p["comp"], p["node"]))
            for p in problem.get("probes", [])]
     energy = np.zeros(steps)
-    probes = np.zeros((len(prb), steps))
+    probes = np.zeros((len(prb), steps), e.dtype)
     snaps = []
     for n in range(steps):
         h_new = h + dt * inv_mu * (sysm.K_he @ e)
