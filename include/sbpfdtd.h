@@ -88,6 +88,23 @@ sbp_status sbp_set_face_bc(sbp_ctx *ctx, int block, int face, sbp_bc bc);
  * face values are interpolated by a norm-compatible pair of operators. */
 sbp_status sbp_connect(sbp_ctx *ctx, int blk_a, int face_a, int blk_b, int face_b, int ratio);
 
+/* Makes both faces of `axis` (0 = x, 1 = y, 2 = z) of `block` periodic
+ * (Section III, EPBC1-EPBC6 with sigma = chi = +-1/2 of EPBCP): each face is
+ * penalised with the opposite face's values, the high face with e^{-j alpha}
+ * times the low face's and the low face with e^{+j alpha} times the high
+ * face's, alpha = k0_axis times the block length along the axis.
+ *   block_im < 0: real fields; alpha must be 0.
+ *   block_im >= 0: the fields are complex, `block` holding the real and
+ *     `block_im` the imaginary part.  The two blocks must have the same cells
+ *     and spacings (and should be given the same materials); the call makes
+ *     the axis periodic in both, with the parts mixed by cos / sin alpha at
+ *     the faces.  Every periodic axis of a complex block names the same
+ *     block_im.  W^n is then the energy of the complex field.
+ * Errors: SBP_EINVAL for a bad block or axis, a non-finite alpha, alpha != 0
+ * without block_im, mismatched parts, or a face already coupled;
+ * SBP_ESTATE after sbp_finalize. */
+sbp_status sbp_set_periodic(sbp_ctx *ctx, int block, int block_im, int axis, double alpha);
+
 /* Soft source (a current density inside the E update) on node (i,j,k) of an
  * E component; p = {tw, t0, f0} in seconds / Hz; evaluated at (n+1/2) dt. */
 sbp_status sbp_add_source(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int k,

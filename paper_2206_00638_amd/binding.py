@@ -38,6 +38,7 @@ SIGNATURES = {
     "sbp_add_block": [_P, _I, _I, _I, _D, _D, _D, _D, _D, _D, _P, _P, _P, _IP],
     "sbp_set_face_bc": [_P, _I, _I, _I],
     "sbp_connect": [_P, _I, _I, _I, _I, _I],
+    "sbp_set_periodic": [_P, _I, _I, _I, _D],
     "sbp_add_source": [_P, _I, _I, _I, _I, _I, _I, _DP, _D, _IP],
     "sbp_add_probe": [_P, _I, _I, _I, _I, _I, _IP],
     "sbp_finalize": [_P, _D, _I, _L, _DP],
@@ -168,6 +169,11 @@ class Context:
 
     def connect(self, a, fa, b, fb, ratio):
         self._chk(self._lib.sbp_connect(self.h, a, fa, b, fb, ratio))
+
+    def set_periodic(self, block, axis, alpha=0.0, block_im=-1):
+        """Both faces of `axis` periodic with the Bloch phase e^{-j alpha};
+        alpha != 0 needs `block_im`, the block holding the imaginary part."""
+        self._chk(self._lib.sbp_set_periodic(self.h, int(block), int(block_im), int(axis), float(alpha)))
 
     def add_source(self, block, comp, node, waveform, tw, t0, f0=0.0, amp=1.0):
         p = (ctypes.c_double * 3)(tw, t0, f0)
@@ -301,6 +307,21 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
                 ctx.set_face_bc(bid, f, bc)
     for (a, fa, b, fb, r) in problem.get("interfaces", []):
         ctx.connect(a, fa, b, fb, r)
+    # periodic axes (block, axis, alpha); a block with a nonzero phase on any
+    # axis has complex fields: a twin block, appended after the problem's
+    # blocks, holds the imaginary part (ctx.imag_part[block])
+    periodic = [(int(b), int(a), float(al)) for (b, a, al) in problem.get("periodic", [])]
+    ctx.imag_part = {}
+    for b in sorted({b for (b, _, al) in periodic if al != 0.0}):
+        src = problem["blocks"][b]
+        tw = ctx.add_block(src["n"], src["h"], src.get("origin", (0.0, 0.0, 0.0)), src.get("eps_r"),
+                           src.get("mu_r"), src.get("sigma"))
+        for f, bc in enumerate(src["faces"]):
+            if bc in BC:
+                ctx.set_face_bc(tw, f, bc)
+        ctx.imag_part[b] = tw
+    for (b, a, al) in periodic:
+        ctx.set_periodic(b, a, al, ctx.imag_part.get(b, -1))
     for s in problem.get("sources", []):
         ctx.add_source(s["block"], s["comp"], s["node"], s["waveform"], s["tw"], s["t0"], s.get("f0", 0.0),
                        s.get("amp", 1.0))

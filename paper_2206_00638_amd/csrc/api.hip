@@ -55,8 +55,14 @@ struct HostBlock {
   int iface[6];  // index into ifaces or -1
 };
 
+// A coupled pair of faces.  Interfaces join two blocks; a periodic axis
+// joins a block's two faces of that axis (a == b, fa the high face), and for
+// complex fields `partner` is the block holding the other part (im: this
+// block holds the imaginary part) with the Bloch phase alpha.
 struct HostIface {
   int a, fa, b, fb, ratio;
+  int partner = -1, im = 0;
+  double alpha = 0.0;
 };
 
 struct HostSource {
@@ -822,6 +828,38 @@ sbp_status sbp_connect(sbp_ctx* c, int a, int fa, int b, int fb, int ratio) {
   return SBP_OK;
 }
 
+sbp_status sbp_set_periodic(sbp_ctx* c, int block, int block_im, int axis, double alpha) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "set_periodic after finalize");
+  if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
+  if (axis < 0 || axis > 2) return fail(c, SBP_EINVAL, "bad axis");
+  if (!std::isfinite(alpha)) return fail(c, SBP_EINVAL, "phase must be finite");
+  const int lo = 2 * axis, hi = 2 * axis + 1;
+  HostBlock& R = c->blocks[block];
+  if (R.iface[lo] >= 0 || R.iface[hi] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
+  if (block_im < 0) {
+    if (alpha != 0.0) return fail(c, SBP_EINVAL, "a Bloch phase needs the block of the imaginary part");
+  } else {
+    if (!check_block(c, block_im) || block_im == block) return fail(c, SBP_EINVAL, "bad imaginary-part block");
+    const HostBlock& I = c->blocks[block_im];
+    for (int t = 0; t < 3; ++t)
+      if (I.n[t] != R.n[t] || I.h[t] != R.h[t])
+        return fail(c, SBP_EINVAL, "the two parts of a complex block must have the same cells and spacings");
+    if (I.iface[lo] >= 0 || I.iface[hi] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
+  }
+  auto add = [&](int b, int partner, int im) {
+    HostIface f{b, hi, b, lo, 1};
+    f.partner = partner;
+    f.im = im;
+    f.alpha = alpha;
+    c->ifaces.push_back(f);
+    c->blocks[b].iface[lo] = c->blocks[b].iface[hi] = (int)c->ifaces.size() - 1;
+  };
+  add(block, block_im, 0);
+  if (block_im >= 0) add(block_im, block, 1);
+  return SBP_OK;
+}
+
 sbp_status sbp_add_source(sbp_ctx* c, int block, sbp_comp comp, int i, int j, int k, sbp_wave w,
                           const double p[3], double amplitude, int* id) {
   if (!c) return SBP_EINVAL;
@@ -1011,6 +1049,13 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
           J.slot = slot;
           J.comp = is_h ? 3 + ta[slot] : ta[slot];
           J.nb = nb;
+          // EPBC1-EPBC6: the high face takes e^{-j alpha} times the low
+          // face's values, the low face e^{+j alpha} times the high face's;
+          // for fields split into real and imaginary parts the part held by
+          // the other block enters with +-sin(alpha)
+          J.nb2 = I.partner;
+          J.w1 = I.partner >= 0 ? std::cos(I.alpha) : 1.0;
+          J.w2 = I.partner >= 0 ? ((f % 2) ? 1.0 : -1.0) * (I.im ? -1.0 : 1.0) * std::sin(I.alpha) : 0.0;
           const HostBlock& N = c->blocks[nb];
           // face-normal index of the neighbour's face: "+" along the normal for
           // tangential E (0 or n), "-" for tangential H (0 or n+1)

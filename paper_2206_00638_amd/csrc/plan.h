@@ -109,6 +109,9 @@ struct FaceJob {
   int block, face, is_h, slot;
   int comp;             // component gathered
   int nb;               // neighbour block
+  int nb2;              // second source block (periodic faces of complex
+                        // fields: the other part), or -1
+  double w1, w2;        // value = w1 * (nb's face) + w2 * (nb2's face)
   int nb_idx;           // face-normal node index of the neighbour face
   int t_axis[2];        // tangential axes (ascending)
   int ext[2];           // own face-node extents along the tangential axes

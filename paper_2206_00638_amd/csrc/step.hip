@@ -977,18 +977,24 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
   const int r0 = (int)(id % J.ext[0]), r1 = (int)(id / J.ext[0]);
   const Taps& T0 = taps[J.taps_off[0] + r0];
   const Taps& T1 = taps[J.taps_off[1] + r1];
-  const T* nf = (const T*)pool + N.foff + (long long)J.comp * N.csz;
   const long long st[3] = {1, N.sx, N.sxy};
   const int axis = J.face >> 1;
   const long long onrm = (long long)J.nb_idx * st[axis];
-  double v = 0.0;
-  for (int q = 0; q < T1.count; ++q) {
-    double s = 0.0;
-    const long long o1 = onrm + (long long)(T1.start + q) * st[J.t_axis[1]];
-    for (int p = 0; p < T0.count; ++p)
-      s += T0.w[p] * (double)nf[o1 + (long long)(T0.start + p) * st[J.t_axis[0]]];
-    v += T1.w[q] * s;
-  }
+  // the interpolated face value of one source block (nb2 has nb's geometry)
+  auto gather = [&](const DevBlock& S) {
+    const T* nf = (const T*)pool + S.foff + (long long)J.comp * S.csz;
+    double v = 0.0;
+    for (int q = 0; q < T1.count; ++q) {
+      double s = 0.0;
+      const long long o1 = onrm + (long long)(T1.start + q) * st[J.t_axis[1]];
+      for (int p = 0; p < T0.count; ++p)
+        s += T0.w[p] * (double)nf[o1 + (long long)(T0.start + p) * st[J.t_axis[0]]];
+      v += T1.w[q] * s;
+    }
+    return v;
+  };
+  double v = J.w1 * gather(N);
+  if (J.nb2 >= 0) v += J.w2 * gather(blocks[J.nb2]);
   // own face-node index in the node-box face layout
   const int bx = B.n[0] + 2, by = B.n[1] + 2;
   long long fidx;
