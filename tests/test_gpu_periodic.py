@@ -140,3 +140,51 @@ def test_set_periodic_errors(sbp):
     with pytest.raises(sbp.SbpError):
         ctx.set_periodic(a, 2, 0.0)           # faces already coupled
     ctx.close()
+
+
+def test_bloch_eigenmode_rotates_by_its_eigenvalue(sbp):
+    """Section IV on the GPU: the eigenvector of the one-step amplification
+    matrix (oracle, dense eigen-decomposition) whose numerical wavenumber is
+    nearest k0, stepped by the HIP path in fp64, is multiplied by its
+    eigenvalue at every step; the wavenumber read back from the run
+    (E_NUMWN) equals the eigen-analysis one."""
+    import cmath
+    from oracle import dispersion as D
+    from oracle import system as S
+    h = (1e-3, 1e-3, 1e-3)
+    n = (4, 4, 4)
+    k0 = 2.0 * math.pi * 0.08 / h[0]
+    kv = (0.3 * k0, 0.0, math.sqrt(1 - 0.09) * k0)
+    alphas = [kv[a] * n[a] * h[a] for a in range(3)]
+    dt = 0.99 / (S.C0 * math.sqrt(3.0) / h[0])
+    box = D.sbp_box(n, h, alphas)
+    lam = D.amplification_matrix(box.K_eh, box.K_he, box.eps, box.mu, dt)
+    ev, vec = np.linalg.eig(lam)
+    kts = D.numerical_wavenumbers(ev, dt)
+    m = int(np.argmin(np.abs(kts - k0)))
+    u = vec[:, m] / np.abs(vec[:, m]).max()
+    fields = box.split(u[:box.ne].copy(), u[box.ne:].copy())
+    blk = {"n": n, "h": h, "faces": ["pec"] * 6, "eps_r": None, "mu_r": None, "sigma": None}
+    prob = {"blocks": [blk], "periodic": [(0, a, alphas[a]) for a in range(3)], "sources": [], "probes": []}
+    ctx = sbp.build_problem(prob, prec="f64", cfl=0.99)
+    assert abs(ctx.dt - dt) < 1e-12 * dt
+    im = ctx.imag_part[0]
+    for (b, c), v in fields.items():
+        ctx.write_field(0, c, np.real(v))
+        ctx.write_field(im, c, np.imag(v))
+    steps = 60
+    ctx.step(steps)
+    got = np.concatenate([(ctx.read_field(0, c) + 1j * ctx.read_field(im, c)).reshape(-1) for c in COMPS])
+    ctx.close()
+    want = np.concatenate([(ev[m] ** steps * fields[(0, c)]).reshape(-1) for c in COMPS])
+    assert np.abs(got - want).max() < 1e-11
+    # the wavenumber measured from the run: the mean rotation per step
+    ratio = np.vdot(np.concatenate([fields[(0, c)].reshape(-1) for c in COMPS]), got) / \
+        np.vdot(np.concatenate([fields[(0, c)].reshape(-1) for c in COMPS]),
+                np.concatenate([fields[(0, c)].reshape(-1) for c in COMPS]))
+    k_run = cmath.log(ratio) / (1j * S.C0 * dt * steps)
+    # the principal log of lambda^steps wraps: compare modulo 2 pi / (c dt steps)
+    wrap = 2.0 * math.pi / (S.C0 * dt * steps)
+    d = (k_run - kts[m]).real
+    assert abs(d - wrap * round(d / wrap)) < 1e-9 * abs(kts[m])
+    assert abs(k_run.imag) < 1e-9 * abs(kts[m])
