@@ -138,6 +138,37 @@ def batched(steps, warmup):
             "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
+def bloch(steps, warmup):
+    """Periodic faces with a Bloch phase: a 192^3 vacuum box, complex fields
+    (two 192^3 blocks holding the real and imaginary parts), fp32, phases of
+    an oblique wave at lambda/20."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import bloch_box
+    prob = bloch_box()
+    cells = int(np.prod(prob["blocks"][0]["n"]))
+    stream = torch.cuda.Stream()
+    ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(True)
+    ctx.step(20)
+    torch.cuda.synchronize()
+    kern = ctx.kernel_ms()
+    ctx.close()
+    hb, eb, fb = algorithmic_bytes(prob, 4)
+    ms = wall * 1e3 / steps
+    return {"workload": prob["name"], "complex_cells": cells, "real_blocks": 2, "steps": steps,
+            "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s (complex cells)",
+            "ms_per_step": ms, "kernels_ms": list(kern),
+            "step_hbm_gbs_algorithmic": 2 * (hb + eb + fb) / (ms * 1e-3) / 1e9}
+
+
 def subgrid(steps, warmup):
     """The 1:2 subgrid workload: 27 blocks (coarse 192^3 region at 1 mm around
     a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box, fp32."""
@@ -269,6 +300,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-subgrid", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-bloch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -330,6 +362,8 @@ def main():
         out["batched"] = batched(args.steps, max(args.warmup, 100))
     if not args.no_subgrid:
         out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+    if not args.no_bloch:
+        out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
     if not args.no_accuracy:

@@ -29,15 +29,6 @@ namespace sbp {
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 
-__device__ __forceinline__ double face_value(const KArgs& a, const DevBlock& B, int face, int is_h,
-                                             int slot, int i, int j, int k) {
-  const int axis = face >> 1;
-  const long long t = axis == 0 ? (long long)j + (long long)(B.n[1] + 2) * k
-                    : axis == 1 ? (long long)i + (long long)(B.n[0] + 2) * k
-                                : (long long)i + (long long)(B.n[0] + 2) * j;
-  return a.face[B.fboff[face] + (long long)(is_h * 2 + slot) * B.fsz[face] + t];
-}
-
 // Workgroup sum of `v`, stored to partials[poff + blockIdx.x]; the launch's
 // total is formed later by k_finish, in a fixed order (deterministic).
 __device__ void store_partial(double v, const KArgs& a) {
@@ -163,20 +154,18 @@ __device__ __forceinline__ TRow<T> row_of(const DB& B, int axis, int r, bool min
   return R;
 }
 
-// Closure row applied to u along stride st at node offset o; `face`/`slot`
-// locate the gathered neighbour value of an interface row.
+// Closure row applied to u along stride st at node offset o; on an
+// interface row the gathered neighbour value a.face[fo] joins it.
 template <typename T, bool IFACE>
-__device__ __forceinline__ T drow(const KArgs& a, const DevBlock& B, const T* __restrict__ u, long long o,
-                                  long long st, const TRow<T>& R, int face, int is_h, int slot, int i, int j,
-                                  int k) {
+__device__ __forceinline__ T drow(const KArgs& a, const T* __restrict__ u, long long o, long long st,
+                                  const TRow<T>& R, long long fo) {
   const T* p = u + o + (long long)R.s * st;
   T v = R.c0 * p[0] + R.c1 * p[st] + R.c2 * p[2 * st];
   if constexpr (IFACE) {
-    if (R.nbr) v += R.cn * (T)face_value(a, B, face, is_h, slot, i, j, k);
+    if (R.nbr) v += R.cn * (T)a.face[fo];
   }
   return v;
 }
-
 
 // Probe samples of node (i, j, k): probes of the given field on that node
 // take the new values (only for tiles flagged as holding a probe).
@@ -214,6 +203,18 @@ __device__ __forceinline__ void source_terms(const KArgs& a, const DevBlock& B, 
 template <typename X>
 __device__ __forceinline__ const SBP_CONST X* as_const(const X* p) {
   return (const SBP_CONST X*)p;
+}
+
+// Face-buffer offsets of a node column's x- and y-face interface rows: the
+// buffer of face f holds, per slot (is_h * 2 + tangential component), the
+// face's nodes in its own (x fastest) order: (j, k) on x faces, (i, k) on y
+// faces, (i, j) on z faces.  `lo` splits the column's rows between the low
+// and the high face.
+struct FaceCol {
+  long long x, y;
+};
+__device__ __forceinline__ FaceCol face_col(const SBP_CONST DevBlock& Bc, int i, int j, int lo) {
+  return FaceCol{(i < lo ? Bc.fboff[0] : Bc.fboff[1]) + j, (j < lo ? Bc.fboff[2] : Bc.fboff[3]) + i};
 }
 
 // Element `idx` of a component array addressed as the (wave-uniform) array
@@ -307,8 +308,8 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
                                     const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
-                                    T* __restrict__ Hz, const T* __restrict__ M, int i, int j, int k,
-                                    long long o, bool store, T& onx, T& ony, T& onz) {
+                                    T* __restrict__ Hz, const T* __restrict__ M, const FaceCol& fc, int i,
+                                    int j, int k, long long o, bool store, T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -317,21 +318,23 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
   T dzEy = (v.ey - v.ey_z) * ihz, dzEx = (v.ex - v.ex_z) * ihz;
   T dyEz = (v.ez - v.ez_y) * ihy, dyEx = (v.ex - v.ex_y) * ihy;
   T dxEz = (v.ez - v.ez_x) * ihx, dxEy = (v.ey - v.ey_x) * ihx;
+  // face-buffer slots of tangential E: 0 and 1 (ascending tangential axis)
+  const long long bx = nx + 2, by = ny + 2, bz = nz + 2;
   if (!zin) {
     const TRow<T> rz = row_of<T>(Bc, 2, k, true);
-    const int f = k < 3 ? 4 : 5;
-    dzEy = drow<T, GEN>(a, B, Ey, o, sxy, rz, f, 0, 1, i, j, k);
-    dzEx = drow<T, GEN>(a, B, Ex, o, sxy, rz, f, 0, 0, i, j, k);
+    const long long fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
+    dzEy = drow<T, GEN>(a, Ey, o, sxy, rz, fo + bx * by);
+    dzEx = drow<T, GEN>(a, Ex, o, sxy, rz, fo);
   }
   if (!yin) {
-    const int f = j < 3 ? 2 : 3;
-    dyEz = drow<T, GEN>(a, B, Ez, o, sx, ry, f, 0, 1, i, j, k);
-    dyEx = drow<T, GEN>(a, B, Ex, o, sx, ry, f, 0, 0, i, j, k);
+    const long long fo = fc.y + bx * k;
+    dyEz = drow<T, GEN>(a, Ez, o, sx, ry, fo + bx * bz);
+    dyEx = drow<T, GEN>(a, Ex, o, sx, ry, fo);
   }
   if (!xin) {
-    const int f = i < 3 ? 0 : 1;
-    dxEz = drow<T, GEN>(a, B, Ez, o, 1, rx, f, 0, 1, i, j, k);
-    dxEy = drow<T, GEN>(a, B, Ey, o, 1, rx, f, 0, 0, i, j, k);
+    const long long fo = fc.x + by * k;
+    dxEz = drow<T, GEN>(a, Ez, o, 1, rx, fo + by * bz);
+    dxEy = drow<T, GEN>(a, Ey, o, 1, rx, fo);
   }
   const T db_u = c.db_u, mu_r0 = c.mu_r0;
   T dbx = db_u, dby = db_u, dbz = db_u, mx = mu_r0, my = mu_r0, mz = mu_r0;
@@ -391,6 +394,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, true), ry = row_of<T>(B, 1, j, true);  // D- rows of the column
     const W3<T> lw = h_col_weights<T>(c.nx, c.ny, i, j);
+    const FaceCol fc = GEN ? face_col(Bc, i, j, 3) : FaceCol{0, 0};  // D- rows: low face below 3
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -418,8 +422,8 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, i, j, k, o, true, v0, v1,
-                                   v2);
+      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, i, j, k, o, true, v0,
+                                   v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -542,8 +546,9 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
                                     const EIn<T>& v,
                                     T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
                                     const T* __restrict__ Hx, const T* __restrict__ Hy,
-                                    const T* __restrict__ Hz, const T* __restrict__ MS, int i, int j, int k,
-                                    long long o, T jx, T jy, T jz, T& onx, T& ony, T& onz) {
+                                    const T* __restrict__ Hz, const T* __restrict__ MS, const FaceCol& fc,
+                                    int i, int j, int k, long long o, T jx, T jy, T jz, T& onx, T& ony,
+                                    T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -553,25 +558,27 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   T dzHy = (v.hy_z - hy) * ihz, dzHx = (v.hx_z - hx) * ihz;
   T dyHz = (v.hz_y - hz) * ihy, dyHx = (v.hx_y - hx) * ihy;
   T dxHz = (v.hz_x - hz) * ihx, dxHy = (v.hy_x - hy) * ihx;
+  // face-buffer slots of tangential H: 2 and 3 (ascending tangential axis)
+  const long long bx = nx + 2, by = ny + 2, bz = nz + 2;
   if (!zin) {
     if (k <= nz) {
       const TRow<T> rz = row_of<T>(Bc, 2, k, false);
-      const int f = k < 2 ? 4 : 5;
-      dzHy = drow<T, GEN>(a, B, Hy, o, sxy, rz, f, 1, 1, i, j, k);
-      dzHx = drow<T, GEN>(a, B, Hx, o, sxy, rz, f, 1, 0, i, j, k);
+      const long long fs = bx * by, fo = Bc.fboff[k < 2 ? 4 : 5] + i + bx * j + 2 * fs;
+      dzHy = drow<T, GEN>(a, Hy, o, sxy, rz, fo + fs);
+      dzHx = drow<T, GEN>(a, Hx, o, sxy, rz, fo);
     } else {
       dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
     }
   }
   if (!yin) {
-    const int f = j < 2 ? 2 : 3;
-    dyHz = drow<T, GEN>(a, B, Hz, o, sx, ry, f, 1, 1, i, j, k);
-    dyHx = drow<T, GEN>(a, B, Hx, o, sx, ry, f, 1, 0, i, j, k);
+    const long long fs = bx * bz, fo = fc.y + bx * k + 2 * fs;
+    dyHz = drow<T, GEN>(a, Hz, o, sx, ry, fo + fs);
+    dyHx = drow<T, GEN>(a, Hx, o, sx, ry, fo);
   }
   if (!xin) {
-    const int f = i < 2 ? 0 : 1;
-    dxHz = drow<T, GEN>(a, B, Hz, o, 1, rx, f, 1, 1, i, j, k);
-    dxHy = drow<T, GEN>(a, B, Hy, o, 1, rx, f, 1, 0, i, j, k);
+    const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
+    dxHz = drow<T, GEN>(a, Hz, o, 1, rx, fo + fs);
+    dxHy = drow<T, GEN>(a, Hy, o, 1, rx, fo);
   }
   const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
   const T eps_r0 = c.eps_r0;
@@ -677,6 +684,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, false), ry = row_of<T>(B, 1, j, false);  // D+ rows of the column
     const W3<T> lw = e_col_weights<T>(c.nx, c.ny, i, j);
+    const FaceCol fc = GEN ? face_col(Bc, i, j, 2) : FaceCol{0, 0};  // D+ rows: low face below 2
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -715,8 +723,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, i, j, k, o,
-                                            jx, jy, jz, v0, v1, v2);
+      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc, i, j, k,
+                                            o, jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -839,8 +847,8 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, i, j, kh, o,
-                                      hown, v0, v1, v2);
+        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, FaceCol{0, 0},
+                                      i, j, kh, o, hown, v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
           if (tflags & 2) take_probes<T>(a, B, i, j, kh, true, nstep, v0, v1, v2);

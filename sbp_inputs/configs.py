@@ -241,5 +241,25 @@ def config5(scale=1):
             "ckpt_every": max(45 // scale, 2)}
 
 
+def bloch_box(n=192, frac=0.05, theta=0.6, phi=0.3, scale=1):
+    """A vacuum box of n^3 cells at h = 1 mm with every face periodic, with
+    the Bloch phases of an oblique plane wave (the setting of Section IV's
+    oblique-incidence study: mesh lambda/20, i.e. k0 h / 2 pi = frac = 0.05,
+    dt = 0.99 of the Yee limit); alpha_i = k0_i n h.  Fields are complex.  A
+    modulated Gaussian Ez source at the centre (real part) excites it."""
+    n = max(n // scale, 4)
+    h = 1e-3
+    k0 = 2.0 * math.pi * frac / h
+    kv = (k0 * math.sin(theta) * math.cos(phi), k0 * math.sin(theta) * math.sin(phi), k0 * math.cos(theta))
+    cfl = 0.99
+    return {"name": f"bloch-periodic-{n}^3-complex-fp32", "prec": "f32", "cfl": cfl, "steps": 1000,
+            "blocks": [{"n": (n, n, n), "h": (h, h, h), "origin": (0.0, 0.0, 0.0), "eps_r": None,
+                        "mu_r": None, "sigma": None, "faces": ["pec"] * 6}],
+            "interfaces": [], "periodic": [(0, a, kv[a] * n * h) for a in range(3)],
+            "sources": [_ez_cell(0, (n // 2, n // 2, n // 2), waveform="modgauss", tw=0.2e-9, t0=0.2e-9,
+                                 f0=10e9, amp=1.0)],
+            "probes": [_ez_cell(0, (n // 4, n // 2, n // 2))], "wave_vector": kv}
+
+
 def make_config(k, scale=1):
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k](scale)

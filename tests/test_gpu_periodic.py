@@ -188,3 +188,25 @@ def test_bloch_eigenmode_rotates_by_its_eigenvalue(sbp):
     d = (k_run - kts[m]).real
     assert abs(d - wrap * round(d / wrap)) < 1e-9 * abs(kts[m])
     assert abs(k_run.imag) < 1e-9 * abs(kts[m])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bloch_box_workload_reduced(sbp, prec):
+    """The benchmark's Bloch-periodic box recipe at 16^3 cells against the
+    oracle (complex fields), 80 steps from rest with its source."""
+    from oracle import system as S
+    from sbp_inputs import bloch_box
+    prob = bloch_box(scale=12)
+    steps = 80
+    ctx = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    ctx.step(steps)
+    im = ctx.imag_part[0]
+    g = {(0, c): ctx.read_field(0, c) + 1j * ctx.read_field(im, c) for c in COMPS}
+    ge = ctx.read_energy(0, steps)
+    gp = ctx.read_probe(0, 0, steps)
+    ctx.close()
+    r = S.run(prob, steps=steps)
+    errs = field_errors(g, r["fields"], FLOOR[prec])
+    assert max(errs.values()) < TOL[prec], errs
+    assert rel_l2(ge, r["energy"]) < TOL[prec]
+    assert rel_l2(gp, np.real(r["probes"][0])) < TOL[prec]
