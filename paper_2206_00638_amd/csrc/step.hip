@@ -27,6 +27,7 @@
 namespace sbp {
 
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kGroup = 8;  // tiles per XCD group in the dispatch-order tile walk
 
 
 // Workgroup sum of `v`, stored to partials[poff + blockIdx.x]; the launch's
@@ -83,8 +84,9 @@ __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts) {
 }
 
 // Walks the tile list.  order 0: a workgroup per tile takes the tiles in
-// dispatch order, so the workgroups resident at any moment stream through
-// neighbouring addresses (faster for state larger than the last-level cache).
+// (grouped) dispatch order, so the workgroups resident at any moment stream
+// through neighbouring addresses (faster for state larger than the
+// last-level cache).
 // order 1, or a persistent grid (fewer workgroups than tiles): the workgroups
 // on one XCD (workgroup g sits on XCD g % 8) take a contiguous range of
 // tiles, which keeps neighbouring planes in that XCD's L2 (faster for
@@ -101,7 +103,13 @@ struct TileIter {
       stop = min((x + 1) * per, ntiles);
       stride = G / kXcds;
     } else {
-      t = g;
+      // groups of kGroup consecutive tiles (about four node rows at 128
+      // threads) go to one XCD, consecutive groups to the next XCDs: the
+      // workgroups resident at a time still cover neighbouring addresses,
+      // and the row behind a tile (its y neighbours) is mostly in the same
+      // XCD's L2.  The last partial round of groups keeps dispatch order.
+      const int w = g / kXcds, x = g % kXcds, full = (G / kXcds) / kGroup * kGroup;
+      t = w < full ? ((w / kGroup) * kXcds + x) * kGroup + w % kGroup : g;
       stop = ntiles;
       stride = G;
     }
