@@ -583,14 +583,15 @@ sbp_status build_tiles(sbp_ctx* c) {
   return SBP_OK;
 }
 
-// Tile walk of the two-pass kernels: dispatch order when the fields and
-// materials exceed the 256 MB last-level cache (the step streams from HBM),
-// contiguous ranges per XCD when they fit (L2 reuse of neighbouring planes).
+// Tile walk of the step kernels: contiguous ranges per XCD when the fields
+// and materials fit in the eight XCDs' L2 caches together (8 x 4 MB), so
+// each XCD's share stays resident from step to step; grouped dispatch order
+// otherwise (the step streams through the Infinity Cache or HBM).
 int tile_order(const sbp_ctx* c) {
   size_t bytes = c->pool_elems * elem_size(c);
   for (int m = 0; m < 3; ++m)
     if (c->mat[m]) bytes += c->ncells * elem_size(c);
-  return bytes > (size_t(256) << 20) ? 0 : 1;
+  return bytes > (size_t(32) << 20) ? 0 : 1;
 }
 
 KArgs kargs(sbp_ctx* c) {

@@ -780,7 +780,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
   const void* pin = pool_in(a, nstep);
   void* pout = pool_out(a, nstep);
   const int lane = threadIdx.x & (FX - 1), w = threadIdx.x / FX;
-  TileIter it(a.t1 - a.t0, 1);
+  TileIter it(a.t1 - a.t0, a.order);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
     const SBP_CONST FTile& ft = as_const(a.ftiles)[t];
