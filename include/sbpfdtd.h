@@ -99,10 +99,13 @@ sbp_status sbp_connect(sbp_ctx *ctx, int blk_a, int face_a, int blk_b, int face_
  *     and spacings (and should be given the same materials); the call makes
  *     the axis periodic in both, with the parts mixed by cos / sin alpha at
  *     the faces.  Every periodic axis of a complex block names the same
- *     block_im.  W^n is then the energy of the complex field.
+ *     block_im (alpha may be 0 on some axes), and the two parts take no
+ *     interfaces (sbp_connect).  W^n is then the energy of the complex field.
  * Errors: SBP_EINVAL for a bad block or axis, a non-finite alpha, alpha != 0
- * without block_im, mismatched parts, or a face already coupled;
- * SBP_ESTATE after sbp_finalize. */
+ * without block_im, mismatched parts, a block paired with two different
+ * partners (or as both the real and the imaginary part), a complex block
+ * with interfaces, or a face already coupled; SBP_ESTATE after
+ * sbp_finalize. */
 sbp_status sbp_set_periodic(sbp_ctx *ctx, int block, int block_im, int axis, double alpha);
 
 /* Soft source (a current density inside the E update) on node (i,j,k) of an

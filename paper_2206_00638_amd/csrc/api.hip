@@ -53,6 +53,9 @@ struct HostBlock {
   std::vector<double> eps, mu, sig;
   int faces[6];
   int iface[6];  // index into ifaces or -1
+  // complex fields (periodic faces with a Bloch phase): the block holding
+  // the other part, and whether this block holds the imaginary part
+  int part_of = -1, imag = 0;
 };
 
 // A coupled pair of faces.  Interfaces join two blocks; a periodic axis
@@ -809,6 +812,7 @@ sbp_status sbp_connect(sbp_ctx* c, int a, int fa, int b, int fb, int ratio) {
   if (ratio != 1 && ratio != 2) return fail(c, SBP_EINVAL, "ratio must be 1 or 2");
   HostBlock &A = c->blocks[a], &B = c->blocks[b];
   if (A.iface[fa] >= 0 || B.iface[fb] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
+  if (A.part_of >= 0 || B.part_of >= 0) return fail(c, SBP_EINVAL, "a complex block cannot also have interfaces");
   const int ax = fa / 2;
   const double tol = 1e-9;
   auto close = [&](double u, double v, double scale) { return std::fabs(u - v) <= tol * scale; };
@@ -840,6 +844,7 @@ sbp_status sbp_set_periodic(sbp_ctx* c, int block, int block_im, int axis, doubl
   if (R.iface[lo] >= 0 || R.iface[hi] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
   if (block_im < 0) {
     if (alpha != 0.0) return fail(c, SBP_EINVAL, "a Bloch phase needs the block of the imaginary part");
+    if (R.part_of >= 0) return fail(c, SBP_EINVAL, "the block holds part of a complex field: name the imaginary part");
   } else {
     if (!check_block(c, block_im) || block_im == block) return fail(c, SBP_EINVAL, "bad imaginary-part block");
     const HostBlock& I = c->blocks[block_im];
@@ -847,6 +852,13 @@ sbp_status sbp_set_periodic(sbp_ctx* c, int block, int block_im, int axis, doubl
       if (I.n[t] != R.n[t] || I.h[t] != R.h[t])
         return fail(c, SBP_EINVAL, "the two parts of a complex block must have the same cells and spacings");
     if (I.iface[lo] >= 0 || I.iface[hi] >= 0) return fail(c, SBP_EINVAL, "face already coupled");
+    if ((R.part_of >= 0 && (R.part_of != block_im || R.imag)) || (I.part_of >= 0 && (I.part_of != block || !I.imag)))
+      return fail(c, SBP_EINVAL, "a complex block keeps one imaginary-part block on every periodic axis");
+    // the other faces of the two parts must not couple them to other blocks
+    for (int f = 0; f < 6; ++f)
+      if ((R.iface[f] >= 0 && c->ifaces[R.iface[f]].a != c->ifaces[R.iface[f]].b) ||
+          (I.iface[f] >= 0 && c->ifaces[I.iface[f]].a != c->ifaces[I.iface[f]].b))
+        return fail(c, SBP_EINVAL, "a complex block cannot also have interfaces");
   }
   auto add = [&](int b, int partner, int im) {
     HostIface f{b, hi, b, lo, 1};
@@ -857,7 +869,12 @@ sbp_status sbp_set_periodic(sbp_ctx* c, int block, int block_im, int axis, doubl
     c->blocks[b].iface[lo] = c->blocks[b].iface[hi] = (int)c->ifaces.size() - 1;
   };
   add(block, block_im, 0);
-  if (block_im >= 0) add(block_im, block, 1);
+  if (block_im >= 0) {
+    add(block_im, block, 1);
+    c->blocks[block].part_of = block_im;
+    c->blocks[block_im].part_of = block;
+    c->blocks[block_im].imag = 1;
+  }
   return SBP_OK;
 }
 

@@ -139,6 +139,19 @@ def test_set_periodic_errors(sbp):
     ctx.set_periodic(a, 2, 0.0)
     with pytest.raises(sbp.SbpError):
         ctx.set_periodic(a, 2, 0.0)           # faces already coupled
+    c = ctx.add_block((6, 6, 6), (1e-3,) * 3)
+    d = ctx.add_block((6, 6, 6), (1e-3,) * 3)
+    e = ctx.add_block((6, 6, 6), (1e-3,) * 3)
+    ctx.set_periodic(c, 0, 0.3, d)
+    with pytest.raises(sbp.SbpError):
+        ctx.set_periodic(c, 1, 0.3, e)        # a second partner
+    with pytest.raises(sbp.SbpError):
+        ctx.set_periodic(d, 1, 0.3, c)        # the imaginary part as a real part
+    with pytest.raises(sbp.SbpError):
+        ctx.set_periodic(c, 1, 0.0)           # a complex block without its imaginary part
+    with pytest.raises(sbp.SbpError):
+        ctx.connect(c, 5, e, 4, 1)            # interfaces on a complex block
+    ctx.set_periodic(c, 1, 0.0, d)            # zero phase on another axis of the pair
     ctx.close()
 
 
