@@ -66,8 +66,17 @@ __global__ __launch_bounds__(256) void k_sources(KArgs a) { eval_sources(a, a.st
 // step index and evaluates the source values of step n+1.
 __global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts) {
   __shared__ double red[16];
-  double s = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += a.partials[p];
+  // eight independent running sums per thread keep eight loads in flight
+  // (the partials come from other XCDs' caches); fixed order for a given
+  // nparts and block size
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int nb = blockDim.x;
+  int p = threadIdx.x;
+  for (; p + 7 * nb < nparts; p += 8 * nb)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += a.partials[p + u * nb];
+  for (; p < nparts; p += nb) acc[0] += a.partials[p];
+  double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
