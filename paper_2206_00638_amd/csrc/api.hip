@@ -22,7 +22,7 @@
 namespace sbp {
 template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
-hipError_t launch_finish(const KArgs&, int, hipStream_t);
+hipError_t launch_finish(const KArgs&, int, int, hipStream_t);
 template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
 hipError_t launch_sources(const KArgs&, hipStream_t);
 template <typename T>
@@ -605,6 +605,7 @@ KArgs kargs(sbp_ctx* c) {
   a.ntiles = c->ntiles;
   a.cz = c->cz;
   a.order = tile_order(c);
+  a.hpoff = -1;
   a.pool = c->pool;
   a.pool2 = c->pool2;
   a.mat_eps = c->mat[0];
@@ -663,17 +664,22 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   }
   sbp_status st = mark();
   if (st != SBP_OK) return st;
-  int nparts = 0;
+  // partial sums: the H launches write slots [0, nh); each E workgroup adds
+  // the H partial of its tile (same tile list and grid) to its own, so the
+  // finish sums the E and one-pass slots [nh, nparts) only
+  int nparts = 0, hpoff[4] = {-1, -1, -1, -1};
+  a.hpoff = -1;
   for (int kind = 0; kind < 4; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
-    a.poff = nparts;
+    a.poff = hpoff[kind] = nparts;
     const int grid = grid_of(c, a.t1 - a.t0);
     nparts += grid;
     e = f64 ? launch_h<double>(a, kind, grid, threads, c->stream) : launch_h<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
+  const int nh = nparts;
   if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream)
@@ -686,11 +692,13 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
     a.poff = nparts;
+    a.hpoff = hpoff[kind];
     const int grid = grid_of(c, a.t1 - a.t0);
     nparts += grid;
     e = f64 ? launch_e<double>(a, kind, grid, threads, c->stream) : launch_e<float>(a, kind, grid, threads, c->stream);
     HIPCHK(c, e);
   }
+  a.hpoff = -1;
   if ((st = mark()) != SBP_OK) return st;
   if ((st = mark()) != SBP_OK) return st;
   if (c->fused) {
@@ -706,7 +714,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     }
   }
   if ((st = mark()) != SBP_OK) return st;
-  HIPCHK(c, launch_finish(a, nparts, c->stream));  // W^n into ring slot n; n += 1; sources of step n+1
+  HIPCHK(c, launch_finish(a, nh, nparts, c->stream));  // W^n into ring slot n; n += 1; sources of step n+1
   return SBP_OK;
 }
 

@@ -153,6 +153,8 @@ struct KArgs {
   int nblocks;
   int t0, t1;  // tile range of this launch
   int poff;    // first partial-sum slot of this launch
+  int hpoff;   // E launches: first slot of the H launch over the same tiles
+               // (its partial joins the E workgroup's), else -1
 };
 
 // Field pools of step n: the one it reads (the state E^n, H^{n-1/2}) and

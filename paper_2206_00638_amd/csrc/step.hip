@@ -41,6 +41,7 @@ __device__ void store_partial(double v, const KArgs& a) {
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += red[w];
+    if (a.hpoff >= 0) s += a.partials[a.hpoff + blockIdx.x];  // the H partial of the same tile
     a.partials[a.poff + blockIdx.x] = s;
   }
 }
@@ -61,17 +62,17 @@ __device__ __forceinline__ void eval_sources(const KArgs& a, long long n) {
 // after the state was replaced).
 __global__ __launch_bounds__(256) void k_sources(KArgs a) { eval_sources(a, a.st->step); }
 
-// End of step n: sums partials[0 .. nparts) (one workgroup, fixed order)
+// End of step n: sums partials[p0 .. nparts) (one workgroup, fixed order)
 // into energy ring slot n (W^n), flags a non-finite energy, advances the
 // step index and evaluates the source values of step n+1.
-__global__ __launch_bounds__(1024) void k_finish(KArgs a, int nparts) {
+__global__ __launch_bounds__(1024) void k_finish(KArgs a, int p0, int nparts) {
   __shared__ double red[16];
   // eight independent running sums per thread keep eight loads in flight
   // (the partials come from other XCDs' caches); fixed order for a given
   // nparts and block size
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nb = blockDim.x;
-  int p = threadIdx.x;
+  int p = p0 + threadIdx.x;
   for (; p + 7 * nb < nparts; p += 8 * nb)
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] += a.partials[p + u * nb];
@@ -1056,8 +1057,8 @@ hipError_t launch_fused(const KArgs& a, int kind, int grid, hipStream_t s) {
 template hipError_t launch_fused<float>(const KArgs&, int, int, hipStream_t);
 template hipError_t launch_fused<double>(const KArgs&, int, int, hipStream_t);
 
-hipError_t launch_finish(const KArgs& a, int nparts, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, nparts);
+hipError_t launch_finish(const KArgs& a, int p0, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, p0, nparts);
   return hipGetLastError();
 }
 hipError_t launch_sources(const KArgs& a, hipStream_t s) {
