@@ -589,3 +589,32 @@ def test_unstable_step_flagged(sbp):
         ctx.read_energy(2990, 10)
     assert e.value.status == SBP_EUNSTABLE
     ctx.close()
+
+
+def test_edge_cases_empty_and_maximum_sizes(sbp):
+    """Empty calls are no-ops, and a block whose component array would reach
+    4 GiB (the step kernels' 32-bit byte offsets) is refused before any
+    allocation, in both precisions; the largest block below the limit is
+    accepted."""
+    from paper_2206_00638_amd.binding import SBP_EINVAL, Context, SbpError
+    for prec, too_big, fits in (("f32", (1700, 1700, 400), (1600, 1600, 400)),
+                                ("f64", (1200, 1200, 400), (1100, 1100, 400))):
+        ctx = Context(prec)
+        with pytest.raises(SbpError) as e:
+            ctx.add_block(too_big, (1e-3,) * 3)
+        assert e.value.status == SBP_EINVAL
+        ctx.add_block(fits, (1e-3,) * 3)      # accepted (not finalized: nothing allocated)
+        ctx.close()
+    prob = {"blocks": [block((8, 9, 10))], "interfaces": [], "cfl": 0.9, "sources": [],
+            "probes": [{"block": 0, "comp": "Ez", "node": (2, 2, 2)}]}
+    ctx = sbp.build_problem(prob, prec="f64")
+    write_fields(ctx, random_fields(prob, 3))
+    before = gpu_fields(ctx, prob)
+    ctx.step(0)
+    assert ctx.steps_done() == 0
+    assert len(ctx.read_energy(0, 0)) == 0 and len(ctx.read_probe(0, 0, 0)) == 0
+    after = gpu_fields(ctx, prob)
+    assert all(np.array_equal(before[k], after[k]) for k in before)
+    ctx.step(3)
+    assert ctx.steps_done() == 3 and len(ctx.read_energy(0, 3)) == 3
+    ctx.close()
