@@ -136,6 +136,7 @@ struct sbp_ctx {
   int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
   Taps* d_taps = nullptr;
   int tx = 128, ty = 1, cz = 8, wgs = 0;  // launch shape (sbp_set_launch); fastest measured on 256^3 fp32
+  bool launch_set = false;                  // set by sbp_set_launch / sbp_autotune
   std::string err;
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
@@ -1116,6 +1117,17 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->finalized = true;
   sbp_status st = upload_materials(c);
   if (st != SBP_OK) return st;
+  if (!c->launch_set) {
+    // small problems: fewer than 2048 tiles of 8 planes leave CUs idle, and
+    // tiles of 4 planes fill them (96^3 step 27 -> 22 us); 2 planes per tile
+    // cost more in per-tile set-up than they gain
+    long long tiles = 0;
+    for (const HostBlock& b : c->blocks) {
+      const long long sxy = (long long)(b.n[0] + 2) * (b.n[1] + 2);
+      tiles += (sxy + c->tx * c->ty - 1) / (c->tx * c->ty) * ((b.n[2] + 2 + c->cz - 1) / c->cz);
+    }
+    if (tiles < 2048 && c->cz == 8) c->cz = 4;
+  }
   st = build_tiles(c);
   if (st != SBP_OK) return st;
   c->nstep = 0;
@@ -1160,6 +1172,7 @@ sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
   c->ty = ty;
   c->cz = cz;
   c->wgs = workgroups;
+  c->launch_set = true;
   if (c->finalized) return build_tiles(c);
   return SBP_OK;
 }
