@@ -111,7 +111,7 @@ struct sbp_ctx {
   std::vector<FTile> fbare;
   size_t bare_cap = 0;
   int ntiles = 0;
-  int kind_t0[4] = {0, 0, 0, 0}, kind_t1[4] = {0, 0, 0, 0};  // tile ranges per block kind
+  int kind_t0[8] = {}, kind_t1[8] = {};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
   int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
   FTile* d_ftiles = nullptr;
@@ -450,11 +450,16 @@ int grid_of(const sbp_ctx* c, int ntiles) {
 
 // Kind of a block for the step kernels: bit 0 = per-cell permittivity,
 // bit 1 = general (conductivity, absorbing faces, per-cell permeability or
-// interface faces); plain PEC/PMC blocks take the lean kernels.
+// interface faces), bit 2 = interface or periodic faces (the interface rows
+// are compiled only into that variant); plain PEC/PMC blocks take the lean
+// kernels.
 int block_kind(const HostBlock& b) {
-  bool gen = !b.mu.empty() || !b.sig.empty();
-  for (int f = 0; f < 6; ++f) gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
-  return (b.eps.empty() ? 0 : 1) | (gen ? 2 : 0);
+  bool gen = !b.mu.empty() || !b.sig.empty(), iface = false;
+  for (int f = 0; f < 6; ++f) {
+    iface = iface || b.iface[f] >= 0;
+    gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
+  }
+  return (b.eps.empty() ? 0 : 1) | (gen ? 2 : 0) | (iface ? 4 : 0);
 }
 
 // Windows of W node columns along an axis of s = n+2 nodes for the one-pass
@@ -484,7 +489,7 @@ void windows(int s, int n, int W, std::vector<int>& st, std::vector<int>& lo, st
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
   const int threads = c->tx * c->ty;
-  for (int kind = 0; kind < 4; ++kind) {
+  for (int kind = 0; kind < 8; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
@@ -570,7 +575,7 @@ sbp_status build_tiles(sbp_ctx* c) {
                              c->stream));
   }
   size_t sum = 0;
-  for (int kind = 0; kind < 4; ++kind)
+  for (int kind = 0; kind < 8; ++kind)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
   size_t fsum = 0;
   for (int kind = 0; kind < 2; ++kind)
@@ -668,9 +673,9 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   // partial sums: the H launches write slots [0, nh); each E workgroup adds
   // the H partial of its tile (same tile list and grid) to its own, so the
   // finish sums the E and one-pass slots [nh, nparts) only
-  int nparts = 0, hpoff[4] = {-1, -1, -1, -1};
+  int nparts = 0, hpoff[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   a.hpoff = -1;
-  for (int kind = 0; kind < 4; ++kind) {
+  for (int kind = 0; kind < 8; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
@@ -688,7 +693,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
-  for (int kind = 0; kind < 4; ++kind) {
+  for (int kind = 0; kind < 8; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];

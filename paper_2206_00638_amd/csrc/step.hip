@@ -320,7 +320,7 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 // components, with the closure / PEC / interface rows replacing the interior
 // differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
-template <typename T, bool GEN>
+template <typename T, bool GEN, bool IFACE>
 __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const HIn<T>& v,
@@ -341,18 +341,18 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
   if (!zin) {
     const TRow<T> rz = row_of<T>(Bc, 2, k, true);
     const long long fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
-    dzEy = drow<T, GEN>(a, Ey, o, sxy, rz, fo + bx * by);
-    dzEx = drow<T, GEN>(a, Ex, o, sxy, rz, fo);
+    dzEy = drow<T, IFACE>(a, Ey, o, sxy, rz, fo + bx * by);
+    dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo);
   }
   if (!yin) {
     const long long fo = fc.y + bx * k;
-    dyEz = drow<T, GEN>(a, Ez, o, sx, ry, fo + bx * bz);
-    dyEx = drow<T, GEN>(a, Ex, o, sx, ry, fo);
+    dyEz = drow<T, IFACE>(a, Ez, o, sx, ry, fo + bx * bz);
+    dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
   }
   if (!xin) {
     const long long fo = fc.x + by * k;
-    dxEz = drow<T, GEN>(a, Ez, o, 1, rx, fo + by * bz);
-    dxEy = drow<T, GEN>(a, Ey, o, 1, rx, fo);
+    dxEz = drow<T, IFACE>(a, Ez, o, 1, rx, fo + by * bz);
+    dxEy = drow<T, IFACE>(a, Ey, o, 1, rx, fo);
   }
   const T db_u = c.db_u, mu_r0 = c.mu_r0;
   T dbx = db_u, dby = db_u, dbz = db_u, mx = mu_r0, my = mu_r0, mz = mu_r0;
@@ -388,7 +388,7 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
 // one node per thread in flat (i, j, k) order, plus the H part of W^n:
 // 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
-template <typename T, bool GEN>
+template <typename T, bool GEN, bool IFACE>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, true), ry = row_of<T>(B, 1, j, true);  // D- rows of the column
     const W3<T> lw = h_col_weights<T>(c.nx, c.ny, i, j);
-    const FaceCol fc = GEN ? face_col(Bc, i, j, 3) : FaceCol{0, 0};  // D- rows: low face below 3
+    const FaceCol fc = IFACE ? face_col(Bc, i, j, 3) : FaceCol{0, 0};  // D- rows: low face below 3
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, i, j, k, o, true, v0,
+      es += (double)h_node<T, GEN, IFACE>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, i, j, k, o, true, v0,
                                    v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
@@ -558,7 +558,7 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 // the interior differences on the boundary rows; the absorbing damping
 // 2/(eta h) on tangential face nodes joins the semi-implicit loss.  Returns
 // the node's 4 eps_r (w/h^3) (E^n)^2 (the E part of W^n).
-template <typename T, bool HAS_EPS, bool GEN>
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE>
 __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const EIn<T>& v,
@@ -582,21 +582,21 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     if (k <= nz) {
       const TRow<T> rz = row_of<T>(Bc, 2, k, false);
       const long long fs = bx * by, fo = Bc.fboff[k < 2 ? 4 : 5] + i + bx * j + 2 * fs;
-      dzHy = drow<T, GEN>(a, Hy, o, sxy, rz, fo + fs);
-      dzHx = drow<T, GEN>(a, Hx, o, sxy, rz, fo);
+      dzHy = drow<T, IFACE>(a, Hy, o, sxy, rz, fo + fs);
+      dzHx = drow<T, IFACE>(a, Hx, o, sxy, rz, fo);
     } else {
       dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
     }
   }
   if (!yin) {
     const long long fs = bx * bz, fo = fc.y + bx * k + 2 * fs;
-    dyHz = drow<T, GEN>(a, Hz, o, sx, ry, fo + fs);
-    dyHx = drow<T, GEN>(a, Hx, o, sx, ry, fo);
+    dyHz = drow<T, IFACE>(a, Hz, o, sx, ry, fo + fs);
+    dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
   }
   if (!xin) {
     const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
-    dxHz = drow<T, GEN>(a, Hz, o, 1, rx, fo + fs);
-    dxHy = drow<T, GEN>(a, Hy, o, 1, rx, fo);
+    dxHz = drow<T, IFACE>(a, Hz, o, 1, rx, fo + fs);
+    dxHy = drow<T, IFACE>(a, Hy, o, 1, rx, fo);
   }
   const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
   const T eps_r0 = c.eps_r0;
@@ -677,7 +677,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // node per thread in flat (i, j, k) order, plus the E part of W^{n+1}:
 // 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
-template <typename T, bool HAS_EPS, bool GEN>
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const int j = q / (int)c.sx, i = q - j * (int)c.sx;
     const TRow<T> rx = row_of<T>(B, 0, i, false), ry = row_of<T>(B, 1, j, false);  // D+ rows of the column
     const W3<T> lw = e_col_weights<T>(c.nx, c.ny, i, j);
-    const FaceCol fc = GEN ? face_col(Bc, i, j, 2) : FaceCol{0, 0};  // D+ rows: low face below 2
+    const FaceCol fc = IFACE ? face_col(Bc, i, j, 2) : FaceCol{0, 0};  // D+ rows: low face below 2
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -741,7 +741,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc, i, j, k,
+      es += (double)e_node<T, HAS_EPS, GEN, IFACE>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc, i, j, k,
                                             o, jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
@@ -865,7 +865,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, FaceCol{0, 0},
+        const T eh = h_node<T, false, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, FaceCol{0, 0},
                                       i, j, kh, o, hown, v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
@@ -1031,20 +1031,24 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 
 // ------------------------------------------------------------- launchers
 // kind bit 0: per-cell permittivity; bit 1: general block (loss, absorbing
-// faces, per-cell permeability, interfaces).
+// faces, per-cell permeability or interfaces); bit 2: interface faces
+// (periodic faces included; implies bit 1).
 template <typename T>
 hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
-  if (kind & 2) hipLaunchKernelGGL((k_h_update<T, true>), dim3(grid), dim3(threads), 0, s, a);
-  else hipLaunchKernelGGL((k_h_update<T, false>), dim3(grid), dim3(threads), 0, s, a);
+  if (kind & 4) hipLaunchKernelGGL((k_h_update<T, true, true>), dim3(grid), dim3(threads), 0, s, a);
+  else if (kind & 2) hipLaunchKernelGGL((k_h_update<T, true, false>), dim3(grid), dim3(threads), 0, s, a);
+  else hipLaunchKernelGGL((k_h_update<T, false, false>), dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
-  switch (kind & 3) {
-    case 0: hipLaunchKernelGGL((k_e_update<T, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_e_update<T, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_e_update<T, false, true>), dim3(grid), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_e_update<T, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
+  switch (kind & 7) {
+    case 0: hipLaunchKernelGGL((k_e_update<T, false, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_e_update<T, true, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_e_update<T, false, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_e_update<T, true, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_e_update<T, false, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_e_update<T, true, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
   }
   return hipGetLastError();
 }
