@@ -34,8 +34,8 @@ hipError_t launch_adj_grad(const void*, const void*, const void*, long long, dou
 template <typename T>
 hipError_t launch_adj_cells(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
 template <typename T>
-hipError_t launch_gather(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int, double*,
-                         hipStream_t);
+hipError_t launch_gather(const DevBlock*, const FaceJob*, const GatherWG*, int, const Taps*, const KArgs&, int,
+                         double*, hipStream_t);
 }  // namespace sbp
 
 using namespace sbp;
@@ -133,7 +133,10 @@ struct sbp_ctx {
   size_t face_elems = 1;
   FaceJob* d_jobs_e = nullptr;
   FaceJob* d_jobs_h = nullptr;
-  int njobs_e = 0, njobs_h = 0, max_face_nodes = 0;
+  int njobs_e = 0, njobs_h = 0;
+  GatherWG* d_wg_e = nullptr;  // per-workgroup job tables of the two gathers
+  GatherWG* d_wg_h = nullptr;
+  int nwg_e = 0, nwg_h = 0;
   Taps* d_taps = nullptr;
   int tx = 128, ty = 1, cz = 8, wgs = 0;  // launch shape (sbp_set_launch); fastest measured on 256^3 fp32
   bool launch_set = false;                  // set by sbp_set_launch / sbp_autotune
@@ -664,8 +667,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   // kinds stepped by the two-pass kernels: all, or only the general ones
   auto two_pass = [&](int kind) { return c->kind_t1[kind] > c->kind_t0[kind] && (!c->fused || (kind & 2)); };
   if (c->njobs_e) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->njobs_e, c->max_face_nodes, c->d_taps, a, 0, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream);
     HIPCHK(c, e);
   }
   sbp_status st = mark();
@@ -688,8 +691,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   const int nh = nparts;
   if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->njobs_h, c->max_face_nodes, c->d_taps, a, 1, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream);
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
@@ -1059,7 +1062,6 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   // interface gather jobs
   std::vector<FaceJob> je, jh;
   std::vector<Taps> taps;
-  int maxn = 0;
   for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
     const HostBlock& b = c->blocks[bi];
     for (int f = 0; f < 6; ++f) {
@@ -1100,17 +1102,31 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
             if (!axis_taps(plus, b.n[ta[q]], role, taps))
               return fail(c, SBP_EINVAL, "interface interpolation wider than the tap limit");
           }
-          maxn = std::max(maxn, J.ext[0] * J.ext[1]);
+          J.unit = role == 0 ? 1 : 0;
           (is_h ? jh : je).push_back(J);
         }
     }
   }
   c->njobs_e = (int)je.size();
   c->njobs_h = (int)jh.size();
-  c->max_face_nodes = maxn;
+  // each job's face nodes in runs of 256, one workgroup per run
+  auto wg_table = [](const std::vector<FaceJob>& jobs) {
+    std::vector<GatherWG> t;
+    for (size_t q = 0; q < jobs.size(); ++q)
+      for (int f = 0; f < jobs[q].ext[0] * jobs[q].ext[1]; f += 256) t.push_back(GatherWG{(int)q, f});
+    return t;
+  };
+  const std::vector<GatherWG> we = wg_table(je), wh = wg_table(jh);
+  c->nwg_e = (int)we.size();
+  c->nwg_h = (int)wh.size();
   if (!je.empty()) {
     c->d_jobs_e = (FaceJob*)dalloc(c, je.size() * sizeof(FaceJob));
     c->d_jobs_h = (FaceJob*)dalloc(c, jh.size() * sizeof(FaceJob));
+    c->d_wg_e = (GatherWG*)dalloc(c, we.size() * sizeof(GatherWG));
+    c->d_wg_h = (GatherWG*)dalloc(c, wh.size() * sizeof(GatherWG));
+    if (!c->d_wg_e || !c->d_wg_h) return fail(c, SBP_ENOMEM, "device allocation failed");
+    HIPCHK(c, hipMemcpyAsync(c->d_wg_e, we.data(), we.size() * sizeof(GatherWG), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_wg_h, wh.data(), wh.size() * sizeof(GatherWG), hipMemcpyHostToDevice, c->stream));
     c->d_taps = (Taps*)dalloc(c, taps.size() * sizeof(Taps));
     if (!c->d_jobs_e || !c->d_jobs_h || !c->d_taps) return fail(c, SBP_ENOMEM, "device allocation failed");
     HIPCHK(c, hipMemcpyAsync(c->d_jobs_e, je.data(), je.size() * sizeof(FaceJob), hipMemcpyHostToDevice, c->stream));

@@ -113,9 +113,16 @@ struct FaceJob {
                         // fields: the other part), or -1
   double w1, w2;        // value = w1 * (nb's face) + w2 * (nb2's face)
   int nb_idx;           // face-normal node index of the neighbour face
+  int unit;             // 1: same mesh on both tangential axes (no taps)
   int t_axis[2];        // tangential axes (ascending)
   int ext[2];           // own face-node extents along the tangential axes
   long long taps_off[2];  // offsets into the tap table for each tangential axis
+};
+
+// One workgroup of a face gather: job index and first face node (a job's
+// nodes are split into runs of 256, one per workgroup).
+struct GatherWG {
+  int job, first;
 };
 
 struct StepState {

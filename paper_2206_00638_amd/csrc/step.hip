@@ -989,38 +989,50 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
 // Accumulated in fp64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, const FaceJob* jobs,
-                                                     const Taps* taps, const void* pool0, const void* pool1,
-                                                     const StepState* stp, int from_out, double* face) {
+                                                     const GatherWG* wgs, const Taps* taps, const void* pool0,
+                                                     const void* pool1, const StepState* stp, int from_out,
+                                                     double* face) {
   // E^n lives in the pool step n reads, H^{n+1/2} in the one it writes
   const long long n = stp->step;
   const void* pool = ((n & 1) != from_out) ? pool1 : pool0;
-  const FaceJob J = jobs[blockIdx.y];
+  const GatherWG W = wgs[blockIdx.x];
+  const FaceJob J = jobs[W.job];
   const DevBlock& B = blocks[J.block];
   const DevBlock& N = blocks[J.nb];
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long id = (long long)W.first + threadIdx.x;
   const long long tot = (long long)J.ext[0] * J.ext[1];
   if (id >= tot) return;
   const int r0 = (int)(id % J.ext[0]), r1 = (int)(id / J.ext[0]);
-  const Taps& T0 = taps[J.taps_off[0] + r0];
-  const Taps& T1 = taps[J.taps_off[1] + r1];
   const long long st[3] = {1, N.sx, N.sxy};
   const int axis = J.face >> 1;
   const long long onrm = (long long)J.nb_idx * st[axis];
-  // the interpolated face value of one source block (nb2 has nb's geometry)
-  auto gather = [&](const DevBlock& S) {
-    const T* nf = (const T*)pool + S.foff + (long long)J.comp * S.csz;
-    double v = 0.0;
-    for (int q = 0; q < T1.count; ++q) {
-      double s = 0.0;
-      const long long o1 = onrm + (long long)(T1.start + q) * st[J.t_axis[1]];
-      for (int p = 0; p < T0.count; ++p)
-        s += T0.w[p] * (double)nf[o1 + (long long)(T0.start + p) * st[J.t_axis[0]]];
-      v += T1.w[q] * s;
+  const long long s0 = st[J.t_axis[0]], s1 = st[J.t_axis[1]];
+  double v;
+  if (J.unit) {  // same mesh: the coincident node itself
+    const long long o = onrm + (long long)r0 * s0 + (long long)r1 * s1;
+    v = J.w1 * (double)((const T*)pool + N.foff + (long long)J.comp * N.csz)[o];
+    if (J.nb2 >= 0) {
+      const DevBlock& M = blocks[J.nb2];
+      v += J.w2 * (double)((const T*)pool + M.foff + (long long)J.comp * M.csz)[o];
     }
-    return v;
-  };
-  double v = J.w1 * gather(N);
-  if (J.nb2 >= 0) v += J.w2 * gather(blocks[J.nb2]);
+  } else {
+    const Taps& T0 = taps[J.taps_off[0] + r0];
+    const Taps& T1 = taps[J.taps_off[1] + r1];
+    // the interpolated face value of one source block (nb2 has nb's geometry)
+    auto gather = [&](const DevBlock& S) {
+      const T* nf = (const T*)pool + S.foff + (long long)J.comp * S.csz;
+      double acc = 0.0;
+      for (int q = 0; q < T1.count; ++q) {
+        double sum = 0.0;
+        const long long o1 = onrm + (long long)(T1.start + q) * s1;
+        for (int p = 0; p < T0.count; ++p) sum += T0.w[p] * (double)nf[o1 + (long long)(T0.start + p) * s0];
+        acc += T1.w[q] * sum;
+      }
+      return acc;
+    };
+    v = J.w1 * gather(N);
+    if (J.nb2 >= 0) v += J.w2 * gather(blocks[J.nb2]);
+  }
   // own face-node index in the node-box face layout
   const int bx = B.n[0] + 2, by = B.n[1] + 2;
   long long fidx;
@@ -1070,12 +1082,11 @@ hipError_t launch_sources(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_gather(const DevBlock* blocks, const FaceJob* jobs, int njobs, int max_nodes,
+hipError_t launch_gather(const DevBlock* blocks, const FaceJob* jobs, const GatherWG* wgs, int nwg,
                          const Taps* taps, const KArgs& a, int from_out, double* face, hipStream_t s) {
-  if (njobs == 0) return hipSuccess;
-  dim3 grid((max_nodes + 255) / 256, njobs);
-  hipLaunchKernelGGL(k_face_gather<T>, grid, dim3(256), 0, s, blocks, jobs, taps, a.pool, a.pool2, a.st, from_out,
-                     face);
+  if (nwg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_gather<T>, dim3(nwg), dim3(256), 0, s, blocks, jobs, wgs, taps, a.pool, a.pool2, a.st,
+                     from_out, face);
   return hipGetLastError();
 }
 
@@ -1083,9 +1094,9 @@ template hipError_t launch_h<float>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_h<double>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_e<float>(const KArgs&, int, int, int, hipStream_t);
 template hipError_t launch_e<double>(const KArgs&, int, int, int, hipStream_t);
-template hipError_t launch_gather<float>(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int,
+template hipError_t launch_gather<float>(const DevBlock*, const FaceJob*, const GatherWG*, int, const Taps*, const KArgs&, int,
                                         double*, hipStream_t);
-template hipError_t launch_gather<double>(const DevBlock*, const FaceJob*, int, int, const Taps*, const KArgs&, int,
+template hipError_t launch_gather<double>(const DevBlock*, const FaceJob*, const GatherWG*, int, const Taps*, const KArgs&, int,
                                          double*, hipStream_t);
 
 }  // namespace sbp
