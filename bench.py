@@ -270,6 +270,41 @@ def accuracy(scale):
     return out
 
 
+def copy_ceiling():
+    """Same-harness references for HBM bandwidth on 1 GiB fp32 arrays (far
+    above the 256 MB Infinity Cache): a device-to-device copy (one read and
+    one write per element) and torch's vectorised elementwise add c = a + b
+    (two reads, one write); bytes moved over the best of 5 runs, timed with
+    torch.cuda events on the current stream."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.ones(n, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+
+    def best(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            t = ms if t is None else min(t, ms)
+        return t
+
+    t_copy = best(lambda: c.copy_(a))
+    t_add = best(lambda: torch.add(a, b, out=c))
+    del a, b, c
+    gb = (1 << 30) / 1e9
+    return {"copy_gbs": 2 * gb / (t_copy * 1e-3), "add_gbs": 3 * gb / (t_add * 1e-3),
+            "note": "1 GiB fp32 arrays: device-to-device copy (1 read + 1 write) and c = a + b (2 reads + 1 write)"}
+
+
 def cpu_baseline(problem, target_s=15.0):
     """The loop oracle (plain C, OpenMP) on the host cores, on a bounded
     sample of the workload: the full block for a few steps."""
@@ -365,6 +400,7 @@ def main():
         out["batched"] = batched(args.steps, max(args.warmup, 100))
     if not args.no_subgrid:
         out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+    out["copy_ceiling"] = copy_ceiling()
     if not args.no_bloch:
         out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_adjoint:
