@@ -135,6 +135,7 @@ class Context:
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to torch")
         self._lib = lib()
+        self.imag_part = {}  # block -> block holding its imaginary part (Bloch-periodic faces)
         dev = torch.cuda.current_device() if device is None else device
         torch.cuda.set_device(dev)
         st = torch.cuda.current_stream(dev) if stream is None else stream
@@ -174,6 +175,8 @@ class Context:
         """Both faces of `axis` periodic with the Bloch phase e^{-j alpha};
         alpha != 0 needs `block_im`, the block holding the imaginary part."""
         self._chk(self._lib.sbp_set_periodic(self.h, int(block), int(block_im), int(axis), float(alpha)))
+        if block_im >= 0:
+            self.imag_part[int(block)] = int(block_im)
 
     def add_source(self, block, comp, node, waveform, tw, t0, f0=0.0, amp=1.0):
         p = (ctypes.c_double * 3)(tw, t0, f0)
@@ -311,7 +314,6 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
     # axis has complex fields: a twin block, appended after the problem's
     # blocks, holds the imaginary part (ctx.imag_part[block])
     periodic = [(int(b), int(a), float(al)) for (b, a, al) in problem.get("periodic", [])]
-    ctx.imag_part = {}
     for b in sorted({b for (b, _, al) in periodic if al != 0.0}):
         src = problem["blocks"][b]
         tw = ctx.add_block(src["n"], src["h"], src.get("origin", (0.0, 0.0, 0.0)), src.get("eps_r"),
