@@ -25,6 +25,10 @@ dispersion / dissipation / global errors), for the SBP-SAT scheme with
 periodic faces (EPBC1-EPBC6) and, to pin the procedure, for the classical
 Yee scheme against its closed-form dispersion relation.
 
+``cpml``: convolutional perfectly matched layers on the SBP-SAT differences
+(the truncation the paper's open examples use), pinned by the plain scheme
+at zero strength and by absorption against a larger domain.
+
 ``adjoint``: the discrete adjoint of the leapfrog step in the matrix form
 (explicit transposes), giving the gradient of a region objective with
 respect to the per-cell permittivity; pinned by central finite differences

@@ -79,7 +79,7 @@ CHI_PMC = {("Ex", "t"): +1, ("Ex", "d"): -1, ("Ex", "r"): -1, ("Ex", "l"): +1,
            ("Ey", "b"): -1, ("Ey", "f"): +1, ("Ey", "t"): -1, ("Ey", "d"): +1,
            ("Ez", "b"): +1, ("Ez", "f"): -1, ("Ez", "r"): +1, ("Ez", "l"): -1}
 
-BC_PEC, BC_PMC, BC_ABC, BC_IFACE = "pec", "pmc", "abc", "iface"
+BC_PEC, BC_PMC, BC_ABC, BC_IFACE, BC_CPML = "pec", "pmc", "abc", "iface", "cpml"
 
 
 def cfl_dt(blocks, cfl, c=C0):
@@ -315,7 +315,10 @@ class System:
 
     def _assemble(self):
         abc_diag = np.zeros(self.ne)
-        blocks_eh, blocks_he = [], []
+        # terms kept per axis of their difference (the face normal for the
+        # penalties): K = K_0 + K_1 + K_2, used by the stretched-coordinate
+        # absorbing layers (oracle.cpml)
+        per_eh, per_he = ([], [], []), ([], [], [])
 
         def place(rows_off, cols_off, m, nrows, ncols, store):
             coo = m.tocoo()
@@ -335,14 +338,17 @@ class System:
                     m = sgn * axis_operator(tgt, src, axis, n, h)
                     if tgt in E_COMPS:
                         place(self.e_off[(b, tgt)], self.h_off[(b, src)], m,
-                              self.ne, self.nh, blocks_eh)
+                              self.ne, self.nh, per_eh[axis])
                     else:
                         place(self.h_off[(b, tgt)], self.e_off[(b, src)], m,
-                              self.nh, self.ne, blocks_he)
+                              self.nh, self.ne, per_he[axis])
             # penalties, face by face
             for face in range(6):
                 axis = face // 2
+                blocks_eh, blocks_he = per_eh[axis], per_he[axis]
                 bc = self._bc(b, face)
+                if bc == BC_CPML:   # a PEC face behind the absorbing layer
+                    bc = BC_PEC
                 letter = FACE_LETTER[face]
                 # H equations: tangential E on the face (E13-E15 / EPBC1-3)
                 for hc in H_COMPS:
@@ -397,10 +403,13 @@ class System:
                                   -0.5 * chi * self.face_phase.get((b, face), 1.0) * sat
                                   @ self._face_interp(b, face, hc) @ face_select(hc, nn, fnb),
                                   self.ne, self.nh, blocks_eh)
-        self.K_eh = build(blocks_eh, (self.ne, self.nh))
-        self.K_he = build(blocks_he, (self.nh, self.ne))
-        self.K_eh.eliminate_zeros()
-        self.K_he.eliminate_zeros()
+        empty = [(np.zeros(0), np.zeros(0, int), np.zeros(0, int))]
+        self.K_eh_ax = [build(per_eh[a] + empty, (self.ne, self.nh)) for a in range(3)]
+        self.K_he_ax = [build(per_he[a] + empty, (self.nh, self.ne)) for a in range(3)]
+        self.K_eh = self.K_eh_ax[0] + self.K_eh_ax[1] + self.K_eh_ax[2]
+        self.K_he = self.K_he_ax[0] + self.K_he_ax[1] + self.K_he_ax[2]
+        for m in self.K_eh_ax + self.K_he_ax + [self.K_eh, self.K_he]:
+            m.eliminate_zeros()
         self.abc = abc_diag  # geometric damping rate coefficient (x 1/eps -> 1/s)
 
     # ----------------------------------------------------- vectors <-> fields
