@@ -172,6 +172,37 @@ def bloch(steps, warmup):
             "step_hbm_gbs_algorithmic": 2 * (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
+def cpml_leg(steps, warmup):
+    """The dielectric-boxes 256^3 fp32 workload with every face a PEC face
+    behind a 10-cell convolutional PML (the truncation of the paper's open
+    examples) instead of a PEC cavity wall."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(2)
+    prob["blocks"][0]["faces"] = ["cpml"] * 6
+    prob["cpml"] = {"cells": 10}
+    cells = int(np.prod(prob["blocks"][0]["n"]))
+    stream = torch.cuda.Stream()
+    ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(True)
+    ctx.step(20)
+    torch.cuda.synchronize()
+    kern = ctx.kernel_ms()
+    ctx.close()
+    ms = wall * 1e3 / steps
+    return {"workload": "dielectric-boxes-256^3-fp32-cpml10", "cells": cells, "steps": steps,
+            "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
+            "kernels_ms": list(kern)}
+
+
 def subgrid(steps, warmup):
     """The 1:2 subgrid workload: 27 blocks (coarse 192^3 region at 1 mm around
     a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box, fp32."""
@@ -339,6 +370,7 @@ def main():
     ap.add_argument("--no-subgrid", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-bloch", action="store_true")
+    ap.add_argument("--no-cpml", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -401,6 +433,8 @@ def main():
     if not args.no_subgrid:
         out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
     out["copy_ceiling"] = copy_ceiling()
+    if not args.no_cpml:
+        out["cpml"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_bloch:
         out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_adjoint:

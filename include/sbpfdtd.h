@@ -48,8 +48,10 @@ typedef enum { SBP_FP64 = 0, SBP_FP32 = 1 } sbp_prec;
 
 /* Face treatments (Section III): PEC and PMC penalties (E13-E15 / E18,
  * E19-E21 / E23); SBP_ABC1 is a first-order absorbing (characteristic)
- * penalty, which the paper does not have (it truncates with CPML). */
-typedef enum { SBP_PEC = 0, SBP_PMC = 1, SBP_ABC1 = 2 } sbp_bc;
+ * penalty, which the paper does not have; SBP_CPML is a PEC face behind a
+ * convolutional perfectly matched layer (the truncation of the paper's
+ * Section VI examples; see sbp_set_cpml). */
+typedef enum { SBP_PEC = 0, SBP_PMC = 1, SBP_ABC1 = 2, SBP_CPML = 3 } sbp_bc;
 
 typedef enum { SBP_EX = 0, SBP_EY, SBP_EZ, SBP_HX, SBP_HY, SBP_HZ } sbp_comp;
 
@@ -107,6 +109,22 @@ sbp_status sbp_connect(sbp_ctx *ctx, int blk_a, int face_a, int blk_b, int face_
  * with interfaces, or a face already coupled; SBP_ESTATE after
  * sbp_finalize. */
 sbp_status sbp_set_periodic(sbp_ctx *ctx, int block, int block_im, int axis, double alpha);
+
+/* Layer parameters of the faces set to SBP_CPML (before sbp_finalize; the
+ * defaults are 10, 3, 0.8, 1, 0).  Inside a layer of `cells` cells next to
+ * such a face every difference along the face normal (the SBP operator with
+ * its closure rows and the face's PEC penalty) becomes d/kappa + psi, with
+ * psi <- b psi + c d advanced once per half step.  At depth rho in [0, 1]
+ * into the layer (1 on the face): sigma = sigma_factor (order+1)/(eta0 h)
+ * rho^order, kappa = 1 + (kappa_max - 1) rho^order, alpha = alpha_max
+ * (1 - rho) (S/m); b = exp(-(sigma/kappa + alpha) dt/eps0), c = sigma (b - 1)
+ * / (sigma kappa + kappa^2 alpha), at each node's own position (grids of
+ * Table T1).  The psi are part of the saved state.  Blocks with layers are
+ * rejected by sbp_adjoint.  Errors: SBP_EINVAL for cells < 1, order outside
+ * 1..8, sigma_factor < 0, kappa_max < 1 or alpha_max < 0; SBP_ESTATE after
+ * sbp_finalize. */
+sbp_status sbp_set_cpml(sbp_ctx *ctx, int cells, int order, double sigma_factor, double kappa_max,
+                        double alpha_max);
 
 /* Soft source (a current density inside the E update) on node (i,j,k) of an
  * E component; p = {tw, t0, f0} in seconds / Hz; evaluated at (n+1/2) dt. */

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libsbpfdtd.so")
 
 SBP_OK, SBP_EINVAL, SBP_ENOMEM, SBP_EHIP, SBP_ESTATE, SBP_EUNSTABLE, SBP_ERANGE = 0, -1, -2, -3, -4, -5, -6
 SBP_FP64, SBP_FP32 = 0, 1
-BC = {"pec": 0, "pmc": 1, "abc": 2}
+BC = {"pec": 0, "pmc": 1, "abc": 2, "cpml": 3}
 COMPS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
 WAVE = {"gauss": 0, "modgauss": 1}
 STATUS_NAMES = {0: "SBP_OK", -1: "SBP_EINVAL", -2: "SBP_ENOMEM", -3: "SBP_EHIP", -4: "SBP_ESTATE",
@@ -39,6 +39,7 @@ SIGNATURES = {
     "sbp_set_face_bc": [_P, _I, _I, _I],
     "sbp_connect": [_P, _I, _I, _I, _I, _I],
     "sbp_set_periodic": [_P, _I, _I, _I, _D],
+    "sbp_set_cpml": [_P, _I, _I, _D, _D, _D],
     "sbp_add_source": [_P, _I, _I, _I, _I, _I, _I, _DP, _D, _IP],
     "sbp_add_probe": [_P, _I, _I, _I, _I, _I, _IP],
     "sbp_finalize": [_P, _D, _I, _L, _DP],
@@ -178,6 +179,11 @@ class Context:
         if block_im >= 0:
             self.imag_part[int(block)] = int(block_im)
 
+    def set_cpml(self, cells=10, m=3, sigma_factor=0.8, kappa_max=1.0, alpha_max=0.0):
+        """Parameters of the convolutional PML behind faces set to "cpml"."""
+        self._chk(self._lib.sbp_set_cpml(self.h, int(cells), int(m), float(sigma_factor), float(kappa_max),
+                                         float(alpha_max)))
+
     def add_source(self, block, comp, node, waveform, tw, t0, f0=0.0, amp=1.0):
         p = (ctypes.c_double * 3)(tw, t0, f0)
         sid = ctypes.c_int()
@@ -310,6 +316,8 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
                 ctx.set_face_bc(bid, f, bc)
     for (a, fa, b, fb, r) in problem.get("interfaces", []):
         ctx.connect(a, fa, b, fb, r)
+    if "cpml" in problem:
+        ctx.set_cpml(**problem["cpml"])
     # periodic axes (block, axis, alpha); a block with a nonzero phase on any
     # axis has complex fields: a twin block, appended after the problem's
     # blocks, holds the imaginary part (ctx.imag_part[block])

@@ -111,7 +111,7 @@ struct sbp_ctx {
   std::vector<FTile> fbare;
   size_t bare_cap = 0;
   int ntiles = 0;
-  int kind_t0[8] = {}, kind_t1[8] = {};  // tile ranges per block kind
+  int kind_t0[16] = {}, kind_t1[16] = {};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
   int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
   FTile* d_ftiles = nullptr;
@@ -130,6 +130,13 @@ struct sbp_ctx {
   size_t partials_cap = 0;
   StepState* d_st = nullptr;
   double* d_face = nullptr;
+  // convolutional PML (faces set to SBP_CPML): layer parameters, per-block
+  // profile tables and recursion variables, both in the field type
+  int pml_cells = 10, pml_m = 3;
+  double pml_sigma_factor = 0.8, pml_kappa_max = 1.0, pml_alpha_max = 0.0;
+  void* d_pml = nullptr;
+  void* d_psi = nullptr;
+  size_t psi_elems = 0;
   size_t face_elems = 1;
   FaceJob* d_jobs_e = nullptr;
   FaceJob* d_jobs_h = nullptr;
@@ -213,6 +220,48 @@ Row mkrow(int s, double c0, double c1, double c2, double ih) {
   return r;
 }
 
+// Convolutional PML profiles of a block: for axis a, grid g ("+" 0, "-" 1)
+// and quantity q (0: b, 1: c, 2: 1/kappa), P entries per node index (the
+// "+" grid's node n+1 and any index past the grid are neutral: 1, 0, 1).
+// At depth rho in [0, 1] into a layer of `cells` cells next to a face set to
+// SBP_CPML: sigma = sigma_max rho^m with sigma_max = sigma_factor (m+1) /
+// (eta0 h), kappa = 1 + (kappa_max - 1) rho^m, alpha = alpha_max (1 - rho);
+// b = exp(-(sigma/kappa + alpha) dt/eps0), c = sigma (b-1) / (sigma kappa +
+// kappa^2 alpha).  Node positions: "+" grid i h, "-" grid 0, (j-1/2) h, n h.
+void pml_profiles(const sbp_ctx* c, const HostBlock& b, int P, std::vector<double>& out) {
+  const double eta0 = std::sqrt(kMu0 / kEps0);
+  for (int a = 0; a < 3; ++a) {
+    const int n = b.n[a];
+    const double h = b.h[a], L = n * h;
+    const bool lo = b.iface[2 * a] < 0 && b.faces[2 * a] == SBP_CPML;
+    const bool hi = b.iface[2 * a + 1] < 0 && b.faces[2 * a + 1] == SBP_CPML;
+    const double d = c->pml_cells * h;
+    const double smax = c->pml_sigma_factor * (c->pml_m + 1) / (eta0 * h);
+    for (int g = 0; g < 2; ++g) {
+      std::vector<double> vb(P, 1.0), vc(P, 0.0), vk(P, 1.0);
+      const int cnt = g == 0 ? n + 1 : n + 2;
+      for (int idx = 0; idx < cnt; ++idx) {
+        const double x = g == 0 ? idx * h : (idx == 0 ? 0.0 : (idx == n + 1 ? L : (idx - 0.5) * h));
+        double rho = 0.0;
+        if (lo) rho = std::max(rho, std::min(std::max((d - x) / d, 0.0), 1.0));
+        if (hi) rho = std::max(rho, std::min(std::max((x - (L - d)) / d, 0.0), 1.0));
+        if (rho <= 0.0) continue;
+        const double rm = std::pow(rho, c->pml_m);
+        const double sig = smax * rm, kap = 1.0 + (c->pml_kappa_max - 1.0) * rm;
+        const double alp = c->pml_alpha_max * (1.0 - rho);
+        const double bb = std::exp(-(sig / kap + alp) * c->dt / kEps0);
+        const double den = sig * kap + kap * kap * alp;
+        vb[idx] = bb;
+        vc[idx] = sig > 0.0 ? sig * (bb - 1.0) / den : 0.0;
+        vk[idx] = 1.0 / kap;
+      }
+      out.insert(out.end(), vb.begin(), vb.end());
+      out.insert(out.end(), vc.begin(), vc.end());
+      out.insert(out.end(), vk.begin(), vk.end());
+    }
+  }
+}
+
 void build_rows(const HostBlock& b, DevBlock& d) {
   for (int a = 0; a < 3; ++a) {
     const int n = b.n[a];
@@ -250,14 +299,14 @@ void build_rows(const HostBlock& b, DevBlock& d) {
       d.dm[a][0].cn = d.dm[a][0].c[0];
       d.dm[a][0].c[0] = 0.0;
       d.dm[a][0].nbr = 1;
-    } else if (flo == SBP_PEC) {
+    } else if (flo == SBP_PEC || flo == SBP_CPML) {  // a PEC face behind an absorbing layer
       d.dm[a][0].c[0] = -d.dm[a][0].c[0];
     }
     if (ihi) {
       d.dm[a][5].cn = d.dm[a][5].c[2];
       d.dm[a][5].c[2] = 0.0;
       d.dm[a][5].nbr = 1;
-    } else if (fhi == SBP_PEC) {
+    } else if (fhi == SBP_PEC || fhi == SBP_CPML) {
       d.dm[a][5].c[2] = -d.dm[a][5].c[2];
     }
   }
@@ -452,17 +501,24 @@ int grid_of(const sbp_ctx* c, int ntiles) {
 }
 
 // Kind of a block for the step kernels: bit 0 = per-cell permittivity,
-// bit 1 = general (conductivity, absorbing faces, per-cell permeability or
-// interface faces), bit 2 = interface or periodic faces (the interface rows
-// are compiled only into that variant); plain PEC/PMC blocks take the lean
-// kernels.
+// bit 1 = general (conductivity, absorbing faces, per-cell permeability,
+// interface faces or absorbing layers), bit 2 = interface or periodic faces
+// (the interface rows are compiled only into that variant), bit 3 = CPML
+// layers; plain PEC/PMC blocks take the lean kernels.
+bool has_pml(const HostBlock& b) {
+  for (int f = 0; f < 6; ++f)
+    if (b.iface[f] < 0 && b.faces[f] == SBP_CPML) return true;
+  return false;
+}
+
 int block_kind(const HostBlock& b) {
   bool gen = !b.mu.empty() || !b.sig.empty(), iface = false;
   for (int f = 0; f < 6; ++f) {
     iface = iface || b.iface[f] >= 0;
     gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
   }
-  return (b.eps.empty() ? 0 : 1) | (gen ? 2 : 0) | (iface ? 4 : 0);
+  const bool pml = has_pml(b);
+  return (b.eps.empty() ? 0 : 1) | (gen || pml ? 2 : 0) | (iface ? 4 : 0) | (pml ? 8 : 0);
 }
 
 // Windows of W node columns along an axis of s = n+2 nodes for the one-pass
@@ -492,7 +548,7 @@ void windows(int s, int n, int W, std::vector<int>& st, std::vector<int>& lo, st
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
   const int threads = c->tx * c->ty;
-  for (int kind = 0; kind < 8; ++kind) {
+  for (int kind = 0; kind < 16; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
@@ -578,7 +634,7 @@ sbp_status build_tiles(sbp_ctx* c) {
                              c->stream));
   }
   size_t sum = 0;
-  for (int kind = 0; kind < 8; ++kind)
+  for (int kind = 0; kind < 16; ++kind)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
   size_t fsum = 0;
   for (int kind = 0; kind < 2; ++kind)
@@ -621,6 +677,8 @@ KArgs kargs(sbp_ctx* c) {
   a.mat_mu = c->mat[1];
   a.mat_sig = c->mat[2];
   a.face = c->d_face;
+  a.pml_prof = c->d_pml;
+  a.psi = c->d_psi;
   a.src = c->d_src;
   a.srcval = c->d_srcval;
   a.nsrc = c->nsrc_total;
@@ -676,9 +734,10 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   // partial sums: the H launches write slots [0, nh); each E workgroup adds
   // the H partial of its tile (same tile list and grid) to its own, so the
   // finish sums the E and one-pass slots [nh, nparts) only
-  int nparts = 0, hpoff[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  int nparts = 0, hpoff[16];
+  for (int& v : hpoff) v = -1;
   a.hpoff = -1;
-  for (int kind = 0; kind < 8; ++kind) {
+  for (int kind = 0; kind < 16; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
@@ -696,7 +755,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
-  for (int kind = 0; kind < 8; ++kind) {
+  for (int kind = 0; kind < 16; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
@@ -815,7 +874,7 @@ sbp_status sbp_set_face_bc(sbp_ctx* c, int block, int face, sbp_bc bc) {
   if (!c) return SBP_EINVAL;
   if (c->finalized) return fail(c, SBP_ESTATE, "set_face_bc after finalize");
   if (!check_block(c, block) || face < 0 || face > 5) return fail(c, SBP_EINVAL, "bad block or face");
-  if (bc != SBP_PEC && bc != SBP_PMC && bc != SBP_ABC1) return fail(c, SBP_EINVAL, "bad face treatment");
+  if (bc != SBP_PEC && bc != SBP_PMC && bc != SBP_ABC1 && bc != SBP_CPML) return fail(c, SBP_EINVAL, "bad face treatment");
   c->blocks[block].faces[face] = bc;
   return SBP_OK;
 }
@@ -952,7 +1011,8 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   std::vector<Probe> dprb;
   c->hblocks.assign(c->blocks.size(), DevBlock());
   c->probe_order.assign(c->prbs.size(), 0);
-  size_t foff = 0, coff = 0, fboff = 0;
+  size_t foff = 0, coff = 0, fboff = 0, psi = 0;
+  std::vector<double> pml;
   for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
     HostBlock& b = c->blocks[bi];
     DevBlock& d = c->hblocks[bi];
@@ -992,6 +1052,13 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
       }
     }
     build_rows(b, d);
+    if (has_pml(b)) {  // twelve psi arrays (six H, six E terms) over the node box
+      d.pml_stride = std::max(b.n[0], std::max(b.n[1], b.n[2])) + 2;
+      d.pml_off = (long long)pml.size();
+      pml_profiles(c, b, d.pml_stride, pml);
+      d.psi_off = (long long)psi;
+      psi += 12 * (size_t)d.csz;
+    }
     d.db_u = c->dt / (kMu0 * d.mu_r0);
     d.cb_u = c->dt / (kEps0 * d.eps_r0);
     d.dte0x4 = 4.0 * c->dt / kEps0;
@@ -1046,6 +1113,19 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->d_st = (StepState*)dalloc(c, sizeof(StepState));
   c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
   c->face_elems = std::max<size_t>(fboff, 1);
+  c->psi_elems = psi;
+  c->d_pml = dalloc(c, std::max<size_t>(pml.size(), 1) * elem_size(c));
+  c->d_psi = dalloc(c, std::max<size_t>(psi, 1) * elem_size(c));
+  if (!c->d_pml || !c->d_psi) return fail(c, SBP_ENOMEM, "device allocation failed");
+  if (!pml.empty()) {
+    if (c->prec == SBP_FP64) {
+      HIPCHK(c, hipMemcpy(c->d_pml, pml.data(), pml.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(pml.begin(), pml.end());
+      HIPCHK(c, hipMemcpy(c->d_pml, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_psi, 0, std::max<size_t>(psi, 1) * elem_size(c), c->stream));
   if (!c->pool || !c->pool2 || !c->d_blocks || !c->d_src || !c->d_srcval || !c->d_prb || !c->d_energy || !c->d_probes || !c->d_st || !c->d_face)
     return fail(c, SBP_ENOMEM, "device allocation failed");
   HIPCHK(c, hipMemsetAsync(c->pool, 0, foff * elem_size(c), c->stream));
@@ -1195,6 +1275,20 @@ sbp_status sbp_set_launch(sbp_ctx* c, int tx, int ty, int cz, int workgroups) {
   c->wgs = workgroups;
   c->launch_set = true;
   if (c->finalized) return build_tiles(c);
+  return SBP_OK;
+}
+
+sbp_status sbp_set_cpml(sbp_ctx* c, int cells, int order, double sigma_factor, double kappa_max, double alpha_max) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "set_cpml after finalize");
+  if (cells < 1 || order < 1 || order > 8 || !(sigma_factor >= 0.0) || !(kappa_max >= 1.0) || !(alpha_max >= 0.0) ||
+      !std::isfinite(sigma_factor) || !std::isfinite(kappa_max) || !std::isfinite(alpha_max))
+    return fail(c, SBP_EINVAL, "CPML: cells >= 1, 1 <= order <= 8, sigma_factor >= 0, kappa_max >= 1, alpha_max >= 0");
+  c->pml_cells = cells;
+  c->pml_m = order;
+  c->pml_sigma_factor = sigma_factor;
+  c->pml_kappa_max = kappa_max;
+  c->pml_alpha_max = alpha_max;
   return SBP_OK;
 }
 
@@ -1367,7 +1461,7 @@ sbp_status sbp_read_probe(sbp_ctx* c, int id, long first, long count, double* ds
 sbp_status sbp_state_bytes(const sbp_ctx* c, size_t* bytes) {
   if (!c || !bytes) return SBP_EINVAL;
   if (!c->finalized) return SBP_ESTATE;
-  *bytes = c->pool_elems * elem_size(c) + 256;
+  *bytes = c->pool_elems * elem_size(c) + 256 + c->psi_elems * elem_size(c);  // fields, step state, CPML psi
   return SBP_OK;
 }
 
@@ -1381,6 +1475,9 @@ sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
                            c->stream));
   HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c), c->d_st, sizeof(StepState),
                            hipMemcpyDeviceToDevice, c->stream));
+  if (c->psi_elems)
+    HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c) + 256, c->d_psi,
+                             c->psi_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
   return SBP_OK;
 }
 
@@ -1396,6 +1493,9 @@ sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpyAsync(pool_at(c, st.step), dev_buf, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice,
                            c->stream));
+  if (c->psi_elems)
+    HIPCHK(c, hipMemcpyAsync(c->d_psi, (const char*)dev_buf + c->pool_elems * elem_size(c) + 256,
+                             c->psi_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
   st.counter = 0;
   st.flags = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
@@ -1515,7 +1615,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   for (const HostBlock& b : c->blocks) {
     bool lossy = false;
     for (double v : b.sig) lossy = lossy || v != 0.0;
-    for (int f = 0; f < 6; ++f) lossy = lossy || (b.iface[f] < 0 && b.faces[f] == SBP_ABC1);
+    for (int f = 0; f < 6; ++f) lossy = lossy || (b.iface[f] < 0 && (b.faces[f] == SBP_ABC1 || b.faces[f] == SBP_CPML));
     if (lossy) return fail(c, SBP_EINVAL, "the adjoint covers lossless blocks (no conductivity, no absorbing faces)");
   }
   long K = ckpt_every > 0 ? ckpt_every : (long)std::ceil(std::sqrt((double)nsteps));

@@ -40,6 +40,11 @@ struct DevBlock {
   Row dm[3][DM_ROWS];
   int abc_mask;         // bit f: face f absorbing
   int iface_mask;       // bit f: face f coupled to another block
+  int pml_stride;       // absorbing layers: entries per profile (max n + 2), 0 if none
+  long long pml_off;    // profile table offset: (b, c, 1/kappa) of axis a, grid g
+                        // ("+" 0, "-" 1), quantity q at pml_off + ((a*2+g)*3+q)*stride + idx
+  long long psi_off;    // psi arrays of the layers: slot s (0-5 H terms, 6-11 E terms)
+                        // of node offset o at psi_off + s*csz + o
   long long fboff[6];   // face-buffer offset (doubles): E slot 0,1 then H slot 0,1
   long long fsz[6];     // nodes per slot of the face buffer (node-box face)
   int src0, nsrc, prb0, nprb;
@@ -146,6 +151,8 @@ struct KArgs {
   const void* mat_mu;
   const void* mat_sig;
   const double* face;
+  const void* pml_prof;  // absorbing-layer profiles (field type)
+  void* psi;             // absorbing-layer recursion variables (field type)
   const Source* src;
   double* srcval;  // current density of each source at (n+1/2) dt of the step
   int nsrc;        // sources over all blocks

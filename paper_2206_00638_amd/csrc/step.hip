@@ -235,6 +235,30 @@ __device__ __forceinline__ FaceCol face_col(const SBP_CONST DevBlock& Bc, int i,
   return FaceCol{(i < lo ? Bc.fboff[0] : Bc.fboff[1]) + j, (j < lo ? Bc.fboff[2] : Bc.fboff[3]) + i};
 }
 
+// Absorbing layers (convolutional PML): profile value q (0: b, 1: c,
+// 2: 1/kappa) of axis `axis`, grid g (0: "+", 1: "-") at node index idx.
+template <typename T>
+__device__ __forceinline__ T pml_at(const KArgs& a, const SBP_CONST DevBlock& Bc, int axis, int g, int q, int idx) {
+  return ((const T*)a.pml_prof)[Bc.pml_off + (long long)((axis * 2 + g) * 3 + q) * Bc.pml_stride + idx];
+}
+// A node column's x and y profile values (hoisted out of the march).
+template <typename T>
+struct PmlCol {
+  T bx, cx, kx, by, cy, ky;
+};
+template <typename T>
+__device__ __forceinline__ PmlCol<T> pml_col(const KArgs& a, const SBP_CONST DevBlock& Bc, int g, int i, int j) {
+  return PmlCol<T>{pml_at<T>(a, Bc, 0, g, 0, i), pml_at<T>(a, Bc, 0, g, 1, i), pml_at<T>(a, Bc, 0, g, 2, i),
+                   pml_at<T>(a, Bc, 1, g, 0, j), pml_at<T>(a, Bc, 1, g, 1, j), pml_at<T>(a, Bc, 1, g, 2, j)};
+}
+// Stretched difference inside a layer: psi <- b psi + c d, d <- d / kappa + psi.
+template <typename T>
+__device__ __forceinline__ void stretch(T& d, T b, T c, T ik, T* psi) {
+  const T p = b * *psi + c * d;
+  *psi = p;
+  d = d * ik + p;
+}
+
 // Element `idx` of a component array addressed as the (wave-uniform) array
 // base plus a 32-bit byte offset, so that an access costs one vector offset
 // instead of a 64-bit address.  Component arrays stay below 4 GiB (checked
@@ -320,14 +344,15 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 // components, with the closure / PEC / interface rows replacing the interior
 // differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
-template <typename T, bool GEN, bool IFACE>
+template <typename T, bool GEN, bool IFACE, bool PML>
 __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
-                                    T* __restrict__ Hz, const T* __restrict__ M, const FaceCol& fc, int i,
-                                    int j, int k, long long o, bool store, T& onx, T& ony, T& onz) {
+                                    T* __restrict__ Hz, const T* __restrict__ M, const FaceCol& fc,
+                                    const PmlCol<T>& pc, int i, int j, int k, long long o, bool store, T& onx,
+                                    T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -353,6 +378,23 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     const long long fo = fc.x + by * k;
     dxEz = drow<T, IFACE>(a, Ez, o, 1, rx, fo + by * bz);
     dxEy = drow<T, IFACE>(a, Ey, o, 1, rx, fo);
+  }
+  if constexpr (PML) {  // absorbing layers: H terms sit on the "-" grid of their axis
+    T* ps = (T*)a.psi + Bc.psi_off + o;  // slots 0-5: (Hx,z) (Hx,y) (Hy,x) (Hy,z) (Hz,y) (Hz,x)
+    const long long cs = Bc.csz;
+    const T bzp = pml_at<T>(a, Bc, 2, 1, 0, k), czp = pml_at<T>(a, Bc, 2, 1, 1, k), kzp = pml_at<T>(a, Bc, 2, 1, 2, k);
+    if (czp != T(0) || kzp != T(1)) {
+      stretch(dzEy, bzp, czp, kzp, ps);
+      stretch(dzEx, bzp, czp, kzp, ps + 3 * cs);
+    }
+    if (pc.cy != T(0) || pc.ky != T(1)) {
+      stretch(dyEz, pc.by, pc.cy, pc.ky, ps + cs);
+      stretch(dyEx, pc.by, pc.cy, pc.ky, ps + 4 * cs);
+    }
+    if (pc.cx != T(0) || pc.kx != T(1)) {
+      stretch(dxEz, pc.bx, pc.cx, pc.kx, ps + 2 * cs);
+      stretch(dxEy, pc.bx, pc.cx, pc.kx, ps + 5 * cs);
+    }
   }
   const T db_u = c.db_u, mu_r0 = c.mu_r0;
   T dbx = db_u, dby = db_u, dbz = db_u, mx = mu_r0, my = mu_r0, mz = mu_r0;
@@ -388,7 +430,7 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
 // one node per thread in flat (i, j, k) order, plus the H part of W^n:
 // 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
-template <typename T, bool GEN, bool IFACE>
+template <typename T, bool GEN, bool IFACE, bool PML>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -413,6 +455,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
     const TRow<T> rx = row_of<T>(B, 0, i, true), ry = row_of<T>(B, 1, j, true);  // D- rows of the column
     const W3<T> lw = h_col_weights<T>(c.nx, c.ny, i, j);
     const FaceCol fc = IFACE ? face_col(Bc, i, j, 3) : FaceCol{0, 0};  // D- rows: low face below 3
+    const PmlCol<T> pc = PML ? pml_col<T>(a, Bc, 1, i, j) : PmlCol<T>{};
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -440,8 +483,8 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2;
-      es += (double)h_node<T, GEN, IFACE>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, i, j, k, o, true, v0,
-                                   v1, v2);
+      es += (double)h_node<T, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, i, j, k,
+                                               o, true, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -558,15 +601,15 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 // the interior differences on the boundary rows; the absorbing damping
 // 2/(eta h) on tangential face nodes joins the semi-implicit loss.  Returns
 // the node's 4 eps_r (w/h^3) (E^n)^2 (the E part of W^n).
-template <typename T, bool HAS_EPS, bool GEN, bool IFACE>
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML>
 __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const EIn<T>& v,
                                     T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
                                     const T* __restrict__ Hx, const T* __restrict__ Hy,
                                     const T* __restrict__ Hz, const T* __restrict__ MS, const FaceCol& fc,
-                                    int i, int j, int k, long long o, T jx, T jy, T jz, T& onx, T& ony,
-                                    T& onz) {
+                                    const PmlCol<T>& pc, int i, int j, int k, long long o, T jx, T jy, T jz,
+                                    T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -597,6 +640,26 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
     dxHz = drow<T, IFACE>(a, Hz, o, 1, rx, fo + fs);
     dxHy = drow<T, IFACE>(a, Hy, o, 1, rx, fo);
+  }
+  if constexpr (PML) {  // absorbing layers: E terms sit on the "+" grid of their axis
+    T* ps = (T*)a.psi + Bc.psi_off + 6 * Bc.csz + o;  // slots 6-11: (Ex,y) (Ex,z) (Ey,z) (Ey,x) (Ez,x) (Ez,y)
+    const long long cs = Bc.csz;
+    if (k <= nz) {
+      const T bzp = pml_at<T>(a, Bc, 2, 0, 0, k), czp = pml_at<T>(a, Bc, 2, 0, 1, k),
+              kzp = pml_at<T>(a, Bc, 2, 0, 2, k);
+      if (czp != T(0) || kzp != T(1)) {
+        stretch(dzHy, bzp, czp, kzp, ps + cs);
+        stretch(dzHx, bzp, czp, kzp, ps + 2 * cs);
+      }
+    }
+    if (pc.cy != T(0) || pc.ky != T(1)) {
+      stretch(dyHz, pc.by, pc.cy, pc.ky, ps);
+      stretch(dyHx, pc.by, pc.cy, pc.ky, ps + 5 * cs);
+    }
+    if (pc.cx != T(0) || pc.kx != T(1)) {
+      stretch(dxHz, pc.bx, pc.cx, pc.kx, ps + 3 * cs);
+      stretch(dxHy, pc.bx, pc.cx, pc.kx, ps + 4 * cs);
+    }
   }
   const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
   const T eps_r0 = c.eps_r0;
@@ -677,7 +740,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // node per thread in flat (i, j, k) order, plus the E part of W^{n+1}:
 // 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
-template <typename T, bool HAS_EPS, bool GEN, bool IFACE>
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -703,6 +766,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const TRow<T> rx = row_of<T>(B, 0, i, false), ry = row_of<T>(B, 1, j, false);  // D+ rows of the column
     const W3<T> lw = e_col_weights<T>(c.nx, c.ny, i, j);
     const FaceCol fc = IFACE ? face_col(Bc, i, j, 2) : FaceCol{0, 0};  // D+ rows: low face below 2
+    const PmlCol<T> pc = PML ? pml_col<T>(a, Bc, 0, i, j) : PmlCol<T>{};
     const int k0 = tz0, k1 = min(tz0 + a.cz, c.nz + 2);
     const T* Ex = base;
     const T* Ey = base + csz;
@@ -741,8 +805,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       T v0, v1, v2;
-      es += (double)e_node<T, HAS_EPS, GEN, IFACE>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc, i, j, k,
-                                            o, jx, jy, jz, v0, v1, v2);
+      es += (double)e_node<T, HAS_EPS, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc,
+                                                        pc, i, j, k, o, jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -865,8 +929,8 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr, FaceCol{0, 0},
-                                      i, j, kh, o, hown, v0, v1, v2);
+        const T eh = h_node<T, false, false, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr,
+                                                    FaceCol{0, 0}, PmlCol<T>{}, i, j, kh, o, hown, v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
           if (tflags & 2) take_probes<T>(a, B, i, j, kh, true, nstep, v0, v1, v2);
@@ -1043,24 +1107,35 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 
 // ------------------------------------------------------------- launchers
 // kind bit 0: per-cell permittivity; bit 1: general block (loss, absorbing
-// faces, per-cell permeability or interfaces); bit 2: interface faces
-// (periodic faces included; implies bit 1).
+// faces, per-cell permeability, interfaces or absorbing layers); bit 2:
+// interface faces (periodic faces included); bit 3: absorbing layers.  Bits
+// 2 and 3 imply bit 1.
 template <typename T>
 hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
-  if (kind & 4) hipLaunchKernelGGL((k_h_update<T, true, true>), dim3(grid), dim3(threads), 0, s, a);
-  else if (kind & 2) hipLaunchKernelGGL((k_h_update<T, true, false>), dim3(grid), dim3(threads), 0, s, a);
-  else hipLaunchKernelGGL((k_h_update<T, false, false>), dim3(grid), dim3(threads), 0, s, a);
+  const dim3 g(grid), b(threads);
+  switch (kind & 14) {
+    case 0: hipLaunchKernelGGL((k_h_update<T, false, false, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_h_update<T, true, false, false>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_h_update<T, true, true, false>), g, b, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_h_update<T, true, false, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_h_update<T, true, true, true>), g, b, 0, s, a); break;
+  }
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
-  switch (kind & 7) {
-    case 0: hipLaunchKernelGGL((k_e_update<T, false, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_e_update<T, true, false, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_e_update<T, false, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_e_update<T, true, true, false>), dim3(grid), dim3(threads), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_e_update<T, false, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_e_update<T, true, true, true>), dim3(grid), dim3(threads), 0, s, a); break;
+  const dim3 g(grid), b(threads);
+  switch (kind & 15) {
+    case 0: hipLaunchKernelGGL((k_e_update<T, false, false, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_e_update<T, true, false, false, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_e_update<T, false, true, false, false>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_e_update<T, true, true, false, false>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_e_update<T, false, true, true, false>), g, b, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_e_update<T, true, true, true, false>), g, b, 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_e_update<T, false, true, false, true>), g, b, 0, s, a); break;
+    case 11: hipLaunchKernelGGL((k_e_update<T, true, true, false, true>), g, b, 0, s, a); break;
+    case 14: hipLaunchKernelGGL((k_e_update<T, false, true, true, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_e_update<T, true, true, true, true>), g, b, 0, s, a); break;
   }
   return hipGetLastError();
 }
