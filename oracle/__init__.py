@@ -29,6 +29,10 @@ Yee scheme against its closed-form dispersion relation.
 (the truncation the paper's open examples use), pinned by the plain scheme
 at zero strength and by absorption against a larger domain.
 
+``tfsf``: total-field / scattered-field plane-wave injection from a
+one-dimensional incident line, pinned by an empty scattered region (to
+rounding) in vacuum.
+
 ``adjoint``: the discrete adjoint of the leapfrog step in the matrix form
 (explicit transposes), giving the gradient of a region objective with
 respect to the per-cell permittivity; pinned by central finite differences
