@@ -110,6 +110,29 @@ sbp_status sbp_connect(sbp_ctx *ctx, int blk_a, int face_a, int blk_b, int face_
  * sbp_finalize. */
 sbp_status sbp_set_periodic(sbp_ctx *ctx, int block, int block_im, int axis, double alpha);
 
+/* Total-field / scattered-field plane-wave injection (Section VI brings
+ * the incident wave of its examples in this way).  `box` = {ilo, ihi, jlo,
+ * jhi, klo, khi} is a box of cells of `block`, at least 4 cells inside it on
+ * every side (and at least cells + 4 inside any SBP_CPML face); nodes on or
+ * inside it carry the total field, the others the scattered field.  Each
+ * difference that couples nodes of the two regions takes the neighbour's
+ * value in the node's own convention, i.e. adds or removes the incident
+ * field there (inside the Cb bracket for E).  The incident wave travels
+ * along +axis with E along `pol` (an E component across the axis); it comes
+ * from a one-dimensional line stepped on the device with the same dt, h,
+ * eps0 and mu0 (the interior difference of the axis; PEC ends) over node
+ * indices -margin .. n[axis] + margin, driven by a soft current source of
+ * waveform `w`, p = {tw, t0, f0}, on line node src_cell (in
+ * 1 - margin .. n[axis] + margin - 1), evaluated at (n+1/2) dt.  The line is
+ * part of the saved state.  One box per context, before sbp_finalize; the
+ * block takes no interface or periodic faces; sbp_adjoint rejects it.
+ * Errors: SBP_EINVAL for a bad block, axis, polarisation, box, margin
+ * (1 .. 2^20), source cell, waveform or width (and at sbp_finalize for a box
+ * too close to absorbing layers or a block with interface or periodic
+ * faces); SBP_ESTATE for a second box or after sbp_finalize. */
+sbp_status sbp_set_tfsf(sbp_ctx *ctx, int block, const int box[6], int axis, sbp_comp pol, int margin,
+                        int src_cell, sbp_wave w, const double p[3], double amplitude);
+
 /* Layer parameters of the faces set to SBP_CPML (before sbp_finalize; the
  * defaults are 10, 3, 0.8, 1, 0).  Inside a layer of `cells` cells next to
  * such a face every difference along the face normal (the SBP operator with

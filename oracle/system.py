@@ -256,7 +256,10 @@ class System:
     def _bc(self, b, face):
         if (b, face) in self.face_link:
             return BC_IFACE
-        return self.blocks[b]["faces"][face]
+        bc = self.blocks[b]["faces"][face]
+        if bc not in (BC_PEC, BC_PMC, BC_ABC, BC_IFACE, BC_CPML):
+            raise ValueError(f"unknown face condition {bc!r}")
+        return bc
 
     def _materials(self):
         self.eps = np.zeros(self.ne)

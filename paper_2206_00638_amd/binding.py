@@ -40,6 +40,7 @@ SIGNATURES = {
     "sbp_connect": [_P, _I, _I, _I, _I, _I],
     "sbp_set_periodic": [_P, _I, _I, _I, _D],
     "sbp_set_cpml": [_P, _I, _I, _D, _D, _D],
+    "sbp_set_tfsf": [_P, _I, _IP, _I, _I, _I, _I, _I, _DP, _D],
     "sbp_add_source": [_P, _I, _I, _I, _I, _I, _I, _DP, _D, _IP],
     "sbp_add_probe": [_P, _I, _I, _I, _I, _I, _IP],
     "sbp_finalize": [_P, _D, _I, _L, _DP],
@@ -184,6 +185,15 @@ class Context:
         self._chk(self._lib.sbp_set_cpml(self.h, int(cells), int(m), float(sigma_factor), float(kappa_max),
                                          float(alpha_max)))
 
+    def set_tfsf(self, block, box, axis, pol, cell, waveform, tw, t0, f0=0.0, amp=1.0, margin=16):
+        """Total-field / scattered-field box (cells lo/hi per axis) with a
+        plane wave along +axis, E along component `pol` (0-2), from a line
+        source on line node `cell`."""
+        b = (ctypes.c_int * 6)(*[int(v) for v in box])
+        p = (ctypes.c_double * 3)(tw, t0, f0)
+        self._chk(self._lib.sbp_set_tfsf(self.h, int(block), b, int(axis), int(pol), int(margin), int(cell),
+                                         WAVE[waveform], p, float(amp)))
+
     def add_source(self, block, comp, node, waveform, tw, t0, f0=0.0, amp=1.0):
         p = (ctypes.c_double * 3)(tw, t0, f0)
         sid = ctypes.c_int()
@@ -312,8 +322,11 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
         bid = ctx.add_block(b["n"], b["h"], b.get("origin", (0.0, 0.0, 0.0)), b.get("eps_r"),
                             b.get("mu_r"), b.get("sigma"))
         for f, bc in enumerate(b["faces"]):
-            if bc in BC:
-                ctx.set_face_bc(bid, f, bc)
+            if bc == "iface":  # coupled by the interface list below
+                continue
+            if bc not in BC:
+                raise ValueError(f"unknown face condition {bc!r}")
+            ctx.set_face_bc(bid, f, bc)
     for (a, fa, b, fb, r) in problem.get("interfaces", []):
         ctx.connect(a, fa, b, fb, r)
     if "cpml" in problem:
@@ -332,6 +345,11 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
         ctx.imag_part[b] = tw
     for (b, a, al) in periodic:
         ctx.set_periodic(b, a, al, ctx.imag_part.get(b, -1))
+    if "tfsf" in problem:
+        tf = problem["tfsf"]
+        src = tf["source"]
+        ctx.set_tfsf(tf["block"], tf["box"], tf["axis"], tf["pol"], src["cell"], src["waveform"], src["tw"],
+                     src["t0"], src.get("f0", 0.0), src.get("amp", 1.0), tf.get("margin", 16))
     for s in problem.get("sources", []):
         ctx.add_source(s["block"], s["comp"], s["node"], s["waveform"], s["tw"], s["t0"], s.get("f0", 0.0),
                        s.get("amp", 1.0))

@@ -25,6 +25,7 @@ template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream
 hipError_t launch_finish(const KArgs&, int, int, hipStream_t);
 template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
 hipError_t launch_sources(const KArgs&, hipStream_t);
+hipError_t launch_line(const KArgs&, int, hipStream_t);
 template <typename T>
 hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, double, double*, hipStream_t);
 template <typename T>
@@ -56,6 +57,7 @@ struct HostBlock {
   // complex fields (periodic faces with a Bloch phase): the block holding
   // the other part, and whether this block holds the imaginary part
   int part_of = -1, imag = 0;
+  int tfsf = 0;  // holds the total-field / scattered-field box
 };
 
 // A coupled pair of faces.  Interfaces join two blocks; a periodic axis
@@ -111,7 +113,7 @@ struct sbp_ctx {
   std::vector<FTile> fbare;
   size_t bare_cap = 0;
   int ntiles = 0;
-  int kind_t0[16] = {}, kind_t1[16] = {};  // tile ranges per block kind
+  int kind_t0[32] = {}, kind_t1[32] = {};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
   int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
   FTile* d_ftiles = nullptr;
@@ -145,6 +147,15 @@ struct sbp_ctx {
   GatherWG* d_wg_h = nullptr;
   int nwg_e = 0, nwg_h = 0;
   Taps* d_taps = nullptr;
+  // total-field / scattered-field injection (sbp_set_tfsf): the block, cell
+  // box, propagation axis, E polarisation, line margin, the incident source
+  // (its cell on the line) and the device line (E then H, fp64)
+  bool tf_on = false;
+  int tf_block = -1, tf_box[6] = {0, 0, 0, 0, 0, 0}, tf_axis = 0, tf_pol = 0, tf_margin = 16, tf_cell = 0;
+  Source tf_srcdef{};
+  int tf_sidx = 0, tf_len = 0;
+  double* d_line = nullptr;
+  TfDesc* d_tf = nullptr;
   int tx = 128, ty = 1, cz = 8, wgs = 0;  // launch shape (sbp_set_launch); fastest measured on 256^3 fp32
   bool launch_set = false;                  // set by sbp_set_launch / sbp_autotune
   std::string err;
@@ -195,6 +206,8 @@ void dfree(sbp_ctx* c, void* p) {
 }
 
 size_t elem_size(const sbp_ctx* c) { return c->prec == SBP_FP64 ? 8 : 4; }
+// Bytes of the TF/SF incident line (E then H, fp64).
+size_t line_bytes(const sbp_ctx* c) { return c->tf_on ? (2 * (size_t)c->tf_len + 1) * sizeof(double) : 0; }
 
 // grid type per component and axis: true = "+" (n+1 nodes), false = "-" (n+2), Table T1
 const bool kPlus[6][3] = {{false, true, true}, {true, false, true}, {true, true, false},
@@ -504,7 +517,8 @@ int grid_of(const sbp_ctx* c, int ntiles) {
 // bit 1 = general (conductivity, absorbing faces, per-cell permeability,
 // interface faces or absorbing layers), bit 2 = interface or periodic faces
 // (the interface rows are compiled only into that variant), bit 3 = CPML
-// layers; plain PEC/PMC blocks take the lean kernels.
+// layers, bit 4 = the TF/SF box (its corrections are compiled only into
+// that variant); plain PEC/PMC blocks take the lean kernels.
 bool has_pml(const HostBlock& b) {
   for (int f = 0; f < 6; ++f)
     if (b.iface[f] < 0 && b.faces[f] == SBP_CPML) return true;
@@ -518,7 +532,8 @@ int block_kind(const HostBlock& b) {
     gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
   }
   const bool pml = has_pml(b);
-  return (b.eps.empty() ? 0 : 1) | (gen || pml ? 2 : 0) | (iface ? 4 : 0) | (pml ? 8 : 0);
+  gen = gen || b.tfsf;
+  return (b.eps.empty() ? 0 : 1) | (gen || pml ? 2 : 0) | (iface ? 4 : 0) | (pml ? 8 : 0) | (b.tfsf ? 16 : 0);
 }
 
 // Windows of W node columns along an axis of s = n+2 nodes for the one-pass
@@ -545,10 +560,28 @@ void windows(int s, int n, int W, std::vector<int>& st, std::vector<int>& lo, st
   for (int t = 0; t < T; ++t) hi[t] = t < T - 1 ? lo[t + 1] - 1 : s - 1;
 }
 
+// Whether a tile of the TF/SF block holds a node that the box surface
+// couples across (bit 2 of the tile flags): such nodes have all indices in
+// [lo-1, hi+1] and one of them in {lo-1, lo, hi, hi+1}.
+bool tf_tile(const sbp_ctx* c, long long sx, long long q0, int threads, int z0, int cz, long long sxy) {
+  const int* bx = c->tf_box;
+  auto near = [&](int v, int a) { return v >= bx[2 * a] - 1 && v <= bx[2 * a + 1] + 1; };
+  auto edge = [&](int v, int a) { return v <= bx[2 * a] || v >= bx[2 * a + 1]; };
+  const long long q1 = std::min<long long>(q0 + threads, sxy);
+  for (int k = z0; k < z0 + cz; ++k) {
+    if (!near(k, 2)) continue;
+    for (long long q = q0; q < q1; ++q) {
+      const int j = (int)(q / sx), i = (int)(q - j * sx);
+      if (near(i, 0) && near(j, 1) && (edge(i, 0) || edge(j, 1) || edge(k, 2))) return true;
+    }
+  }
+  return false;
+}
+
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
   const int threads = c->tx * c->ty;
-  for (int kind = 0; kind < 16; ++kind) {
+  for (int kind = 0; kind < 32; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
@@ -566,6 +599,7 @@ sbp_status build_tiles(sbp_ctx* c) {
             if (sr.block == (int)bi && inside(sr.s.i, sr.s.j, sr.s.k)) flags |= 1;
           for (auto& pr : c->prbs)
             if (pr.block == (int)bi && inside(pr.p.i, pr.p.j, pr.p.k)) flags |= 2;
+          if (b.tfsf && tf_tile(c, sx, q0, threads, z0, c->cz, sxy)) flags |= 4;
           tl.push_back(Tile{(int)bi, (int)q0, z0, flags});
         }
     }
@@ -634,7 +668,7 @@ sbp_status build_tiles(sbp_ctx* c) {
                              c->stream));
   }
   size_t sum = 0;
-  for (int kind = 0; kind < 16; ++kind)
+  for (int kind = 0; kind < 32; ++kind)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
   size_t fsum = 0;
   for (int kind = 0; kind < 2; ++kind)
@@ -696,6 +730,7 @@ KArgs kargs(sbp_ctx* c) {
   a.t0 = 0;
   a.t1 = c->ntiles;
   a.poff = 0;
+  a.tf = c->tf_on ? c->d_tf : nullptr;
   return a;
 }
 
@@ -734,10 +769,10 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   // partial sums: the H launches write slots [0, nh); each E workgroup adds
   // the H partial of its tile (same tile list and grid) to its own, so the
   // finish sums the E and one-pass slots [nh, nparts) only
-  int nparts = 0, hpoff[16];
+  int nparts = 0, hpoff[32];
   for (int& v : hpoff) v = -1;
   a.hpoff = -1;
-  for (int kind = 0; kind < 16; ++kind) {
+  for (int kind = 0; kind < 32; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
@@ -748,6 +783,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   const int nh = nparts;
+  if (a.tf) HIPCHK(c, launch_line(a, 0, c->stream));  // incident line: H^{n+1/2}
   if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream)
@@ -755,7 +791,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
-  for (int kind = 0; kind < 16; ++kind) {
+  for (int kind = 0; kind < 32; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = c->kind_t0[kind];
     a.t1 = c->kind_t1[kind];
@@ -767,6 +803,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   a.hpoff = -1;
+  if (a.tf) HIPCHK(c, launch_line(a, 1, c->stream));  // incident line: E^{n+1} (source of step n)
   if ((st = mark()) != SBP_OK) return st;
   if ((st = mark()) != SBP_OK) return st;
   if (c->fused) {
@@ -954,6 +991,42 @@ sbp_status sbp_set_periodic(sbp_ctx* c, int block, int block_im, int axis, doubl
   return SBP_OK;
 }
 
+sbp_status sbp_set_tfsf(sbp_ctx* c, int block, const int box[6], int axis, sbp_comp pol, int margin, int src_cell,
+                        sbp_wave w, const double p[3], double amplitude) {
+  if (!c) return SBP_EINVAL;
+  if (c->finalized) return fail(c, SBP_ESTATE, "set_tfsf after finalize");
+  if (c->tf_on) return fail(c, SBP_ESTATE, "one TF/SF box per context");
+  if (!check_block(c, block) || !box) return fail(c, SBP_EINVAL, "bad block");
+  if (axis < 0 || axis > 2) return fail(c, SBP_EINVAL, "bad axis");
+  if (pol < SBP_EX || pol > SBP_EZ || (int)pol == axis) return fail(c, SBP_EINVAL, "the polarisation is an E component across the axis");
+  HostBlock& b = c->blocks[block];
+  for (int a = 0; a < 3; ++a)
+    if (box[2 * a] < 4 || box[2 * a + 1] > b.n[a] - 4 || box[2 * a] >= box[2 * a + 1])
+      return fail(c, SBP_EINVAL, "the TF/SF box must lie at least 4 cells inside the block");
+  if (margin < 1 || margin > (1 << 20)) return fail(c, SBP_EINVAL, "margin must be in 1 .. 2^20");
+  const int L = b.n[axis] + 2 * margin;
+  if (src_cell + margin < 1 || src_cell + margin > L - 1) return fail(c, SBP_EINVAL, "source cell outside the line");
+  if (w != SBP_GAUSS && w != SBP_MODGAUSS) return fail(c, SBP_EINVAL, "bad waveform");
+  if (!p || !(p[0] > 0)) return fail(c, SBP_EINVAL, "source width must be positive");
+  c->tf_on = true;
+  c->tf_block = block;
+  for (int f = 0; f < 6; ++f) c->tf_box[f] = box[f];
+  c->tf_axis = axis;
+  c->tf_pol = pol;
+  c->tf_margin = margin;
+  c->tf_cell = src_cell;
+  std::memset(&c->tf_srcdef, 0, sizeof(Source));
+  c->tf_srcdef.comp = pol;
+  c->tf_srcdef.i = c->tf_srcdef.j = c->tf_srcdef.k = -1;  // on no block node
+  c->tf_srcdef.wave = w;
+  c->tf_srcdef.tw = p[0];
+  c->tf_srcdef.t0 = p[1];
+  c->tf_srcdef.f0 = p[2];
+  c->tf_srcdef.amp = amplitude;
+  b.tfsf = 1;
+  return SBP_OK;
+}
+
 sbp_status sbp_add_source(sbp_ctx* c, int block, sbp_comp comp, int i, int j, int k, sbp_wave w,
                           const double p[3], double amplitude, int* id) {
   if (!c) return SBP_EINVAL;
@@ -1099,6 +1172,20 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
       if (cnt > 2) return fail(c, SBP_EINVAL, "more than two probes of one field on one node column");
     }
   }
+  if (c->tf_on) {  // the incident source follows the point sources of every block
+    const HostBlock& b = c->blocks[c->tf_block];
+    for (int f = 0; f < 6; ++f)
+      if (b.iface[f] >= 0) return fail(c, SBP_EINVAL, "the TF/SF block takes no interface or periodic faces");
+    for (int f = 0; f < 6; ++f) {
+      const int a = f / 2;
+      const int gap = (f & 1) ? b.n[a] - c->tf_box[f] : c->tf_box[f];
+      if (b.iface[f] < 0 && b.faces[f] == SBP_CPML && gap < c->pml_cells + 4)
+        return fail(c, SBP_EINVAL, "the TF/SF box must lie at least 4 cells inside the absorbing layers");
+    }
+    c->tf_sidx = (int)dsrc.size();
+    dsrc.push_back(c->tf_srcdef);
+    c->tf_len = b.n[c->tf_axis] + 2 * c->tf_margin;
+  }
   c->pool_elems = foff;
   c->ncells = coff;
   c->pool = dalloc(c, foff * elem_size(c));
@@ -1114,6 +1201,35 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   c->d_face = (double*)dalloc(c, std::max<size_t>(fboff, 1) * sizeof(double));
   c->face_elems = std::max<size_t>(fboff, 1);
   c->psi_elems = psi;
+  if (c->tf_on) {
+    c->d_line = (double*)dalloc(c, line_bytes(c));
+    c->d_tf = (TfDesc*)dalloc(c, sizeof(TfDesc));
+    if (!c->d_line || !c->d_tf) return fail(c, SBP_ENOMEM, "device allocation failed");
+    HIPCHK(c, hipMemsetAsync(c->d_line, 0, line_bytes(c), c->stream));
+    const HostBlock& b = c->blocks[c->tf_block];
+    const int pr = c->tf_axis, ep = c->tf_pol, hq = 3 - pr - ep;
+    // signs of d_axis in the H equation of H_hq and the E equation of E_ep
+    // (curl part of H_c: +d_{c+2} E_{c+1} - d_{c+1} E_{c+2}; the same for E)
+    const double sh = (hq + 2) % 3 == pr ? 1.0 : -1.0, se = (ep + 1) % 3 == pr ? 1.0 : -1.0;
+    TfDesc t;
+    t.e1 = c->d_line;
+    t.h1 = c->d_line + c->tf_len + 1;
+    t.ch = c->dt * sh / (kMu0 * b.h[pr]);
+    t.ce = c->dt * se / (kEps0 * b.h[pr]);
+    t.block = c->tf_block;
+    t.axis = pr;
+    t.ep = ep;
+    t.hq = hq;
+    t.margin = c->tf_margin;
+    t.len = c->tf_len;
+    t.src = c->tf_cell + c->tf_margin;
+    t.sidx = c->tf_sidx;
+    for (int a = 0; a < 3; ++a) {
+      t.lo[a] = c->tf_box[2 * a];
+      t.hi[a] = c->tf_box[2 * a + 1];
+    }
+    HIPCHK(c, hipMemcpy(c->d_tf, &t, sizeof(t), hipMemcpyHostToDevice));
+  }
   c->d_pml = dalloc(c, std::max<size_t>(pml.size(), 1) * elem_size(c));
   c->d_psi = dalloc(c, std::max<size_t>(psi, 1) * elem_size(c));
   if (!c->d_pml || !c->d_psi) return fail(c, SBP_ENOMEM, "device allocation failed");
@@ -1461,7 +1577,8 @@ sbp_status sbp_read_probe(sbp_ctx* c, int id, long first, long count, double* ds
 sbp_status sbp_state_bytes(const sbp_ctx* c, size_t* bytes) {
   if (!c || !bytes) return SBP_EINVAL;
   if (!c->finalized) return SBP_ESTATE;
-  *bytes = c->pool_elems * elem_size(c) + 256 + c->psi_elems * elem_size(c);  // fields, step state, CPML psi
+  // fields, step state, CPML psi, TF/SF incident line
+  *bytes = c->pool_elems * elem_size(c) + 256 + c->psi_elems * elem_size(c) + line_bytes(c);
   return SBP_OK;
 }
 
@@ -1475,9 +1592,13 @@ sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
                            c->stream));
   HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c), c->d_st, sizeof(StepState),
                            hipMemcpyDeviceToDevice, c->stream));
+  const size_t po = c->pool_elems * elem_size(c) + 256;
   if (c->psi_elems)
-    HIPCHK(c, hipMemcpyAsync((char*)dev_buf + c->pool_elems * elem_size(c) + 256, c->d_psi,
-                             c->psi_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char*)dev_buf + po, c->d_psi, c->psi_elems * elem_size(c), hipMemcpyDeviceToDevice,
+                             c->stream));
+  if (c->tf_on)
+    HIPCHK(c, hipMemcpyAsync((char*)dev_buf + po + c->psi_elems * elem_size(c), c->d_line, line_bytes(c),
+                             hipMemcpyDeviceToDevice, c->stream));
   return SBP_OK;
 }
 
@@ -1493,9 +1614,13 @@ sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpyAsync(pool_at(c, st.step), dev_buf, c->pool_elems * elem_size(c), hipMemcpyDeviceToDevice,
                            c->stream));
+  const size_t po = c->pool_elems * elem_size(c) + 256;
   if (c->psi_elems)
-    HIPCHK(c, hipMemcpyAsync(c->d_psi, (const char*)dev_buf + c->pool_elems * elem_size(c) + 256,
-                             c->psi_elems * elem_size(c), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_psi, (const char*)dev_buf + po, c->psi_elems * elem_size(c),
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (c->tf_on)
+    HIPCHK(c, hipMemcpyAsync(c->d_line, (const char*)dev_buf + po + c->psi_elems * elem_size(c), line_bytes(c),
+                             hipMemcpyDeviceToDevice, c->stream));
   st.counter = 0;
   st.flags = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
@@ -1617,6 +1742,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
     for (double v : b.sig) lossy = lossy || v != 0.0;
     for (int f = 0; f < 6; ++f) lossy = lossy || (b.iface[f] < 0 && (b.faces[f] == SBP_ABC1 || b.faces[f] == SBP_CPML));
     if (lossy) return fail(c, SBP_EINVAL, "the adjoint covers lossless blocks (no conductivity, no absorbing faces)");
+    if (b.tfsf) return fail(c, SBP_EINVAL, "the adjoint does not cover TF/SF injection");
   }
   long K = ckpt_every > 0 ? ckpt_every : (long)std::ceil(std::sqrt((double)nsteps));
   if (K > nsteps) K = nsteps;

@@ -137,6 +137,21 @@ struct StepState {
 };
 
 
+// Total-field / scattered-field injection (one box per context): the
+// block, the cell box [lo, hi] per axis, the propagation axis (+axis), the
+// incident E and H components (0-2), and the incident line (fp64, E at "+"
+// index i in e1[i + margin], H at (i + 1/2) h in h1[i + margin]).
+struct TfDesc {
+  double* e1;
+  double* h1;
+  double ch, ce;  // line coefficients: dt s_H / (mu0 h), dt s_E / (eps0 h), s the signs of
+                  // d_axis in the H and E equations of the incident pair
+  int block, axis, ep, hq, margin, len;
+  int src;   // line index of the incident soft source
+  int sidx;  // its slot in srcval (after the point sources of every block)
+  int lo[3], hi[3];
+};
+
 // Arguments of the step kernels (one struct, passed by value).
 struct KArgs {
   const DevBlock* blocks;
@@ -169,6 +184,7 @@ struct KArgs {
   int poff;    // first partial-sum slot of this launch
   int hpoff;   // E launches: first slot of the H launch over the same tiles
                // (its partial joins the E workgroup's), else -1
+  const struct TfDesc* tf;  // total-field / scattered-field injection, or null
 };
 
 // Field pools of step n: the one it reads (the state E^n, H^{n-1/2}) and

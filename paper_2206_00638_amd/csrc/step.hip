@@ -251,6 +251,117 @@ __device__ __forceinline__ PmlCol<T> pml_col(const KArgs& a, const SBP_CONST Dev
   return PmlCol<T>{pml_at<T>(a, Bc, 0, g, 0, i), pml_at<T>(a, Bc, 0, g, 1, i), pml_at<T>(a, Bc, 0, g, 2, i),
                    pml_at<T>(a, Bc, 1, g, 0, j), pml_at<T>(a, Bc, 1, g, 1, j), pml_at<T>(a, Bc, 1, g, 2, j)};
 }
+// ------------------------------------------------------------- TF/SF
+// Membership of a node index along one axis in the total-field box
+// [lo h, hi h]: "+" nodes lo..hi, "-" nodes lo+1..hi.
+__device__ __forceinline__ bool tf_in(bool plus, int idx, int lo, int hi) {
+  return plus ? (idx >= lo && idx <= hi) : (idx >= lo + 1 && idx <= hi);
+}
+
+// The correction of one curl term of a node across the TF/SF surface: the
+// term's difference along `ax` (two-point; the box lies in the interior)
+// couples the node (grid type "+" along ax for E, "-" for H; index pa) to
+// the source component's nodes q of the other grid type (E: pa, pa+1; H:
+// pa-1, pa).  Whenever p and q lie on opposite sides, the incident value of q
+// joins the node's update: + in the total region, - in the scattered one
+// (the neighbour's value taken in the node's own convention).  `other`
+// tells whether the node lies inside the box along the other two axes.
+template <bool E_SIDE>
+__device__ __forceinline__ double tf_term(const SBP_CONST TfDesc& tf, int ax, int pa, int pprop, bool other,
+                                          double sg, double ih) {
+  if (!other) return 0.0;
+  const int lo = tf.lo[ax], hi = tf.hi[ax];
+  const bool pin = tf_in(E_SIDE, pa, lo, hi);
+  const int o0 = E_SIDE ? 0 : -1;
+  double acc = 0.0;
+  for (int t = 0; t < 2; ++t) {
+    const int qa = pa + o0 + t;
+    const bool qin = tf_in(!E_SIDE, qa, lo, hi);
+    if (qin == pin) continue;
+    const int ip = ax == tf.axis ? qa : pprop;  // the source node's index along the propagation
+    const double v = E_SIDE ? tf.h1[ip - 1 + tf.margin] : tf.e1[ip + tf.margin];
+    acc += (pin ? 1.0 : -1.0) * sg * (t ? ih : -ih) * v;
+  }
+  return acc;
+}
+
+// Corrections of the three H components at node (i, j, k) (the incident E
+// component enters the H terms that difference it).
+template <typename T>
+__device__ __forceinline__ void tf_h(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& mx, T& my,
+                                     T& mz) {
+  const SBP_CONST TfDesc& tf = *as_const(a.tf);
+  const int idx[3] = {i, j, k};
+  const int ep = tf.ep, pr = tf.axis;
+  // H component hc is "+" along hc and "-" along the others; its terms:
+  // Hx: +d_z Ey, -d_y Ez; Hy: +d_x Ez, -d_z Ex; Hz: +d_y Ex, -d_x Ey
+  double c3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int hc = 0; hc < 3; ++hc) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ax = t ? (hc + 1) % 3 : (hc + 2) % 3, src = t ? (hc + 2) % 3 : (hc + 1) % 3;
+      if (src != ep) continue;
+      bool other = true;
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (b != ax) other = other && tf_in(b == hc, idx[b], tf.lo[b], tf.hi[b]);
+      c3[hc] += tf_term<false>(tf, ax, idx[ax], idx[pr], other, t ? -1.0 : 1.0, Bc.ih[ax]);
+    }
+  }
+  mx = (T)c3[0];
+  my = (T)c3[1];
+  mz = (T)c3[2];
+}
+
+// Corrections of the three E components at node (i, j, k), as currents
+// inside the Cb bracket (the incident H component's terms).
+template <typename T>
+__device__ __forceinline__ void tf_e(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& jx, T& jy,
+                                     T& jz) {
+  const SBP_CONST TfDesc& tf = *as_const(a.tf);
+  const int idx[3] = {i, j, k};
+  const int hq = tf.hq, pr = tf.axis;
+  // E component ec is "-" along ec and "+" along the others; its terms:
+  // Ex: +d_y Hz, -d_z Hy; Ey: +d_z Hx, -d_x Hz; Ez: +d_x Hy, -d_y Hx
+  double c3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ec = 0; ec < 3; ++ec) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ax = t ? (ec + 2) % 3 : (ec + 1) % 3, src = t ? (ec + 1) % 3 : (ec + 2) % 3;
+      if (src != hq) continue;
+      bool other = true;
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (b != ax) other = other && tf_in(b != ec, idx[b], tf.lo[b], tf.hi[b]);
+      c3[ec] += tf_term<true>(tf, ax, idx[ax], idx[pr], other, t ? -1.0 : 1.0, Bc.ih[ax]);
+    }
+  }
+  jx += (T)c3[0];
+  jy += (T)c3[1];
+  jz += (T)c3[2];
+}
+
+// The incident line: one-dimensional leapfrog along the propagation axis
+// with the same dt, h, eps0, mu0 (the interior difference); PEC ends; a soft
+// current source at line index src.  H half step, then (after the 3D E
+// update) the E step with the source value of step n, at (n + 1/2) dt.
+__global__ __launch_bounds__(256) void k_line_h(const TfDesc* tfp) {
+  const SBP_CONST TfDesc& tf = *as_const(tfp);
+  const double c = tf.ch;
+  for (int i = threadIdx.x; i < tf.len; i += blockDim.x) tf.h1[i] += c * (tf.e1[i + 1] - tf.e1[i]);
+}
+__global__ __launch_bounds__(256) void k_line_e(const TfDesc* tfp, const double* srcval, double dte0) {
+  const SBP_CONST TfDesc& tf = *as_const(tfp);
+  const double c = tf.ce;
+  for (int i = 1 + threadIdx.x; i < tf.len; i += blockDim.x) {
+    double v = tf.e1[i] + c * (tf.h1[i] - tf.h1[i - 1]);
+    if (i == tf.src) v += dte0 * srcval[tf.sidx];
+    tf.e1[i] = v;
+  }
+}
+
 // Stretched difference inside a layer: psi <- b psi + c d, d <- d / kappa + psi.
 template <typename T>
 __device__ __forceinline__ void stretch(T& d, T b, T c, T ik, T* psi) {
@@ -344,15 +455,15 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 // components, with the closure / PEC / interface rows replacing the interior
 // differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
-template <typename T, bool GEN, bool IFACE, bool PML>
+template <typename T, bool GEN, bool IFACE, bool PML, bool TF = false>
 __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
                                     const T* __restrict__ Ez, T* __restrict__ Hx, T* __restrict__ Hy,
                                     T* __restrict__ Hz, const T* __restrict__ M, const FaceCol& fc,
-                                    const PmlCol<T>& pc, int i, int j, int k, long long o, bool store, T& onx,
-                                    T& ony, T& onz) {
+                                    const PmlCol<T>& pc, T tcx, T tcy, T tcz, int i, int j, int k, long long o,
+                                    bool store, T& onx, T& ony, T& onz) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long sx = c.sx, sxy = c.sxy;
   const T ihx = c.ihx, ihy = c.ihy, ihz = c.ihz;
@@ -412,9 +523,15 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     dby = dtm0x2 / (my + my);
     dbz = dtm0x2 / (mz + mz);
   }
-  const T nhx = hx + dbx * (dzEy - dyEz);
-  const T nhy = hy + dby * (dxEz - dzEx);
-  const T nhz = hz + dbz * (dyEx - dxEy);
+  T chx = dzEy - dyEz, chy = dxEz - dzEx, chz = dyEx - dxEy;
+  if constexpr (TF) {  // TF/SF corrections (zero off the box surface)
+    chx += tcx;
+    chy += tcy;
+    chz += tcz;
+  }
+  const T nhx = hx + dbx * chx;
+  const T nhy = hy + dby * chy;
+  const T nhz = hz + dbz * chz;
   const bool vx = i <= nx, vy = j <= ny, vz = k <= nz;
   if (store && vx) st32(Hx, (unsigned)o, nhx);
   if (store && vy) st32(Hy, (unsigned)o, nhy);
@@ -430,7 +547,7 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
 // one node per thread in flat (i, j, k) order, plus the H part of W^n:
 // 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
-template <typename T, bool GEN, bool IFACE, bool PML>
+template <typename T, bool GEN, bool IFACE, bool PML, bool TF = false>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -482,9 +599,10 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         nxt.ey_z = cur.ey;
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
-      T v0, v1, v2;
-      es += (double)h_node<T, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, i, j, k,
-                                               o, true, v0, v1, v2);
+      T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
+      if (TF && (tflags & 4)) tf_h<T>(a, Bc, i, j, k, tcx, tcy, tcz);
+      es += (double)h_node<T, GEN, IFACE, PML, TF>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, tcx,
+                                               tcy, tcz, i, j, k, o, true, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
     }
@@ -740,7 +858,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // node per thread in flat (i, j, k) order, plus the E part of W^{n+1}:
 // 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
-template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML>
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML, bool TF = false>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
@@ -804,6 +922,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       }
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
+      if (TF && (tflags & 4)) tf_e<T>(a, Bc, i, j, k, jx, jy, jz);
       T v0, v1, v2;
       es += (double)e_node<T, HAS_EPS, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc,
                                                         pc, i, j, k, o, jx, jy, jz, v0, v1, v2);
@@ -930,7 +1049,8 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
         const T eh = h_node<T, false, false, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr,
-                                                    FaceCol{0, 0}, PmlCol<T>{}, i, j, kh, o, hown, v0, v1, v2);
+                                                    FaceCol{0, 0}, PmlCol<T>{}, T(0), T(0), T(0), i, j, kh, o, hown,
+                                                    v0, v1, v2);
         if (hown) {
           eacc += kh_e * (double)eh;
           if (tflags & 2) take_probes<T>(a, B, i, j, kh, true, nstep, v0, v1, v2);
@@ -1113,8 +1233,10 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 template <typename T>
 hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
   const dim3 g(grid), b(threads);
-  switch (kind & 14) {
+  switch (kind & 30) {
     case 0: hipLaunchKernelGGL((k_h_update<T, false, false, false>), g, b, 0, s, a); break;
+    case 18: hipLaunchKernelGGL((k_h_update<T, true, false, false, true>), g, b, 0, s, a); break;
+    case 26: hipLaunchKernelGGL((k_h_update<T, true, false, true, true>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_h_update<T, true, false, false>), g, b, 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_h_update<T, true, true, false>), g, b, 0, s, a); break;
     case 10: hipLaunchKernelGGL((k_h_update<T, true, false, true>), g, b, 0, s, a); break;
@@ -1125,8 +1247,12 @@ hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t
 template <typename T>
 hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
   const dim3 g(grid), b(threads);
-  switch (kind & 15) {
+  switch (kind & 31) {
     case 0: hipLaunchKernelGGL((k_e_update<T, false, false, false, false>), g, b, 0, s, a); break;
+    case 18: hipLaunchKernelGGL((k_e_update<T, false, true, false, false, true>), g, b, 0, s, a); break;
+    case 19: hipLaunchKernelGGL((k_e_update<T, true, true, false, false, true>), g, b, 0, s, a); break;
+    case 26: hipLaunchKernelGGL((k_e_update<T, false, true, false, true, true>), g, b, 0, s, a); break;
+    case 27: hipLaunchKernelGGL((k_e_update<T, true, true, false, true, true>), g, b, 0, s, a); break;
     case 1: hipLaunchKernelGGL((k_e_update<T, true, false, false, false>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_e_update<T, false, true, false, false>), g, b, 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_e_update<T, true, true, false, false>), g, b, 0, s, a); break;
@@ -1150,6 +1276,13 @@ template hipError_t launch_fused<double>(const KArgs&, int, int, hipStream_t);
 
 hipError_t launch_finish(const KArgs& a, int p0, int nparts, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, p0, nparts);
+  return hipGetLastError();
+}
+hipError_t launch_line(const KArgs& a, int e_side, hipStream_t s) {
+  if (e_side)
+    hipLaunchKernelGGL(k_line_e, dim3(1), dim3(256), 0, s, a.tf, a.srcval, a.dt / a.eps0);
+  else
+    hipLaunchKernelGGL(k_line_h, dim3(1), dim3(256), 0, s, a.tf);
   return hipGetLastError();
 }
 hipError_t launch_sources(const KArgs& a, hipStream_t s) {

@@ -1,0 +1,178 @@
+"""GPU parity of the total-field / scattered-field injection against the
+fp64 oracle (oracle.tfsf): fields, W^n and probes (fp64 1e-12 / fp32 1e-5
+relative), the vacuum properties (scattered region empty to rounding, total
+region equal to the incident wave), the incident line in the saved state,
+and the argument checks."""
+import numpy as np
+import pytest
+
+from gpu_util import COMPS, field_errors, per_field_errors, random_fields, rel_l2, write_fields
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+FLOOR = {"f64": 1e-6, "f32": 1e-1}
+
+
+@pytest.fixture(scope="module")
+def sbp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_00638_amd as p
+    p.lib()
+    return p
+
+
+def _problem(n=(20, 12, 14), axis=0, pol=2, eps_box=None, faces=("pec",) * 6, box=None, probes=True):
+    eps = None
+    if eps_box is not None:
+        eps = np.ones((n[2], n[1], n[0]))
+        eps[6:9, 5:7, 8:11] = eps_box
+    blk = {"n": tuple(n), "h": (1e-3, 1.1e-3, 0.9e-3), "eps_r": eps, "mu_r": None, "sigma": None,
+           "faces": list(faces)}
+    if box is None:
+        box = [4, n[0] - 4, 4, n[1] - 4, 4, n[2] - 4]
+        box[2 * axis] = 5
+    tf = {"block": 0, "box": tuple(box), "axis": axis, "pol": pol, "margin": 16,
+          "source": {"cell": -12, "waveform": "modgauss", "tw": 4e-11, "t0": 5e-11, "f0": 3e10, "amp": 1.0}}
+    prob = {"blocks": [blk], "cfl": 0.9, "tfsf": tf}
+    if probes:
+        prob["probes"] = [{"block": 0, "comp": "Ez", "node": (9, 6, 7)},
+                          {"block": 0, "comp": "Hy", "node": (2, 3, 2)}]
+    return prob
+
+
+def _gpu(sbp, prob, prec, steps, init=None):
+    ctx = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    if init is not None:
+        write_fields(ctx, init)
+    ctx.step(steps)
+    out = {"fields": {(0, c): ctx.read_field(0, c) for c in COMPS}, "energy": ctx.read_energy(0, steps),
+           "probes": np.array([ctx.read_probe(p, 0, steps) for p in range(len(prob.get("probes", [])))])}
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("axis,pol", [(0, 2), (1, 0), (2, 1)])
+def test_tfsf_matches_oracle(sbp, prec, axis, pol):
+    from oracle import tfsf as T
+    prob = _problem(axis=axis, pol=pol, eps_box=4.0)
+    init = random_fields(prob, 11, scale=1e-4)
+    steps = 90
+    g = _gpu(sbp, prob, prec, steps, init)
+    r = T.run(prob, steps=steps, init=init)
+    errs = field_errors(g["fields"], r["fields"], FLOOR[prec])
+    assert max(errs.values()) < TOL[prec], errs
+    assert max(per_field_errors(g["fields"], r["fields"]).values()) < TOL[prec]
+    assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
+    assert rel_l2(g["probes"], r["probes"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tfsf_several_tiles_and_ragged_tail(sbp, prec):
+    """A block whose node planes span several 128-node tiles with a ragged
+    last one, and a box edge inside a tile."""
+    from oracle import tfsf as T
+    n = (37, 21, 26)
+    prob = _problem(n=n, axis=1, pol=2, eps_box=2.5, box=(6, 29, 5, 15, 7, 19),
+                    faces=("pec", "pmc", "pec", "abc", "pmc", "pec"))
+    init = random_fields(prob, 5, scale=1e-4)
+    steps = 70
+    g = _gpu(sbp, prob, prec, steps, init)
+    r = T.run(prob, steps=steps, init=init)
+    errs = field_errors(g["fields"], r["fields"], FLOOR[prec])
+    assert max(errs.values()) < TOL[prec], errs
+    assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
+
+
+def _split_masks(r):
+    mt_e, mt_h = r["mask_t"]
+    ms_e, ms_h = r["mask_s"]
+    t = r["system"].split(mt_e.astype(float), mt_h.astype(float))
+    s = r["system"].split(ms_e.astype(float), ms_h.astype(float))
+    return t, s
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_vacuum_scattered_region_stays_empty(sbp, prec, tol):
+    """With no scatterer the scattered region holds rounding only and the
+    total region the incident wave (the oracle's incident vectors)."""
+    from oracle import tfsf as T
+    prob = _problem(axis=0, pol=1, probes=False)
+    steps = 110
+    g = _gpu(sbp, prob, prec, steps)
+    r = T.run(prob, steps=steps)
+    t, s = _split_masks(r)
+    inc = r["system"].split(r["e_inc"], r["h_inc"])
+    for kind in "EH":
+        keys = [(0, c) for c in COMPS if c[0] == kind]
+        big = max(float(np.abs(g["fields"][k] * t[k]).max()) for k in keys)
+        assert big > 1e-6
+        leak = max(float(np.abs(g["fields"][k] * s[k]).max()) for k in keys)
+        assert leak < tol * big, (kind, leak, big)
+        if kind == "E":  # E^n against the incident E at step n
+            err = max(float(np.abs((g["fields"][k] - inc[k]) * t[k]).max()) for k in keys)
+            assert err < tol * big, (kind, err, big)
+
+
+def test_tfsf_with_absorbing_layers(sbp):
+    """CPML faces around a vacuum TF/SF box: the scattered region stays
+    empty, so the fields equal the oracle's (whose faces are PEC)."""
+    from oracle import tfsf as T
+    n = (30, 22, 24)
+    prob = _problem(n=n, axis=2, pol=0, faces=("cpml",) * 6, box=(9, 21, 9, 13, 9, 15), probes=False)
+    prob["cpml"] = {"cells": 5, "m": 3, "sigma_factor": 0.8, "kappa_max": 1.0, "alpha_max": 0.0}
+    steps = 100
+    g = _gpu(sbp, prob, "f64", steps)
+    r = T.run(prob, steps=steps)
+    errs = per_field_errors(g["fields"], r["fields"])
+    assert max(errs.values()) < 1e-12, errs
+
+
+def test_incident_line_travels_with_the_state(sbp):
+    prob = _problem(eps_box=3.0, probes=False)
+    ctx = sbp.build_problem(prob, prec="f64", history=256)
+    import torch
+    ctx.step(40)
+    nb = ctx.state_bytes()
+    buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ctx.save_state(buf.data_ptr(), nb)
+    ctx.step(30)
+    a = {c: ctx.read_field(0, c) for c in COMPS}
+    ctx.load_state(buf.data_ptr(), nb)
+    ctx.step(30)
+    b = {c: ctx.read_field(0, c) for c in COMPS}
+    ctx.close()
+    for c in COMPS:
+        assert np.array_equal(a[c], b[c]), c
+
+
+def test_tfsf_argument_checks(sbp):
+    from paper_2206_00638_amd.binding import SbpError
+    bad = [dict(box=(3, 16, 4, 8, 4, 10)), dict(box=(4, 17, 4, 8, 4, 10)), dict(box=(8, 8, 4, 8, 4, 10)),
+           dict(axis=0, pol=0), dict(cell=-16), dict(cell=36)]
+    for kw in bad:
+        args = dict(box=(5, 16, 4, 8, 4, 10), axis=0, pol=2, cell=-12)
+        args.update(kw)
+        ctx = sbp.Context("f64")
+        ctx.add_block((20, 12, 14), (1e-3, 1e-3, 1e-3))
+        with pytest.raises(SbpError):
+            ctx.set_tfsf(0, args["box"], args["axis"], args["pol"], args["cell"], "gauss", 3e-11, 3e-11)
+        ctx.close()
+    # one box per context, and a box too close to absorbing layers
+    ctx = sbp.Context("f64")
+    ctx.add_block((20, 12, 14), (1e-3, 1e-3, 1e-3))
+    ctx.set_tfsf(0, (5, 15, 4, 8, 4, 10), 0, 2, -12, "gauss", 3e-11, 3e-11)
+    with pytest.raises(SbpError):
+        ctx.set_tfsf(0, (5, 15, 4, 8, 4, 10), 0, 2, -12, "gauss", 3e-11, 3e-11)
+    ctx.close()
+    ctx = sbp.Context("f64")
+    ctx.add_block((20, 12, 14), (1e-3, 1e-3, 1e-3))
+    ctx.set_face_bc(0, 0, "cpml")
+    ctx.set_cpml(cells=4)
+    ctx.set_tfsf(0, (5, 15, 4, 8, 4, 10), 0, 2, -12, "gauss", 3e-11, 3e-11)
+    with pytest.raises(SbpError):
+        ctx.finalize(0.9)
+    ctx.close()
