@@ -172,10 +172,12 @@ def bloch(steps, warmup):
             "step_hbm_gbs_algorithmic": 2 * (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
-def cpml_leg(steps, warmup):
+def cpml_leg(steps, warmup, tfsf=False):
     """The dielectric-boxes 256^3 fp32 workload with every face a PEC face
     behind a 10-cell convolutional PML (the truncation of the paper's open
-    examples) instead of a PEC cavity wall."""
+    examples) instead of a PEC cavity wall; with `tfsf`, the boxes also
+    scatter a plane wave (along +z, E along x) brought in through a
+    total-field / scattered-field box 16 cells inside the faces."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
@@ -183,6 +185,13 @@ def cpml_leg(steps, warmup):
     prob = make_config(2)
     prob["blocks"][0]["faces"] = ["cpml"] * 6
     prob["cpml"] = {"cells": 10}
+    name = "dielectric-boxes-256^3-fp32-cpml10"
+    if tfsf:
+        n = prob["blocks"][0]["n"]
+        prob["tfsf"] = {"block": 0, "box": (16, n[0] - 16, 16, n[1] - 16, 16, n[2] - 16), "axis": 2, "pol": 0,
+                        "margin": 16, "source": {"cell": -12, "waveform": "modgauss", "tw": 2e-10, "t0": 2.5e-10,
+                                                 "f0": 1e10, "amp": 1.0}}
+        name += "-tfsf16"
     cells = int(np.prod(prob["blocks"][0]["n"]))
     stream = torch.cuda.Stream()
     ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
@@ -198,7 +207,7 @@ def cpml_leg(steps, warmup):
     kern = ctx.kernel_ms()
     ctx.close()
     ms = wall * 1e3 / steps
-    return {"workload": "dielectric-boxes-256^3-fp32-cpml10", "cells": cells, "steps": steps,
+    return {"workload": name, "cells": cells, "steps": steps,
             "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
             "kernels_ms": list(kern)}
 
@@ -371,6 +380,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-bloch", action="store_true")
     ap.add_argument("--no-cpml", action="store_true")
+    ap.add_argument("--no-tfsf", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -435,6 +445,8 @@ def main():
     out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpml:
         out["cpml"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20))
+    if not args.no_tfsf:
+        out["cpml_tfsf"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20), tfsf=True)
     if not args.no_bloch:
         out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_adjoint:

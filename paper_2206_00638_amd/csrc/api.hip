@@ -25,7 +25,6 @@ template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream
 hipError_t launch_finish(const KArgs&, int, int, hipStream_t);
 template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
 hipError_t launch_sources(const KArgs&, hipStream_t);
-hipError_t launch_line(const KArgs&, int, hipStream_t);
 template <typename T>
 hipError_t launch_adj_objective(const void*, const DevBlock*, int, const int*, double, double*, hipStream_t);
 template <typename T>
@@ -783,7 +782,6 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   const int nh = nparts;
-  if (a.tf) HIPCHK(c, launch_line(a, 0, c->stream));  // incident line: H^{n+1/2}
   if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream)
@@ -803,7 +801,6 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     HIPCHK(c, e);
   }
   a.hpoff = -1;
-  if (a.tf) HIPCHK(c, launch_line(a, 1, c->stream));  // incident line: E^{n+1} (source of step n)
   if ((st = mark()) != SBP_OK) return st;
   if ((st = mark()) != SBP_OK) return st;
   if (c->fused) {
@@ -1227,6 +1224,25 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
     for (int a = 0; a < 3; ++a) {
       t.lo[a] = c->tf_box[2 * a];
       t.hi[a] = c->tf_box[2 * a + 1];
+    }
+    // the curl terms that difference E_ep (in the H components other than
+    // ep) and H_hq (in the E components other than hq): with the curl parts
+    // H_c: +d_{c+2} E_{c+1} - d_{c+1} E_{c+2} and E_c: +d_{c+1} H_{c+2} -
+    // d_{c+2} H_{c+1}, the term's axis is the one left over, its sign + when
+    // it is the first term
+    for (int m = 0, cc = 0; cc < 3; ++cc) {
+      if (cc == ep) continue;
+      const bool first = (cc + 1) % 3 == ep;
+      t.h_comp[m] = cc;
+      t.h_ax[m] = first ? (cc + 2) % 3 : (cc + 1) % 3;
+      t.h_sg[m++] = first ? 1.0 : -1.0;
+    }
+    for (int m = 0, cc = 0; cc < 3; ++cc) {
+      if (cc == hq) continue;
+      const bool first = (cc + 2) % 3 == hq;
+      t.e_comp[m] = cc;
+      t.e_ax[m] = first ? (cc + 1) % 3 : (cc + 2) % 3;
+      t.e_sg[m++] = first ? 1.0 : -1.0;
     }
     HIPCHK(c, hipMemcpy(c->d_tf, &t, sizeof(t), hipMemcpyHostToDevice));
   }

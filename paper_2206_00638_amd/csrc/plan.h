@@ -150,6 +150,10 @@ struct TfDesc {
   int src;   // line index of the incident soft source
   int sidx;  // its slot in srcval (after the point sources of every block)
   int lo[3], hi[3];
+  // the two curl terms that difference the incident E component (H side)
+  // and the incident H component (E side): component, difference axis, sign
+  int h_comp[2], h_ax[2], e_comp[2], e_ax[2];
+  double h_sg[2], e_sg[2];
 };
 
 // Arguments of the step kernels (one struct, passed by value).

@@ -62,11 +62,29 @@ __device__ __forceinline__ void eval_sources(const KArgs& a, long long n) {
 // after the state was replaced).
 __global__ __launch_bounds__(256) void k_sources(KArgs a) { eval_sources(a, a.st->step); }
 
-// End of step n: sums partials[p0 .. nparts) (one workgroup, fixed order)
-// into energy ring slot n (W^n), flags a non-finite energy, advances the
-// step index and evaluates the source values of step n+1.
+// End of step n: steps the TF/SF incident line (if any), sums partials[p0
+// .. nparts) (one workgroup, fixed order) into energy ring slot n (W^n),
+// flags a non-finite energy, advances the step index and evaluates the
+// source values of step n+1.
 __global__ __launch_bounds__(1024) void k_finish(KArgs a, int p0, int nparts) {
   __shared__ double red[16];
+  if (a.tf) {
+    // the TF/SF incident line, stepped one half step ahead of the 3D fields:
+    // E^{n+1} with the source value of step n (at (n + 1/2) dt), then
+    // H^{n+3/2}, which the E update of step n+1 reads (the H update of step
+    // n+1 reads E^{n+1}).  One-dimensional leapfrog along the propagation
+    // axis with the interior difference, PEC ends.
+    const TfDesc& tf = *a.tf;
+    double* e1 = tf.e1;
+    double* h1 = tf.h1;
+    const int len = tf.len;
+    const double ce = tf.ce, ch = tf.ch, se = a.dt / a.eps0 * a.srcval[tf.sidx];
+    for (int i = 1 + threadIdx.x; i < len; i += blockDim.x)
+      e1[i] += ce * (h1[i] - h1[i - 1]) + (i == tf.src ? se : 0.0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += blockDim.x) h1[i] += ch * (e1[i + 1] - e1[i]);
+    __syncthreads();  // the source values of step n are read before they are replaced
+  }
   // eight independent running sums per thread keep eight loads in flight
   // (the partials come from other XCDs' caches); fixed order for a given
   // nparts and block size
@@ -258,107 +276,65 @@ __device__ __forceinline__ bool tf_in(bool plus, int idx, int lo, int hi) {
   return plus ? (idx >= lo && idx <= hi) : (idx >= lo + 1 && idx <= hi);
 }
 
-// The correction of one curl term of a node across the TF/SF surface: the
-// term's difference along `ax` (two-point; the box lies in the interior)
-// couples the node (grid type "+" along ax for E, "-" for H; index pa) to
-// the source component's nodes q of the other grid type (E: pa, pa+1; H:
-// pa-1, pa).  Whenever p and q lie on opposite sides, the incident value of q
-// joins the node's update: + in the total region, - in the scattered one
-// (the neighbour's value taken in the node's own convention).  `other`
-// tells whether the node lies inside the box along the other two axes.
-template <bool E_SIDE>
-__device__ __forceinline__ double tf_term(const SBP_CONST TfDesc& tf, int ax, int pa, int pprop, bool other,
-                                          double sg, double ih) {
-  if (!other) return 0.0;
-  const int lo = tf.lo[ax], hi = tf.hi[ax];
-  const bool pin = tf_in(E_SIDE, pa, lo, hi);
-  const int o0 = E_SIDE ? 0 : -1;
-  double acc = 0.0;
+// Component v (0, 1, 2) of (i, j, k), without a local array (a dynamic
+// index into one would go through scratch memory).
+__device__ __forceinline__ int sel3(int v, int i, int j, int k) { return v == 0 ? i : (v == 1 ? j : k); }
+
+// Whether node (i, j, k) can take a correction: all indices within one of
+// the box and one of them on its edge (lo - 1, lo, hi or hi + 1).
+__device__ __forceinline__ bool tf_near(const SBP_CONST TfDesc& tf, int i, int j, int k) {
+  bool in = true, edge = false;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int x = b == 0 ? i : (b == 1 ? j : k), lo = tf.lo[b], hi = tf.hi[b];
+    in = in && x >= lo - 1 && x <= hi + 1;
+    edge = edge || x <= lo || x >= hi;
+  }
+  return in && edge;
+}
+
+// The corrections of a node across the TF/SF surface.  Two curl terms
+// difference the incident component (on the H side: the H components other
+// than the incident E one; on the E side likewise).  A term's difference
+// along `ax` (two-point: the box lies in the interior) couples the node
+// (grid type "-" along ax for H, "+" for E; index pa) to the source
+// component's nodes q of the other grid type (H: pa-1, pa; E: pa, pa+1).
+// Whenever p and q lie on opposite sides of the surface, the incident value
+// of q joins the node's update, + in the total region and - in the
+// scattered one (the neighbour's value taken in the node's own convention).
+// Along the other two axes p and q share index and grid type, so they must
+// lie inside the box there.
+template <bool E_SIDE, typename T>
+__device__ __forceinline__ void tf_terms(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& cx,
+                                         T& cy, T& cz) {
+  const SBP_CONST TfDesc& tf = *as_const(a.tf);
+  const int pr = tf.axis, margin = tf.margin;
+  const int pprop = sel3(pr, i, j, k);
+#pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int qa = pa + o0 + t;
-    const bool qin = tf_in(!E_SIDE, qa, lo, hi);
-    if (qin == pin) continue;
-    const int ip = ax == tf.axis ? qa : pprop;  // the source node's index along the propagation
-    const double v = E_SIDE ? tf.h1[ip - 1 + tf.margin] : tf.e1[ip + tf.margin];
-    acc += (pin ? 1.0 : -1.0) * sg * (t ? ih : -ih) * v;
-  }
-  return acc;
-}
-
-// Corrections of the three H components at node (i, j, k) (the incident E
-// component enters the H terms that difference it).
-template <typename T>
-__device__ __forceinline__ void tf_h(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& mx, T& my,
-                                     T& mz) {
-  const SBP_CONST TfDesc& tf = *as_const(a.tf);
-  const int idx[3] = {i, j, k};
-  const int ep = tf.ep, pr = tf.axis;
-  // H component hc is "+" along hc and "-" along the others; its terms:
-  // Hx: +d_z Ey, -d_y Ez; Hy: +d_x Ez, -d_z Ex; Hz: +d_y Ex, -d_x Ey
-  double c3[3] = {0.0, 0.0, 0.0};
+    const int c = E_SIDE ? tf.e_comp[t] : tf.h_comp[t];
+    const int ax = E_SIDE ? tf.e_ax[t] : tf.h_ax[t];
+    const int o = 3 - c - ax;
+    const double sg = E_SIDE ? tf.e_sg[t] : tf.h_sg[t], ih = Bc.ih[ax];
+    // H_c is "+" along c and "-" along o; E_c is "-" along c and "+" along o
+    const bool other = tf_in(!E_SIDE, sel3(c, i, j, k), tf.lo[c], tf.hi[c]) &&
+                       tf_in(E_SIDE, sel3(o, i, j, k), tf.lo[o], tf.hi[o]);
+    if (!other) continue;
+    const int pa = sel3(ax, i, j, k), lo = tf.lo[ax], hi = tf.hi[ax];
+    const bool pin = tf_in(E_SIDE, pa, lo, hi);
+    double acc = 0.0;
 #pragma unroll
-  for (int hc = 0; hc < 3; ++hc) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int ax = t ? (hc + 1) % 3 : (hc + 2) % 3, src = t ? (hc + 2) % 3 : (hc + 1) % 3;
-      if (src != ep) continue;
-      bool other = true;
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        if (b != ax) other = other && tf_in(b == hc, idx[b], tf.lo[b], tf.hi[b]);
-      c3[hc] += tf_term<false>(tf, ax, idx[ax], idx[pr], other, t ? -1.0 : 1.0, Bc.ih[ax]);
+    for (int q = 0; q < 2; ++q) {
+      const int qa = pa + (E_SIDE ? q : q - 1);
+      if (tf_in(!E_SIDE, qa, lo, hi) == pin) continue;
+      const int ip = ax == pr ? qa : pprop;  // the source node's index along the propagation
+      const double v = E_SIDE ? tf.h1[ip - 1 + margin] : tf.e1[ip + margin];
+      acc += (q ? ih : -ih) * v;
     }
-  }
-  mx = (T)c3[0];
-  my = (T)c3[1];
-  mz = (T)c3[2];
-}
-
-// Corrections of the three E components at node (i, j, k), as currents
-// inside the Cb bracket (the incident H component's terms).
-template <typename T>
-__device__ __forceinline__ void tf_e(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& jx, T& jy,
-                                     T& jz) {
-  const SBP_CONST TfDesc& tf = *as_const(a.tf);
-  const int idx[3] = {i, j, k};
-  const int hq = tf.hq, pr = tf.axis;
-  // E component ec is "-" along ec and "+" along the others; its terms:
-  // Ex: +d_y Hz, -d_z Hy; Ey: +d_z Hx, -d_x Hz; Ez: +d_x Hy, -d_y Hx
-  double c3[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int ec = 0; ec < 3; ++ec) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int ax = t ? (ec + 2) % 3 : (ec + 1) % 3, src = t ? (ec + 1) % 3 : (ec + 2) % 3;
-      if (src != hq) continue;
-      bool other = true;
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        if (b != ax) other = other && tf_in(b != ec, idx[b], tf.lo[b], tf.hi[b]);
-      c3[ec] += tf_term<true>(tf, ax, idx[ax], idx[pr], other, t ? -1.0 : 1.0, Bc.ih[ax]);
-    }
-  }
-  jx += (T)c3[0];
-  jy += (T)c3[1];
-  jz += (T)c3[2];
-}
-
-// The incident line: one-dimensional leapfrog along the propagation axis
-// with the same dt, h, eps0, mu0 (the interior difference); PEC ends; a soft
-// current source at line index src.  H half step, then (after the 3D E
-// update) the E step with the source value of step n, at (n + 1/2) dt.
-__global__ __launch_bounds__(256) void k_line_h(const TfDesc* tfp) {
-  const SBP_CONST TfDesc& tf = *as_const(tfp);
-  const double c = tf.ch;
-  for (int i = threadIdx.x; i < tf.len; i += blockDim.x) tf.h1[i] += c * (tf.e1[i + 1] - tf.e1[i]);
-}
-__global__ __launch_bounds__(256) void k_line_e(const TfDesc* tfp, const double* srcval, double dte0) {
-  const SBP_CONST TfDesc& tf = *as_const(tfp);
-  const double c = tf.ce;
-  for (int i = 1 + threadIdx.x; i < tf.len; i += blockDim.x) {
-    double v = tf.e1[i] + c * (tf.h1[i] - tf.h1[i - 1]);
-    if (i == tf.src) v += dte0 * srcval[tf.sidx];
-    tf.e1[i] = v;
+    const T d = (T)((pin ? sg : -sg) * acc);
+    cx += c == 0 ? d : T(0);
+    cy += c == 1 ? d : T(0);
+    cz += c == 2 ? d : T(0);
   }
 }
 
@@ -600,7 +576,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
-      if (TF && (tflags & 4)) tf_h<T>(a, Bc, i, j, k, tcx, tcy, tcz);
+      if (TF && (tflags & 4) && tf_near(*as_const(a.tf), i, j, k)) tf_terms<false, T>(a, Bc, i, j, k, tcx, tcy, tcz);
       es += (double)h_node<T, GEN, IFACE, PML, TF>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, tcx,
                                                tcy, tcz, i, j, k, o, true, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
@@ -922,7 +898,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       }
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
-      if (TF && (tflags & 4)) tf_e<T>(a, Bc, i, j, k, jx, jy, jz);
+      if (TF && (tflags & 4) && tf_near(*as_const(a.tf), i, j, k)) tf_terms<true, T>(a, Bc, i, j, k, jx, jy, jz);
       T v0, v1, v2;
       es += (double)e_node<T, HAS_EPS, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc,
                                                         pc, i, j, k, o, jx, jy, jz, v0, v1, v2);
@@ -1276,13 +1252,6 @@ template hipError_t launch_fused<double>(const KArgs&, int, int, hipStream_t);
 
 hipError_t launch_finish(const KArgs& a, int p0, int nparts, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, a, p0, nparts);
-  return hipGetLastError();
-}
-hipError_t launch_line(const KArgs& a, int e_side, hipStream_t s) {
-  if (e_side)
-    hipLaunchKernelGGL(k_line_e, dim3(1), dim3(256), 0, s, a.tf, a.srcval, a.dt / a.eps0);
-  else
-    hipLaunchKernelGGL(k_line_h, dim3(1), dim3(256), 0, s, a.tf);
   return hipGetLastError();
 }
 hipError_t launch_sources(const KArgs& a, hipStream_t s) {
