@@ -299,11 +299,55 @@ __device__ __forceinline__ bool tf_near(const SBP_CONST TfDesc& tf, int i, int j
 // along `ax` (two-point: the box lies in the interior) couples the node
 // (grid type "-" along ax for H, "+" for E; index pa) to the source
 // component's nodes q of the other grid type (H: pa-1, pa; E: pa, pa+1).
-// Whenever p and q lie on opposite sides of the surface, the incident value
-// of q joins the node's update, + in the total region and - in the
-// scattered one (the neighbour's value taken in the node's own convention).
-// Along the other two axes p and q share index and grid type, so they must
-// lie inside the box there.
+// Where p and q lie on opposite sides of the surface (at most one q per term,
+// the box being at least a cell thick), the incident value of q joins the
+// node's update, + in the total region and - in the scattered one (the
+// neighbour's value taken in the node's own convention), times the
+// difference's coefficient -1/h (first q) or +1/h (second q).  Along the
+// other two axes p and q share index and grid type, so they must lie inside
+// the box there.
+//
+// tf_gather finds, per term, the sign of the correction (0: none) and loads
+// the incident value.  The E kernel gathers one plane ahead, with the field
+// values of that plane, so that these loads do not wait behind the next
+// plane's (vector memory loads complete in order).
+struct TfPre {
+  double v[2];
+  int s[2];
+};
+
+template <bool E_SIDE>
+__device__ __forceinline__ void tf_gather(const KArgs& a, int i, int j, int k, TfPre& p) {
+  p.v[0] = p.v[1] = 0.0;
+  p.s[0] = p.s[1] = 0;
+  const SBP_CONST TfDesc& tf = *as_const(a.tf);
+  if (!tf_near(tf, i, j, k)) return;
+  const int pr = tf.axis, margin = tf.margin;
+  const int pprop = sel3(pr, i, j, k);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = E_SIDE ? tf.e_comp[t] : tf.h_comp[t];
+    const int ax = E_SIDE ? tf.e_ax[t] : tf.h_ax[t];
+    const int o = 3 - c - ax;
+    const double sg = E_SIDE ? tf.e_sg[t] : tf.h_sg[t];
+    // H_c is "+" along c and "-" along o; E_c is "-" along c and "+" along o
+    const bool other = tf_in(!E_SIDE, sel3(c, i, j, k), tf.lo[c], tf.hi[c]) &&
+                       tf_in(E_SIDE, sel3(o, i, j, k), tf.lo[o], tf.hi[o]);
+    if (!other) continue;
+    const int pa = sel3(ax, i, j, k), lo = tf.lo[ax], hi = tf.hi[ax];
+    const bool pin = tf_in(E_SIDE, pa, lo, hi);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int qa = pa + (E_SIDE ? q : q - 1);
+      if (tf_in(!E_SIDE, qa, lo, hi) == pin) continue;
+      const int ip = ax == pr ? qa : pprop;  // the source node's index along the propagation
+      p.v[t] = E_SIDE ? tf.h1[ip - 1 + margin] : tf.e1[ip + margin];
+      p.s[t] = ((pin ? sg : -sg) > 0.0) == (q == 1) ? 1 : -1;
+    }
+  }
+}
+
+// The same corrections, gathered and combined in one go (the H kernel).
 template <bool E_SIDE, typename T>
 __device__ __forceinline__ void tf_terms(const KArgs& a, const SBP_CONST DevBlock& Bc, int i, int j, int k, T& cx,
                                          T& cy, T& cz) {
@@ -332,6 +376,21 @@ __device__ __forceinline__ void tf_terms(const KArgs& a, const SBP_CONST DevBloc
       acc += (q ? ih : -ih) * v;
     }
     const T d = (T)((pin ? sg : -sg) * acc);
+    cx += c == 0 ? d : T(0);
+    cy += c == 1 ? d : T(0);
+    cz += c == 2 ? d : T(0);
+  }
+}
+
+template <bool E_SIDE, typename T>
+__device__ __forceinline__ void tf_combine(const KArgs& a, const SBP_CONST DevBlock& Bc, const TfPre& p, T& cx, T& cy,
+                                           T& cz) {
+  const SBP_CONST TfDesc& tf = *as_const(a.tf);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = E_SIDE ? tf.e_comp[t] : tf.h_comp[t];
+    const int ax = E_SIDE ? tf.e_ax[t] : tf.h_ax[t];
+    const T d = (T)((double)p.s[t] * Bc.ih[ax] * p.v[t]);
     cx += c == 0 ? d : T(0);
     cy += c == 1 ? d : T(0);
     cz += c == 2 ? d : T(0);
@@ -576,6 +635,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
+      // in place: gathering one plane ahead costs the H kernel a wave per SIMD
       if (TF && (tflags & 4) && tf_near(*as_const(a.tf), i, j, k)) tf_terms<false, T>(a, Bc, i, j, k, tcx, tcy, tcz);
       es += (double)h_node<T, GEN, IFACE, PML, TF>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, tcx,
                                                tcy, tcz, i, j, k, o, true, v0, v1, v2);
@@ -885,6 +945,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       cur.e0d = p0[cc.dx + cc.dy];
     }
     e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    TfPre tcur, tnxt;
+    if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k0, tcur);
     for (int k = k0; k < k1; ++k, o += c.sxy) {
       EIn<T> nxt;
       if (k + 1 < k1) {  // next plane first: its loads overlap this plane's arithmetic
@@ -895,15 +957,17 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
         nxt.e0c = cur.e1c;
         nxt.e0d = cur.e1d;
         e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+        if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
-      if (TF && (tflags & 4) && tf_near(*as_const(a.tf), i, j, k)) tf_terms<true, T>(a, Bc, i, j, k, jx, jy, jz);
+      if (TF && (tflags & 4)) tf_combine<true, T>(a, Bc, tcur, jx, jy, jz);
       T v0, v1, v2;
       es += (double)e_node<T, HAS_EPS, GEN, IFACE, PML>(a, B, Bc, rx, ry, lw, c, cur, ExO, EyO, EzO, Hx, Hy, Hz, MS, fc,
                                                         pc, i, j, k, o, jx, jy, jz, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, false, nstep, v0, v1, v2);
       cur = nxt;
+      if (TF) tcur = tnxt;
     }
     eacc += ke4 * es;
   }
