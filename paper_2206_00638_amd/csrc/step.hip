@@ -397,12 +397,47 @@ __device__ __forceinline__ void tf_combine(const KArgs& a, const SBP_CONST DevBl
   }
 }
 
-// Stretched difference inside a layer: psi <- b psi + c d, d <- d / kappa + psi.
+// Stretched difference inside a layer: psi <- b psi + c d, d <- d / kappa +
+// psi; `old` is psi as loaded with the plane's field values.
 template <typename T>
-__device__ __forceinline__ void stretch(T& d, T b, T c, T ik, T* psi) {
-  const T p = b * *psi + c * d;
+__device__ __forceinline__ void stretch(T& d, T b, T c, T ik, T* psi, T old) {
+  const T p = b * old + c * d;
   *psi = p;
   d = d * ik + p;
+}
+
+// z profile value q of grid g at plane k (wave-uniform: a scalar load).
+template <typename T>
+__device__ __forceinline__ T pml_z(const KArgs& a, const SBP_CONST DevBlock& Bc, int g, int q, int k) {
+  return as_const((const T*)a.pml_prof)[Bc.pml_off + (long long)((2 * 2 + g) * 3 + q) * Bc.pml_stride + k];
+}
+
+// The recursion variables a node of plane k updates (the kernels load them
+// one plane ahead, with the field values, so that they do not wait behind
+// the next plane's loads).  H slots 0-5: (Hx,z) (Hx,y) (Hy,x) (Hy,z) (Hz,y)
+// (Hz,x); E slots 6-11: (Ex,y) (Ex,z) (Ey,z) (Ey,x) (Ez,x) (Ez,y).
+template <typename T, bool E_SIDE>
+__device__ __forceinline__ void psi_load(const KArgs& a, const SBP_CONST DevBlock& Bc, const PmlCol<T>& pc, int k,
+                                         long long o, T (&v)[6]) {
+  const T* ps = (const T*)a.psi + Bc.psi_off + (E_SIDE ? 6 * Bc.csz : 0) + o;
+  const long long cs = Bc.csz;
+  const int g = E_SIDE ? 0 : 1;
+  const bool zl = (!E_SIDE || k <= Bc.n[2]) && (pml_z<T>(a, Bc, g, 1, k) != T(0) || pml_z<T>(a, Bc, g, 2, k) != T(1));
+  const int z0 = E_SIDE ? 1 : 0, z1 = E_SIDE ? 2 : 3;  // slots of the z terms
+  const int y0 = E_SIDE ? 0 : 1, y1 = E_SIDE ? 5 : 4;  // y terms
+  const int x0 = E_SIDE ? 3 : 2, x1 = E_SIDE ? 4 : 5;  // x terms
+  if (zl) {
+    v[z0] = ps[z0 * cs];
+    v[z1] = ps[z1 * cs];
+  }
+  if (pc.cy != T(0) || pc.ky != T(1)) {
+    v[y0] = ps[y0 * cs];
+    v[y1] = ps[y1 * cs];
+  }
+  if (pc.cx != T(0) || pc.kx != T(1)) {
+    v[x0] = ps[x0 * cs];
+    v[x1] = ps[x1 * cs];
+  }
 }
 
 // Element `idx` of a component array addressed as the (wave-uniform) array
@@ -466,6 +501,7 @@ template <typename T>
 struct HIn {
   T ex, ey, ez, hx, hy, hz;
   T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
+  T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
 template <typename T>
@@ -528,18 +564,18 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
   if constexpr (PML) {  // absorbing layers: H terms sit on the "-" grid of their axis
     T* ps = (T*)a.psi + Bc.psi_off + o;  // slots 0-5: (Hx,z) (Hx,y) (Hy,x) (Hy,z) (Hz,y) (Hz,x)
     const long long cs = Bc.csz;
-    const T bzp = pml_at<T>(a, Bc, 2, 1, 0, k), czp = pml_at<T>(a, Bc, 2, 1, 1, k), kzp = pml_at<T>(a, Bc, 2, 1, 2, k);
+    const T bzp = pml_z<T>(a, Bc, 1, 0, k), czp = pml_z<T>(a, Bc, 1, 1, k), kzp = pml_z<T>(a, Bc, 1, 2, k);
     if (czp != T(0) || kzp != T(1)) {
-      stretch(dzEy, bzp, czp, kzp, ps);
-      stretch(dzEx, bzp, czp, kzp, ps + 3 * cs);
+      stretch(dzEy, bzp, czp, kzp, ps, v.psi[0]);
+      stretch(dzEx, bzp, czp, kzp, ps + 3 * cs, v.psi[3]);
     }
     if (pc.cy != T(0) || pc.ky != T(1)) {
-      stretch(dyEz, pc.by, pc.cy, pc.ky, ps + cs);
-      stretch(dyEx, pc.by, pc.cy, pc.ky, ps + 4 * cs);
+      stretch(dyEz, pc.by, pc.cy, pc.ky, ps + cs, v.psi[1]);
+      stretch(dyEx, pc.by, pc.cy, pc.ky, ps + 4 * cs, v.psi[4]);
     }
     if (pc.cx != T(0) || pc.kx != T(1)) {
-      stretch(dxEz, pc.bx, pc.cx, pc.kx, ps + 2 * cs);
-      stretch(dxEy, pc.bx, pc.cx, pc.kx, ps + 5 * cs);
+      stretch(dxEz, pc.bx, pc.cx, pc.kx, ps + 2 * cs, v.psi[2]);
+      stretch(dxEy, pc.bx, pc.cx, pc.kx, ps + 5 * cs, v.psi[5]);
     }
   }
   const T db_u = c.db_u, mu_r0 = c.mu_r0;
@@ -626,6 +662,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
       cur.ex_z = Ex[ob];
       cur.ey_z = Ey[ob];
       h_load<T>(cur, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
+      if constexpr (PML) psi_load<T, false>(a, Bc, pc, k0, o, cur.psi);
     }
     for (int k = k0; k < k1; ++k, o += c.sxy) {
       HIn<T> nxt;
@@ -633,6 +670,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         nxt.ex_z = cur.ex;
         nxt.ey_z = cur.ey;
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
+        if constexpr (PML) psi_load<T, false>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
       // in place: gathering one plane ahead costs the H kernel a wave per SIMD
@@ -705,6 +743,7 @@ struct EIn {
   T ex, ey, ez, hx, hy, hz;
   T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
+  T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
 
 // Cell offsets of a node column (i, j) within the block's cells: cell A
@@ -799,20 +838,19 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     T* ps = (T*)a.psi + Bc.psi_off + 6 * Bc.csz + o;  // slots 6-11: (Ex,y) (Ex,z) (Ey,z) (Ey,x) (Ez,x) (Ez,y)
     const long long cs = Bc.csz;
     if (k <= nz) {
-      const T bzp = pml_at<T>(a, Bc, 2, 0, 0, k), czp = pml_at<T>(a, Bc, 2, 0, 1, k),
-              kzp = pml_at<T>(a, Bc, 2, 0, 2, k);
+      const T bzp = pml_z<T>(a, Bc, 0, 0, k), czp = pml_z<T>(a, Bc, 0, 1, k), kzp = pml_z<T>(a, Bc, 0, 2, k);
       if (czp != T(0) || kzp != T(1)) {
-        stretch(dzHy, bzp, czp, kzp, ps + cs);
-        stretch(dzHx, bzp, czp, kzp, ps + 2 * cs);
+        stretch(dzHy, bzp, czp, kzp, ps + cs, v.psi[1]);
+        stretch(dzHx, bzp, czp, kzp, ps + 2 * cs, v.psi[2]);
       }
     }
     if (pc.cy != T(0) || pc.ky != T(1)) {
-      stretch(dyHz, pc.by, pc.cy, pc.ky, ps);
-      stretch(dyHx, pc.by, pc.cy, pc.ky, ps + 5 * cs);
+      stretch(dyHz, pc.by, pc.cy, pc.ky, ps, v.psi[0]);
+      stretch(dyHx, pc.by, pc.cy, pc.ky, ps + 5 * cs, v.psi[5]);
     }
     if (pc.cx != T(0) || pc.kx != T(1)) {
-      stretch(dxHz, pc.bx, pc.cx, pc.kx, ps + 3 * cs);
-      stretch(dxHy, pc.bx, pc.cx, pc.kx, ps + 4 * cs);
+      stretch(dxHz, pc.bx, pc.cx, pc.kx, ps + 3 * cs, v.psi[3]);
+      stretch(dxHy, pc.bx, pc.cx, pc.kx, ps + 4 * cs, v.psi[4]);
     }
   }
   const T cx = dyHz - dzHy, cy = dzHx - dxHz, cz = dxHy - dyHx;
@@ -945,6 +983,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       cur.e0d = p0[cc.dx + cc.dy];
     }
     e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    if constexpr (PML) psi_load<T, true>(a, Bc, pc, k0, o, cur.psi);
     TfPre tcur, tnxt;
     if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k0, tcur);
     for (int k = k0; k < k1; ++k, o += c.sxy) {
@@ -957,6 +996,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
         nxt.e0c = cur.e1c;
         nxt.e0d = cur.e1d;
         e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+        if constexpr (PML) psi_load<T, true>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
         if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
       T jx = T(0), jy = T(0), jz = T(0);
