@@ -190,6 +190,30 @@ __device__ __forceinline__ TRow<T> row_of(const DB& B, int axis, int r, bool min
   return R;
 }
 
+// The x closure rows from values the march loads with the plane: besides
+// the node (d = 0) and its interior partner (d = -1 for D-, +1 for D+), each
+// boundary row reads at most one more node, at offset h_xd / e_xd (0: none);
+// taps with a zero coefficient read nothing.  Loaded in place, these values
+// would wait behind the next plane's loads (vector memory loads complete in
+// order).
+__device__ __forceinline__ int h_xd(int i, int n) {  // D- rows 0, 2, n-1, n+1
+  return (i == 0 || i == n - 1) ? 1 : ((i == 2 || i == n + 1) ? -2 : 0);
+}
+__device__ __forceinline__ int e_xd(int i, int n) {  // D+ rows 0, 1, n-1, n
+  return (i == 0 || i == n - 1) ? 2 : ((i == 1 || i == n) ? -1 : 0);
+}
+// Whether an E kernel variant takes its x rows from the plane's loads: not
+// on interface faces, where the rows also read the face buffer.
+template <typename T, bool GEN, bool IFACE>
+constexpr bool e_xpre() {
+  return !IFACE;
+}
+template <typename T>
+__device__ __forceinline__ T xrow(const TRow<T>& R, T u0, T un, int dn, T ux, int xd) {
+  auto pick = [&](int d) { return d == 0 ? u0 : (d == dn ? un : (d == xd ? ux : T(0))); };
+  return R.c0 * pick(R.s) + R.c1 * pick(R.s + 1) + R.c2 * pick(R.s + 2);
+}
+
 // Closure row applied to u along stride st at node offset o; on an
 // interface row the gathered neighbour value a.face[fo] joins it.
 template <typename T, bool IFACE>
@@ -501,6 +525,7 @@ template <typename T>
 struct HIn {
   T ex, ey, ez, hx, hy, hz;
   T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
+  T ez_xx, ey_xx;  // x closure rows: the value beyond the interior pair (h_xd)
   T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
@@ -520,6 +545,11 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
   v.ex_y = ld32(Ex, uy);
   v.ez_x = ld32(Ez, ux);
   v.ey_x = ld32(Ey, ux);
+  const int xd = h_xd(i, c.nx);
+  if (xd != 0) {
+    v.ez_xx = ld32(Ez, u + (unsigned)xd);
+    v.ey_xx = ld32(Ey, u + (unsigned)xd);
+  }
 }
 
 // H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
@@ -557,9 +587,15 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
   }
   if (!xin) {
-    const long long fo = fc.x + by * k;
-    dxEz = drow<T, IFACE>(a, Ez, o, 1, rx, fo + by * bz);
-    dxEy = drow<T, IFACE>(a, Ey, o, 1, rx, fo);
+    if constexpr (IFACE) {
+      const long long fo = fc.x + by * k;
+      dxEz = drow<T, IFACE>(a, Ez, o, 1, rx, fo + by * bz);
+      dxEy = drow<T, IFACE>(a, Ey, o, 1, rx, fo);
+    } else {
+      const int xd = h_xd(i, nx);
+      dxEz = xrow<T>(rx, v.ez, v.ez_x, -1, v.ez_xx, xd);
+      dxEy = xrow<T>(rx, v.ey, v.ey_x, -1, v.ey_xx, xd);
+    }
   }
   if constexpr (PML) {  // absorbing layers: H terms sit on the "-" grid of their axis
     T* ps = (T*)a.psi + Bc.psi_off + o;  // slots 0-5: (Hx,z) (Hx,y) (Hy,x) (Hy,z) (Hz,y) (Hz,x)
@@ -742,6 +778,7 @@ template <typename T>
 struct EIn {
   T ex, ey, ez, hx, hy, hz;
   T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
+  T hz_xx, hy_xx;  // x closure rows: the value beyond the interior pair (e_xd)
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
   T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
@@ -761,7 +798,7 @@ __device__ __forceinline__ ColCells col_cells(const BC<T>& c, int i, int j) {
   return ColCells{ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
 }
 
-template <typename T, bool HAS_EPS>
+template <typename T, bool HAS_EPS, bool XPRE>
 __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __restrict__ Ex,
                                        const T* __restrict__ Ey, const T* __restrict__ Ez,
                                        const T* __restrict__ Hz, const T* __restrict__ Hx,
@@ -780,6 +817,11 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
   v.hx_y = ld32(Hx, uy);
   v.hz_x = ld32(Hz, ux);
   v.hy_x = ld32(Hy, ux);
+  const int xd = XPRE ? e_xd(i, c.nx) : 0;
+  if (xd != 0) {
+    v.hz_xx = ld32(Hz, u + (unsigned)xd);
+    v.hy_xx = ld32(Hy, u + (unsigned)xd);
+  }
   if (HAS_EPS) {  // ME: the block's cells; q.A relative to them
     const unsigned p1 = (unsigned)(q.A + q.cp * clampi(k, 0, c.nz - 1));
     v.e1a = ld32(ME, p1);
@@ -830,9 +872,15 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
   }
   if (!xin) {
-    const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
-    dxHz = drow<T, IFACE>(a, Hz, o, 1, rx, fo + fs);
-    dxHy = drow<T, IFACE>(a, Hy, o, 1, rx, fo);
+    if constexpr (!e_xpre<T, GEN, IFACE>()) {
+      const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
+      dxHz = drow<T, IFACE>(a, Hz, o, 1, rx, fo + fs);
+      dxHy = drow<T, IFACE>(a, Hy, o, 1, rx, fo);
+    } else {
+      const int xd = e_xd(i, nx);
+      dxHz = xrow<T>(rx, v.hz, v.hz_x, 1, v.hz_xx, xd);
+      dxHy = xrow<T>(rx, v.hy, v.hy_x, 1, v.hy_xx, xd);
+    }
   }
   if constexpr (PML) {  // absorbing layers: E terms sit on the "+" grid of their axis
     T* ps = (T*)a.psi + Bc.psi_off + 6 * Bc.csz + o;  // slots 6-11: (Ex,y) (Ex,z) (Ey,z) (Ey,x) (Ez,x) (Ez,y)
@@ -982,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       cur.e0c = p0[cc.dy];
       cur.e0d = p0[cc.dx + cc.dy];
     }
-    e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    e_load<T, HAS_EPS, e_xpre<T, GEN, IFACE>()>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
     if constexpr (PML) psi_load<T, true>(a, Bc, pc, k0, o, cur.psi);
     TfPre tcur, tnxt;
     if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k0, tcur);
@@ -995,7 +1043,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
         nxt.e0b = cur.e1b;
         nxt.e0c = cur.e1c;
         nxt.e0d = cur.e1d;
-        e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+        e_load<T, HAS_EPS, e_xpre<T, GEN, IFACE>()>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1,
+                                                    o + c.sxy);
         if constexpr (PML) psi_load<T, true>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
         if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
