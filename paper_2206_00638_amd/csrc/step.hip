@@ -202,12 +202,7 @@ __device__ __forceinline__ int h_xd(int i, int n) {  // D- rows 0, 2, n-1, n+1
 __device__ __forceinline__ int e_xd(int i, int n) {  // D+ rows 0, 1, n-1, n
   return (i == 0 || i == n - 1) ? 2 : ((i == 1 || i == n) ? -1 : 0);
 }
-// Whether an E kernel variant takes its x rows from the plane's loads: not
-// on interface faces, where the rows also read the face buffer.
-template <typename T, bool GEN, bool IFACE>
-constexpr bool e_xpre() {
-  return !IFACE;
-}
+
 template <typename T>
 __device__ __forceinline__ T xrow(const TRow<T>& R, T u0, T un, int dn, T ux, int xd) {
   auto pick = [&](int d) { return d == 0 ? u0 : (d == dn ? un : (d == xd ? ux : T(0))); };
@@ -526,6 +521,7 @@ struct HIn {
   T ex, ey, ez, hx, hy, hz;
   T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
   T ez_xx, ey_xx;  // x closure rows: the value beyond the interior pair (h_xd)
+  T ez_f, ey_f;    // interface x rows: the neighbour's face values
   T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
@@ -550,6 +546,15 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
     v.ez_xx = ld32(Ez, u + (unsigned)xd);
     v.ey_xx = ld32(Ey, u + (unsigned)xd);
   }
+}
+
+// Interface x rows of plane k: the neighbour's face values (face buffer,
+// fp64), the Ez and Ey slots of the x face.
+template <typename T>
+__device__ __forceinline__ void h_face(const KArgs& a, const BC<T>& c, const FaceCol& fc, int k, HIn<T>& v) {
+  const long long by = c.ny + 2, bz = c.nz + 2, fo = fc.x + by * k;
+  v.ez_f = (T)a.face[fo + by * bz];
+  v.ey_f = (T)a.face[fo];
 }
 
 // H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
@@ -587,14 +592,12 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
   }
   if (!xin) {
-    if constexpr (IFACE) {
-      const long long fo = fc.x + by * k;
-      dxEz = drow<T, IFACE>(a, Ez, o, 1, rx, fo + by * bz);
-      dxEy = drow<T, IFACE>(a, Ey, o, 1, rx, fo);
-    } else {
-      const int xd = h_xd(i, nx);
-      dxEz = xrow<T>(rx, v.ez, v.ez_x, -1, v.ez_xx, xd);
-      dxEy = xrow<T>(rx, v.ey, v.ey_x, -1, v.ey_xx, xd);
+    const int xd = h_xd(i, nx);
+    dxEz = xrow<T>(rx, v.ez, v.ez_x, -1, v.ez_xx, xd);
+    dxEy = xrow<T>(rx, v.ey, v.ey_x, -1, v.ey_xx, xd);
+    if (IFACE && rx.nbr) {
+      dxEz += rx.cn * v.ez_f;
+      dxEy += rx.cn * v.ey_f;
     }
   }
   if constexpr (PML) {  // absorbing layers: H terms sit on the "-" grid of their axis
@@ -698,6 +701,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
       cur.ex_z = Ex[ob];
       cur.ey_z = Ey[ob];
       h_load<T>(cur, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
+      if (IFACE && rx.nbr) h_face<T>(a, c, fc, k0, cur);
       if constexpr (PML) psi_load<T, false>(a, Bc, pc, k0, o, cur.psi);
     }
     for (int k = k0; k < k1; ++k, o += c.sxy) {
@@ -706,6 +710,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         nxt.ex_z = cur.ex;
         nxt.ey_z = cur.ey;
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
+        if (IFACE && rx.nbr) h_face<T>(a, c, fc, k + 1, nxt);
         if constexpr (PML) psi_load<T, false>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
@@ -779,6 +784,7 @@ struct EIn {
   T ex, ey, ez, hx, hy, hz;
   T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
   T hz_xx, hy_xx;  // x closure rows: the value beyond the interior pair (e_xd)
+  T hz_f, hy_f;    // interface x rows: the neighbour's face values
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
   T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
@@ -798,7 +804,7 @@ __device__ __forceinline__ ColCells col_cells(const BC<T>& c, int i, int j) {
   return ColCells{ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
 }
 
-template <typename T, bool HAS_EPS, bool XPRE>
+template <typename T, bool HAS_EPS>
 __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __restrict__ Ex,
                                        const T* __restrict__ Ey, const T* __restrict__ Ez,
                                        const T* __restrict__ Hz, const T* __restrict__ Hx,
@@ -817,7 +823,7 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
   v.hx_y = ld32(Hx, uy);
   v.hz_x = ld32(Hz, ux);
   v.hy_x = ld32(Hy, ux);
-  const int xd = XPRE ? e_xd(i, c.nx) : 0;
+  const int xd = e_xd(i, c.nx);
   if (xd != 0) {
     v.hz_xx = ld32(Hz, u + (unsigned)xd);
     v.hy_xx = ld32(Hy, u + (unsigned)xd);
@@ -829,6 +835,15 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
     v.e1c = ld32(ME, p1 + (unsigned)q.dy);
     v.e1d = ld32(ME, p1 + (unsigned)(q.dx + q.dy));
   }
+}
+
+// Interface x rows of plane k: the neighbour's face values, the Hz and Hy
+// slots of the x face.
+template <typename T>
+__device__ __forceinline__ void e_face(const KArgs& a, const BC<T>& c, const FaceCol& fc, int k, EIn<T>& v) {
+  const long long by = c.ny + 2, fs = by * (c.nz + 2), fo = fc.x + by * k + 2 * fs;
+  v.hz_f = (T)a.face[fo + fs];
+  v.hy_f = (T)a.face[fo];
 }
 
 // E^{n+1} = Ca E^n + Cb (E7-E9 + J) at node (i, j, k), all valid E
@@ -872,14 +887,12 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
   }
   if (!xin) {
-    if constexpr (!e_xpre<T, GEN, IFACE>()) {
-      const long long fs = by * bz, fo = fc.x + by * k + 2 * fs;
-      dxHz = drow<T, IFACE>(a, Hz, o, 1, rx, fo + fs);
-      dxHy = drow<T, IFACE>(a, Hy, o, 1, rx, fo);
-    } else {
-      const int xd = e_xd(i, nx);
-      dxHz = xrow<T>(rx, v.hz, v.hz_x, 1, v.hz_xx, xd);
-      dxHy = xrow<T>(rx, v.hy, v.hy_x, 1, v.hy_xx, xd);
+    const int xd = e_xd(i, nx);
+    dxHz = xrow<T>(rx, v.hz, v.hz_x, 1, v.hz_xx, xd);
+    dxHy = xrow<T>(rx, v.hy, v.hy_x, 1, v.hy_xx, xd);
+    if (IFACE && rx.nbr) {
+      dxHz += rx.cn * v.hz_f;
+      dxHy += rx.cn * v.hy_f;
     }
   }
   if constexpr (PML) {  // absorbing layers: E terms sit on the "+" grid of their axis
@@ -1030,7 +1043,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
       cur.e0c = p0[cc.dy];
       cur.e0d = p0[cc.dx + cc.dy];
     }
-    e_load<T, HAS_EPS, e_xpre<T, GEN, IFACE>()>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    if (IFACE && rx.nbr) e_face<T>(a, c, fc, k0, cur);
     if constexpr (PML) psi_load<T, true>(a, Bc, pc, k0, o, cur.psi);
     TfPre tcur, tnxt;
     if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k0, tcur);
@@ -1043,8 +1057,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
         nxt.e0b = cur.e1b;
         nxt.e0c = cur.e1c;
         nxt.e0d = cur.e1d;
-        e_load<T, HAS_EPS, e_xpre<T, GEN, IFACE>()>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1,
-                                                    o + c.sxy);
+        e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+        if (IFACE && rx.nbr) e_face<T>(a, c, fc, k + 1, nxt);
         if constexpr (PML) psi_load<T, true>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
         if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
