@@ -522,6 +522,7 @@ struct HIn {
   T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
   T ez_xx, ey_xx;  // x closure rows: the value beyond the interior pair (h_xd)
   T ez_f, ey_f;    // interface x rows: the neighbour's face values
+  T ez_yy, ex_yy, ez_fy, ex_fy;  // y rows of interface blocks: likewise
   T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
@@ -557,6 +558,28 @@ __device__ __forceinline__ void h_face(const KArgs& a, const BC<T>& c, const Fac
   v.ey_f = (T)a.face[fo];
 }
 
+// The y rows of an interface block at plane k from loads issued with the
+// plane: the node beyond the interior pair, and on an interface face the
+// neighbour's face values (Ez and Ex slots of the y face).  Only interface
+// blocks take these: they are small, so their boundary rows are a larger
+// share of the waves, and the plain kernels keep their registers.
+template <typename T>
+__device__ __forceinline__ void h_yrow(const KArgs& a, const BC<T>& c, const FaceCol& fc, const TRow<T>& ry,
+                                       const T* __restrict__ Ez, const T* __restrict__ Ex, int j, int k,
+                                       long long o, HIn<T>& v) {
+  const int yd = h_xd(j, c.ny);
+  if (yd != 0) {
+    const unsigned u = (unsigned)o + (unsigned)(yd * (int)c.sx);
+    v.ez_yy = ld32(Ez, u);
+    v.ex_yy = ld32(Ex, u);
+  }
+  if (ry.nbr) {
+    const long long bx = c.nx + 2, bz = c.nz + 2, fo = fc.y + bx * k;
+    v.ez_fy = (T)a.face[fo + bx * bz];
+    v.ex_fy = (T)a.face[fo];
+  }
+}
+
 // H^{n+1/2} = H^{n-1/2} + dt/mu (E10-E12) at node (i, j, k), all valid H
 // components, with the closure / PEC / interface rows replacing the interior
 // differences on the boundary rows.  Returns the node's
@@ -587,9 +610,19 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo);
   }
   if (!yin) {
-    const long long fo = fc.y + bx * k;
-    dyEz = drow<T, IFACE>(a, Ez, o, sx, ry, fo + bx * bz);
-    dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
+    if constexpr (IFACE) {
+      const int yd = h_xd(j, ny);
+      dyEz = xrow<T>(ry, v.ez, v.ez_y, -1, v.ez_yy, yd);
+      dyEx = xrow<T>(ry, v.ex, v.ex_y, -1, v.ex_yy, yd);
+      if (ry.nbr) {
+        dyEz += ry.cn * v.ez_fy;
+        dyEx += ry.cn * v.ex_fy;
+      }
+    } else {
+      const long long fo = fc.y + bx * k;
+      dyEz = drow<T, IFACE>(a, Ez, o, sx, ry, fo + bx * bz);
+      dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
+    }
   }
   if (!xin) {
     const int xd = h_xd(i, nx);
@@ -702,6 +735,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
       cur.ey_z = Ey[ob];
       h_load<T>(cur, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
       if (IFACE && rx.nbr) h_face<T>(a, c, fc, k0, cur);
+      if (IFACE && !ry.in) h_yrow<T>(a, c, fc, ry, Ez, Ex, j, k0, o, cur);
       if constexpr (PML) psi_load<T, false>(a, Bc, pc, k0, o, cur.psi);
     }
     for (int k = k0; k < k1; ++k, o += c.sxy) {
@@ -711,6 +745,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         nxt.ey_z = cur.ey;
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
         if (IFACE && rx.nbr) h_face<T>(a, c, fc, k + 1, nxt);
+        if (IFACE && !ry.in) h_yrow<T>(a, c, fc, ry, Ez, Ex, j, k + 1, o + c.sxy, nxt);
         if constexpr (PML) psi_load<T, false>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
@@ -785,6 +820,7 @@ struct EIn {
   T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
   T hz_xx, hy_xx;  // x closure rows: the value beyond the interior pair (e_xd)
   T hz_f, hy_f;    // interface x rows: the neighbour's face values
+  T hz_yy, hx_yy, hz_fy, hx_fy;  // y rows of interface blocks: likewise
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
   T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
@@ -846,6 +882,24 @@ __device__ __forceinline__ void e_face(const KArgs& a, const BC<T>& c, const Fac
   v.hy_f = (T)a.face[fo];
 }
 
+// The y rows of an interface block at plane k (Hz and Hx slots of the y face).
+template <typename T>
+__device__ __forceinline__ void e_yrow(const KArgs& a, const BC<T>& c, const FaceCol& fc, const TRow<T>& ry,
+                                       const T* __restrict__ Hz, const T* __restrict__ Hx, int j, int k,
+                                       long long o, EIn<T>& v) {
+  const int yd = e_xd(j, c.ny);
+  if (yd != 0) {
+    const unsigned u = (unsigned)o + (unsigned)(yd * (int)c.sx);
+    v.hz_yy = ld32(Hz, u);
+    v.hx_yy = ld32(Hx, u);
+  }
+  if (ry.nbr) {
+    const long long bx = c.nx + 2, fs = bx * (c.nz + 2), fo = fc.y + bx * k + 2 * fs;
+    v.hz_fy = (T)a.face[fo + fs];
+    v.hx_fy = (T)a.face[fo];
+  }
+}
+
 // E^{n+1} = Ca E^n + Cb (E7-E9 + J) at node (i, j, k), all valid E
 // components, with the closure / PMC / absorbing / interface rows replacing
 // the interior differences on the boundary rows; the absorbing damping
@@ -882,9 +936,19 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     }
   }
   if (!yin) {
-    const long long fs = bx * bz, fo = fc.y + bx * k + 2 * fs;
-    dyHz = drow<T, IFACE>(a, Hz, o, sx, ry, fo + fs);
-    dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
+    if constexpr (IFACE) {
+      const int yd = e_xd(j, ny);
+      dyHz = xrow<T>(ry, v.hz, v.hz_y, 1, v.hz_yy, yd);
+      dyHx = xrow<T>(ry, v.hx, v.hx_y, 1, v.hx_yy, yd);
+      if (ry.nbr) {
+        dyHz += ry.cn * v.hz_fy;
+        dyHx += ry.cn * v.hx_fy;
+      }
+    } else {
+      const long long fs = bx * bz, fo = fc.y + bx * k + 2 * fs;
+      dyHz = drow<T, IFACE>(a, Hz, o, sx, ry, fo + fs);
+      dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
+    }
   }
   if (!xin) {
     const int xd = e_xd(i, nx);
@@ -1045,6 +1109,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     }
     e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
     if (IFACE && rx.nbr) e_face<T>(a, c, fc, k0, cur);
+    if (IFACE && !ry.in) e_yrow<T>(a, c, fc, ry, Hz, Hx, j, k0, o, cur);
     if constexpr (PML) psi_load<T, true>(a, Bc, pc, k0, o, cur.psi);
     TfPre tcur, tnxt;
     if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k0, tcur);
@@ -1059,6 +1124,7 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
         nxt.e0d = cur.e1d;
         e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
         if (IFACE && rx.nbr) e_face<T>(a, c, fc, k + 1, nxt);
+        if (IFACE && !ry.in) e_yrow<T>(a, c, fc, ry, Hz, Hx, j, k + 1, o + c.sxy, nxt);
         if constexpr (PML) psi_load<T, true>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
         if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
