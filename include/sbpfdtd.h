@@ -188,8 +188,10 @@ sbp_status sbp_read_energy(sbp_ctx *ctx, long first, long count, double *dst);
 /* Probe samples n = first .. first+count-1 of probe `id`. */
 sbp_status sbp_read_probe(sbp_ctx *ctx, int id, long first, long count, double *dst);
 
-/* Device-to-device snapshot of the time-stepping state (fields and step
- * index).  bytes must be >= sbp_state_bytes(). */
+/* Device-to-device snapshot of the time-stepping state: the fields, the
+ * step index, the CPML recursion variables and the TF/SF incident line.
+ * bytes must be >= sbp_state_bytes(); sbp_load_state restores a snapshot of
+ * the same context (the sources' values follow from the step index). */
 sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
 sbp_status sbp_save_state(sbp_ctx *ctx, void *dev_buf, size_t bytes);
 sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
