@@ -385,8 +385,9 @@ def main():
                     help="run a 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (one block "
+              "set per GPU with halo exchange between them is a design only); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from sbp_inputs import make_config
