@@ -33,6 +33,11 @@ at zero strength and by absorption against a larger domain.
 one-dimensional incident line, pinned by an empty scattered region (to
 rounding) in vacuum.
 
+``lts``: local time stepping at 1:p for refined blocks (an energy-conserving
+two-level scheme on the E-only form of the lossless leapfrog), pinned by its
+reduction to the leapfrog, energy conservation beyond the fine CFL limit and
+second-order convergence.
+
 ``adjoint``: the discrete adjoint of the leapfrog step in the matrix form
 (explicit transposes), giving the gradient of a region objective with
 respect to the per-cell permittivity; pinned by central finite differences

@@ -26,6 +26,8 @@ to the whole state and p times to the refined part (with the coarse nodes it
 couples to), so the coarse blocks advance at dt while only the refined
 blocks (and their interface neighbours) pay the fine step.  Lossless blocks
 only (PEC / PMC faces, interfaces); sources are not part of this reading.
+`band` > 0 adds the coarse E nodes within that many cells of a face shared
+with a refined block to the substepped part.
 """
 import numpy as np
 
