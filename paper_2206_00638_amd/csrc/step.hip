@@ -523,6 +523,7 @@ struct HIn {
   T ez_xx, ey_xx;  // x closure rows: the value beyond the interior pair (h_xd)
   T ez_f, ey_f;    // interface x rows: the neighbour's face values
   T ez_yy, ex_yy, ez_fy, ex_fy;  // y rows of interface blocks: likewise
+  T ey_zz, ex_zz, ey_fz, ex_fz;  // z rows of interface blocks: likewise
   T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
@@ -556,6 +557,26 @@ __device__ __forceinline__ void h_face(const KArgs& a, const BC<T>& c, const Fac
   const long long by = c.ny + 2, bz = c.nz + 2, fo = fc.x + by * k;
   v.ez_f = (T)a.face[fo + by * bz];
   v.ey_f = (T)a.face[fo];
+}
+
+// The z rows of an interface block at plane k (wave-uniform: only the planes
+// next to the z faces), with the Ey and Ex slots of the z face.
+template <typename T>
+__device__ __forceinline__ void h_zrow(const KArgs& a, const BC<T>& c, const SBP_CONST DevBlock& Bc,
+                                       const T* __restrict__ Ey, const T* __restrict__ Ex, int i, int j, int k,
+                                       long long o, HIn<T>& v) {
+  if (k >= 3 && k <= c.nz - 2) return;
+  const int zd = h_xd(k, c.nz);
+  if (zd != 0) {
+    const unsigned u = (unsigned)o + (unsigned)(zd * (int)c.sxy);
+    v.ey_zz = ld32(Ey, u);
+    v.ex_zz = ld32(Ex, u);
+  }
+  if (row_of<T>(Bc, 2, k, true).nbr) {
+    const long long bx = c.nx + 2, by = c.ny + 2, fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
+    v.ey_fz = (T)a.face[fo + bx * by];
+    v.ex_fz = (T)a.face[fo];
+  }
 }
 
 // The y rows of an interface block at plane k from loads issued with the
@@ -605,9 +626,20 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
   const long long bx = nx + 2, by = ny + 2, bz = nz + 2;
   if (!zin) {
     const TRow<T> rz = row_of<T>(Bc, 2, k, true);
-    const long long fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
-    dzEy = drow<T, IFACE>(a, Ey, o, sxy, rz, fo + bx * by);
-    dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo);
+    if constexpr (IFACE && sizeof(T) == 4) {  // (fp64: registers would spill)
+      // interior pair: E at k (v.ey) and k-1 (v.ey_z)
+      const int zd = h_xd(k, nz);
+      dzEy = xrow<T>(rz, v.ey, v.ey_z, -1, v.ey_zz, zd);
+      dzEx = xrow<T>(rz, v.ex, v.ex_z, -1, v.ex_zz, zd);
+      if (rz.nbr) {
+        dzEy += rz.cn * v.ey_fz;
+        dzEx += rz.cn * v.ex_fz;
+      }
+    } else {
+      const long long fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
+      dzEy = drow<T, IFACE>(a, Ey, o, sxy, rz, fo + bx * by);
+      dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo);
+    }
   }
   if (!yin) {
     if constexpr (IFACE) {
@@ -736,6 +768,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
       h_load<T>(cur, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o);
       if (IFACE && rx.nbr) h_face<T>(a, c, fc, k0, cur);
       if (IFACE && !ry.in) h_yrow<T>(a, c, fc, ry, Ez, Ex, j, k0, o, cur);
+      if constexpr (IFACE && sizeof(T) == 4) h_zrow<T>(a, c, Bc, Ey, Ex, i, j, k0, o, cur);
       if constexpr (PML) psi_load<T, false>(a, Bc, pc, k0, o, cur.psi);
     }
     for (int k = k0; k < k1; ++k, o += c.sxy) {
@@ -746,6 +779,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
         h_load<T>(nxt, c, Ex, Ey, Ez, Hx, Hy, Hz, i, j, o + c.sxy);
         if (IFACE && rx.nbr) h_face<T>(a, c, fc, k + 1, nxt);
         if (IFACE && !ry.in) h_yrow<T>(a, c, fc, ry, Ez, Ex, j, k + 1, o + c.sxy, nxt);
+        if constexpr (IFACE && sizeof(T) == 4) h_zrow<T>(a, c, Bc, Ey, Ex, i, j, k + 1, o + c.sxy, nxt);
         if constexpr (PML) psi_load<T, false>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
       }
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
