@@ -9,10 +9,13 @@ HBM before timing.  Prints one JSON line.
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Extra keys: the fp64 path on the same workload, the field error of both
-paths against the fp64 oracle on a reduced case of the same recipe, the
-roofline of the dominant kernel (algorithmic bytes / mean launch time from
-HIP events on the kernel's stream), and the oracle timed on the host cores
-on a bounded sample of the workload.
+paths against the fp64 oracle on a reduced case of the same recipe (per
+field and per component), the roofline of the dominant kernel (algorithmic
+bytes / mean launch time from HIP events on the kernel's stream), the other
+workloads (batched cavities, 1:2 subgrid, CPML, TF/SF, Bloch box, adjoint;
+fp64 beside fp32 for the batched and adjoint legs), same-harness bandwidth
+references, the paper's own figures with its hardware, and the oracle timed
+on the host cores (all cores and one) on a bounded sample of the workload.
 """
 import argparse
 import hashlib
@@ -108,34 +111,69 @@ def run_gpu(problem, prec, steps, warmup, profile_kernels, fused=False):
     return {"wall_s": wall, "event_ms": ev_ms, "kernel_ms": kern, "launch": launch, "last_energy": energy}
 
 
-def batched(steps, warmup):
+def batched(steps, warmup, prec="f32", tune=True):
     """The batched workload: 64 uneven cavities (sides 32..128, 32.8 M cells)
     in one tile list, launch shape from the autotuner, steps replayed from
-    100-step HIP graphs."""
+    HIP graphs of min(steps, 100) steps: the timed steps are a whole number
+    of replays."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
     from sbp_inputs import make_config
     prob = make_config(4)
     cells = int(sum(np.prod(b["n"]) for b in prob["blocks"]))
+    gsteps = max(1, min(steps, 100))
+    replays = -(-steps // gsteps)
+    timed = replays * gsteps
     stream = torch.cuda.Stream()
-    ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
-    tune_ms = ctx.autotune(5)
+    ctx = build_problem(prob, prec=prec, stream=stream, history=max(timed + warmup + 8, 64))
+    tune_ms = ctx.autotune(5) if tune else None
     launch = ctx.get_launch()
-    ctx.use_graph(100)
-    ctx.step(warmup)
+    ctx.use_graph(gsteps)
+    ctx.step(-(-warmup // gsteps) * gsteps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.step(steps)
+    ctx.step(timed)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.close()
-    hb, eb, fb = algorithmic_bytes(prob, 4)
-    ms = wall * 1e3 / steps
-    return {"workload": prob["name"], "cells": cells, "blocks": len(prob["blocks"]), "steps": steps,
-            "graph_steps": 100, "launch": list(launch), "autotune_ms_per_step": tune_ms,
-            "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
+    elem = 4 if prec == "f32" else 8
+    hb, eb, fb = algorithmic_bytes(prob, elem)
+    ms = wall * 1e3 / timed
+    return {"workload": prob["name"] if prec == "f32" else prob["name"].replace("fp32", "fp64"),
+            "cells": cells, "blocks": len(prob["blocks"]), "steps": timed,
+            "graph_steps": gsteps, "graph_replays": replays, "launch": list(launch), "autotune_ms_per_step": tune_ms,
+            "value": cells * timed / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
             "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
+
+
+def batched_accuracy(steps=100, sample=3):
+    """fp32 and fp64 error of the batched run against the fp64 loop oracle
+    on its smallest cavities (each stepped alone by the oracle, with the
+    batched problem's time step), per field and per component."""
+    import numpy as np
+    from oracle import loops
+    from oracle.system import cfl_dt
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(4)
+    sizes = [int(np.prod(b["n"])) for b in prob["blocks"]]
+    pick = sorted(range(len(sizes)), key=lambda b: sizes[b])[:sample]
+    dt = cfl_dt(prob["blocks"], prob["cfl"])
+    refs = {}
+    for b in pick:
+        one = {"blocks": [prob["blocks"][b]], "interfaces": [], "cfl": prob["cfl"],
+               "sources": [dict(q, block=0) for q in prob["sources"] if q["block"] == b], "probes": []}
+        refs[b] = loops.run_block(one, steps=steps, dt=dt)["fields"]
+    out = {"workload": f"batched cavities {pick} (the smallest), {steps} steps"}
+    for prec in ("f32", "f64"):
+        ctx = build_problem(prob, prec=prec)
+        ctx.step(steps)
+        got = {b: {c: ctx.read_field(b, c) for c in COMPS} for b in pick}
+        ctx.close()
+        out[prec] = field_error_report({(b, c): got[b][c] for b in pick for c in COMPS},
+                                       {(b, c): refs[b][c] for b in pick for c in COMPS})
+    return out
 
 
 def bloch(steps, warmup):
@@ -242,10 +280,11 @@ def subgrid(steps, warmup):
             "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
-def adjoint_leg():
-    """The adjoint workload: 96^3 fp32, J over 2000 steps, checkpoints every
-    45 steps; one sbp_adjoint call (forward run, segment replays, reverse
-    sweep) timed."""
+def adjoint_leg(prec="f32"):
+    """The adjoint workload: 96^3, J over 2000 steps, checkpoints every 45
+    steps; one sbp_adjoint call (forward run, segment replays, reverse
+    sweep) timed, next to the forward run alone.  Returns the record and
+    the gradient (host array)."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
@@ -255,13 +294,14 @@ def adjoint_leg():
     cells = int(np.prod(n))
     steps = prob["steps"]
     stream = torch.cuda.Stream()
-    ctx = build_problem(prob, prec="f32", stream=stream, history=steps + 8)
+    ctx = build_problem(prob, prec=prec, stream=stream, history=steps + 8)
     nb = ctx.state_bytes()
     snap = torch.empty(nb, dtype=torch.uint8, device="cuda")
     ctx.save_state(snap.data_ptr(), nb)
     grad = torch.zeros((n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
     ctx.adjoint(0, steps, prob["region"], grad.data_ptr(), prob["ckpt_every"])  # warm-up
     ctx.load_state(snap.data_ptr(), nb)
+    grad.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     J = ctx.adjoint(0, steps, prob["region"], grad.data_ptr(), prob["ckpt_every"])
@@ -274,10 +314,34 @@ def adjoint_leg():
     torch.cuda.synchronize()
     fwd = time.perf_counter() - t0
     ctx.close()
-    return {"workload": prob["name"], "cells": cells, "steps": steps, "ckpt_every": prob["ckpt_every"],
-            "J": J, "gradient_s": wall, "forward_s": fwd, "gradient_over_forward": wall / fwd,
-            "value": cells * steps / wall / 1e6,
-            "unit": "Mcell-updates/s (forward-step equivalents per second of the gradient)"}
+    rec = {"workload": prob["name"] if prec == "f32" else prob["name"].replace("fp32", "fp64"),
+           "cells": cells, "steps": steps, "ckpt_every": prob["ckpt_every"],
+           "J": J, "gradient_s": wall, "forward_s": fwd, "gradient_over_forward": wall / fwd,
+           "value": cells * steps / wall / 1e6,
+           "unit": "Mcell-updates/s (forward-step equivalents per second of the gradient)"}
+    return rec, grad.cpu().numpy()
+
+
+COMPS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+
+def field_error_report(got, ref):
+    """Relative L2 errors against the oracle: per field (all E, all H
+    components together) and each component on its own."""
+    import numpy as np
+    num = {"E": 0.0, "H": 0.0}
+    den = {"E": 0.0, "H": 0.0}
+    comp = {}
+    for k, r in ref.items():
+        c = k[-1] if isinstance(k, tuple) else k
+        d = float(np.sum((got[k] - r) ** 2))
+        q = float(np.sum(r * r))
+        num[c[0]] += d
+        den[c[0]] += q
+        key = c if not isinstance(k, tuple) else f"{k[0]}/{c}"
+        comp[key] = math.sqrt(d / q) if q > 0 else math.sqrt(d)
+    return {"E_rel_l2": math.sqrt(num["E"] / den["E"]), "H_rel_l2": math.sqrt(num["H"] / den["H"]),
+            "components_rel_l2": comp}
 
 
 def accuracy(scale):
@@ -294,19 +358,13 @@ def accuracy(scale):
     for prec in ("f32", "f64"):
         ctx = build_problem(prob, prec=prec)
         ctx.step(steps)
-        num = {"E": 0.0, "H": 0.0}
-        den = {"E": 0.0, "H": 0.0}
-        for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
-            g = ctx.read_field(0, c)
-            r = ref["fields"][c]
-            num[c[0]] += float(np.sum((g - r) ** 2))
-            den[c[0]] += float(np.sum(r * r))
+        got = {c: ctx.read_field(0, c) for c in COMPS}
         pr = np.array([ctx.read_probe(p, 0, steps) for p in range(len(prob["probes"]))])
         en = ctx.read_energy(0, steps)
         ctx.close()
-        out[prec] = {"E_rel_l2": math.sqrt(num["E"] / den["E"]), "H_rel_l2": math.sqrt(num["H"] / den["H"]),
-                     "probe_rel_l2": float(np.linalg.norm(pr - ref["probes"]) / np.linalg.norm(ref["probes"])),
-                     "energy_rel": float(np.linalg.norm(en - ref["energy"]) / np.linalg.norm(ref["energy"]))}
+        out[prec] = field_error_report(got, ref["fields"])
+        out[prec]["probe_rel_l2"] = float(np.linalg.norm(pr - ref["probes"]) / np.linalg.norm(ref["probes"]))
+        out[prec]["energy_rel"] = float(np.linalg.norm(en - ref["energy"]) / np.linalg.norm(ref["energy"]))
     return out
 
 
@@ -345,26 +403,90 @@ def copy_ceiling():
             "note": "1 GiB fp32 arrays: device-to-device copy (1 read + 1 write) and c = a + b (2 reads + 1 write)"}
 
 
-def cpu_baseline(problem, target_s=15.0):
-    """The loop oracle (plain C, OpenMP) on the host cores, on a bounded
-    sample of the workload: the full block for a few steps."""
+def host_cpu():
+    """CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return model, ncpu
+
+
+def cpu_rate(problem, threads, target_s):
+    """Cell-updates per second of the loop oracle on `threads` host threads
+    (0: all), with its one-off set-up (node coefficients) excluded: one run
+    of 1 step and one of k+1 steps, k sized to about target_s."""
     from oracle import loops
-    cells = problem["blocks"][0]["n"][0] * problem["blocks"][0]["n"][1] * problem["blocks"][0]["n"][2]
-    threads = loops.max_threads()
+    n = problem["blocks"][0]["n"]
+    cells = n[0] * n[1] * n[2]
     t0 = time.perf_counter()
-    loops.run_block(problem, steps=1)
-    t1 = time.perf_counter() - t0           # setup + one step
+    loops.run_block(problem, steps=1, threads=threads)
+    t1 = time.perf_counter() - t0
+    k = int(max(2, min(200, target_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    loops.run_block(problem, steps=3)
-    t3 = time.perf_counter() - t0           # setup + three steps
-    per_step = max((t3 - t1) / 2.0, 1e-6)
-    k = int(max(2, min(200, target_s / per_step)))
-    t0 = time.perf_counter()
-    loops.run_block(problem, steps=k + 1)
+    loops.run_block(problem, steps=k + 1, threads=threads)
     tk = time.perf_counter() - t0
-    rate = k * cells / max(tk - t1 + per_step, 1e-9)   # exclude the one-off setup
-    return {"value": rate / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"full {problem['blocks'][0]['n'][0]}^3 block, {k} steps (setup excluded), fp64 loop form"}
+    return k * cells / max(tk - t1, 1e-9), k
+
+
+def cpu_baseline(problem):
+    """The loop oracle (plain C, fp64, OpenMP over z planes) on the host
+    cores, on a bounded sample of the workload (the full block for a few
+    steps): on all the cores this process may use, and on one core."""
+    from oracle import loops
+    model, ncpu = host_cpu()
+    threads = loops.max_threads()
+    rate_all, k_all = cpu_rate(problem, 0, 12.0)
+    rate_one, k_one = cpu_rate(problem, 1, 8.0)
+    n = problem["blocks"][0]["n"]
+    return {"value": rate_all / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {n[0]}^3 block, {k_all} steps on {threads} threads and {k_one} steps on 1 "
+                      f"(set-up excluded), fp64 loop form",
+            "one_core": {"value": rate_one / 1e6, "unit": "Mcell-updates/s", "cores": 1},
+            "cpu_model": model, "nproc": ncpu}
+
+
+def paper_context(problem):
+    """The paper's own figures with the hardware it states (Section VI-D,
+    Table T3), beside this layout's field storage against the Yee grid's."""
+    def yee_nodes(n):
+        nx, ny, nz = n
+        return (nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz +
+                (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
+
+    def sbp_nodes(n):
+        e, h = node_counts(n)
+        return e + h
+
+    def layout_nodes(n):
+        nx, ny, nz = n
+        sxy = -(-((nx + 2) * (ny + 2)) // 64) * 64
+        return 6 * sxy * (nz + 2)
+
+    out = {"throughput_mcells": 21.15e6 * 5196 / 36187.0 / 1e6,
+           "throughput_note": "SBP-SAT head-model run: 300x300x235 = 21.15 M cells, 10 ns, 36,187 s "
+                              "(Table T3); 5196 steps assumes dt = 1 mm / (c sqrt 3), which the paper "
+                              "does not state",
+           "hardware": "Intel i7-7700 @ 3.6 GHz, one thread, 256 GB RAM; precision not stated",
+           "runtime_overhead_vs_fdtd_pct": 100.0 * (36187.0 / 36138.0 - 1.0),
+           "memory_overhead_vs_fdtd_pct": 100.0 * (984.1 / 973.5 - 1.0),
+           "overhead_note": "whole solvers with CPML and TF/SF (Table T3); the abstract rounds the memory "
+                            "overhead to 1.2 %"}
+    for name, n in (("head_grid_300x300x235", (300, 300, 235)), ("workload", tuple(problem["blocks"][0]["n"]))):
+        y = yee_nodes(n)
+        out[f"field_nodes_vs_yee_pct_{name}"] = {
+            "method": 100.0 * (sbp_nodes(n) / y - 1.0),
+            "this_layout": 100.0 * (layout_nodes(n) / y - 1.0)}
+    return out
 
 
 def main():
@@ -441,6 +563,10 @@ def main():
                            "achieved_gbs": fb1 / (one["kernel_ms"][2] * 1e-3) / 1e9}
     if not args.no_batched:
         out["batched"] = batched(args.steps, max(args.warmup, 100))
+        if not args.no_fp64:
+            out["batched"]["fp64"] = batched(args.steps, max(args.warmup, 100), prec="f64")
+        if not args.no_accuracy:
+            out["batched"]["accuracy"] = batched_accuracy()
     if not args.no_subgrid:
         out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
     out["copy_ceiling"] = copy_ceiling()
@@ -451,9 +577,19 @@ def main():
     if not args.no_bloch:
         out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg()
+        import numpy as np
+        out["adjoint"], g32 = adjoint_leg("f32")
+        if not args.no_fp64:
+            rec64, g64 = adjoint_leg("f64")
+            out["adjoint"]["fp64"] = rec64
+            # the fp64 gradient is the reference here: the GPU tests pin it to
+            # the oracle's adjoint and to central differences
+            out["adjoint"]["accuracy_vs_fp64"] = {
+                "J_rel": abs(out["adjoint"]["J"] - rec64["J"]) / abs(rec64["J"]),
+                "grad_rel_l2": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
     if not args.no_accuracy:
         out["accuracy"] = accuracy(4)
+    out["paper"] = paper_context(prob)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -13,9 +13,11 @@ Two independent forms of the same method:
   SAT penalties written as sigma (P''')^-1 R^T P'' (...) exactly as in
   E13-E15, E19-E21 and EPBC1-EPBC6, leapfrog time marching (Section V) and
   the discrete energy (E16).  scipy.sparse matrices, fp64.
-* ``loops``: plain C loops (``loops.c``) applying the same step row by row
-  (Appendix rows, E24), for one block at a time; fast enough to time on the
-  host and to run the large single-block workloads.
+* ``loops``: plain C loops applying the same step row by row (Appendix
+  rows, E24): ``loops.c`` for one block, ``multiblock.c`` for coupled blocks
+  (interfaces at 1:1 and 1:2, written separately from the matrix form and
+  pinned against it); fast enough to time on the host and to run the
+  workloads at full size and length.
 
 ``yee`` is a plain Yee FDTD reference, used only to pin the interior.
 

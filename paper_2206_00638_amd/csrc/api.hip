@@ -741,9 +741,10 @@ void* pool_other(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool : c->
 
 
 // One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E
-// update, each update one launch per block kind followed by the energy
-// finish: slot n += H part of W^n; slot n+1 = E part of W^{n+1}, and the
-// step index advances.
+// update, each update one launch per block kind.  The H workgroups write the
+// H part of W^n per tile, the E workgroups add the E part (from E^n) and the
+// same tile's H partial, and the finish kernel sums the E partials into
+// energy slot n and advances the step index.
 // One leapfrog step of the state that `a` points at (pool, face buffers,
 // energy / probe rings, step counter): the forward state (kargs(c)) or the
 // adjoint state of sbp_adjoint.

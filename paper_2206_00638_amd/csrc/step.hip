@@ -10,17 +10,20 @@
 // nodes of a block face take the Appendix closure rows with the SAT row
 // changes folded in (PEC in the H update, PMC / absorbing in the E update,
 // interface rows adding the gathered neighbour value): per lane for x, per
-// thread for y, per plane (wave-uniform) for z.  All in the field precision;
-// energies and interface interpolation accumulate in fp64.  Every node
-// update is a pure function of the previous fields, so the results do not
-// depend on the tile shape or on how tiles map to workgroups.
+// thread for y, per plane (wave-uniform) for z.  The field update runs in
+// the field precision; the energy sums, the interface interpolation and the
+// interface penalty (the neighbour's value joining a boundary row) are
+// formed in fp64, the interface row being narrowed once.  Every node update
+// is a pure function of the previous fields, so the results do not depend on
+// the tile shape or on how tiles map to workgroups.
 //
-// The tile list is walked XCD-aware: the workgroups resident on one XCD take
-// a contiguous range of tiles, so the y-neighbour rows a tile re-reads were
-// fetched into the same L2 by the tile before it.
+// The tile list is walked XCD-aware (TileIter): groups of consecutive tiles
+// go to one XCD, so the y-neighbour rows a tile re-reads were mostly fetched
+// into the same L2 by the tile before it.
 //
 // The discrete energy W^n (E16 with the leapfrog pairing of H) is summed in
-// fp64 per workgroup and finished by the last workgroup of each launch.
+// fp64 per workgroup; the E workgroup of a tile adds the H partial of the
+// same tile to its own, and k_finish sums the partials in a fixed order.
 
 #include "plan.h"
 
@@ -209,15 +212,25 @@ __device__ __forceinline__ T xrow(const TRow<T>& R, T u0, T un, int dn, T ux, in
   return R.c0 * pick(R.s) + R.c1 * pick(R.s + 1) + R.c2 * pick(R.s + 2);
 }
 
+// Interface row: the own-value part r (field precision) plus the gathered
+// neighbour value f (fp64) times the row's neighbour coefficient, which is
+// -1/h on a low face and +1/h on a high face.  The penalty is added in fp64
+// and the row narrowed once.
+template <typename T>
+__device__ __forceinline__ T pen(T r, T cn, double ih, double f) {
+  return (T)((double)r + (cn > T(0) ? ih : -ih) * f);
+}
+
 // Closure row applied to u along stride st at node offset o; on an
-// interface row the gathered neighbour value a.face[fo] joins it.
+// interface row the gathered neighbour value a.face[fo] joins it (ih: 1/h
+// of the row's axis in fp64).
 template <typename T, bool IFACE>
 __device__ __forceinline__ T drow(const KArgs& a, const T* __restrict__ u, long long o, long long st,
-                                  const TRow<T>& R, long long fo) {
+                                  const TRow<T>& R, long long fo, double ih) {
   const T* p = u + o + (long long)R.s * st;
   T v = R.c0 * p[0] + R.c1 * p[st] + R.c2 * p[2 * st];
   if constexpr (IFACE) {
-    if (R.nbr) v += R.cn * (T)a.face[fo];
+    if (R.nbr) v = pen<T>(v, R.cn, ih, a.face[fo]);
   }
   return v;
 }
@@ -521,9 +534,11 @@ struct HIn {
   T ex, ey, ez, hx, hy, hz;
   T ey_z, ex_z, ez_y, ex_y, ez_x, ey_x;
   T ez_xx, ey_xx;  // x closure rows: the value beyond the interior pair (h_xd)
-  T ez_f, ey_f;    // interface x rows: the neighbour's face values
-  T ez_yy, ex_yy, ez_fy, ex_fy;  // y rows of interface blocks: likewise
-  T ey_zz, ex_zz, ey_fz, ex_fz;  // z rows of interface blocks: likewise
+  double ez_f, ey_f;  // interface x rows: the neighbour's face values (fp64)
+  T ez_yy, ex_yy;     // y rows of interface blocks: likewise
+  double ez_fy, ex_fy;
+  T ey_zz, ex_zz;     // z rows of interface blocks: likewise
+  double ey_fz, ex_fz;
   T psi[6];  // absorbing layers: the node's recursion variables (slots 0-5)
 };
 
@@ -555,8 +570,8 @@ __device__ __forceinline__ void h_load(HIn<T>& v, const BC<T>& c, const T* __res
 template <typename T>
 __device__ __forceinline__ void h_face(const KArgs& a, const BC<T>& c, const FaceCol& fc, int k, HIn<T>& v) {
   const long long by = c.ny + 2, bz = c.nz + 2, fo = fc.x + by * k;
-  v.ez_f = (T)a.face[fo + by * bz];
-  v.ey_f = (T)a.face[fo];
+  v.ez_f = a.face[fo + by * bz];
+  v.ey_f = a.face[fo];
 }
 
 // The z rows of an interface block at plane k (wave-uniform: only the planes
@@ -574,8 +589,8 @@ __device__ __forceinline__ void h_zrow(const KArgs& a, const BC<T>& c, const SBP
   }
   if (row_of<T>(Bc, 2, k, true).nbr) {
     const long long bx = c.nx + 2, by = c.ny + 2, fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
-    v.ey_fz = (T)a.face[fo + bx * by];
-    v.ex_fz = (T)a.face[fo];
+    v.ey_fz = a.face[fo + bx * by];
+    v.ex_fz = a.face[fo];
   }
 }
 
@@ -596,8 +611,8 @@ __device__ __forceinline__ void h_yrow(const KArgs& a, const BC<T>& c, const Fac
   }
   if (ry.nbr) {
     const long long bx = c.nx + 2, bz = c.nz + 2, fo = fc.y + bx * k;
-    v.ez_fy = (T)a.face[fo + bx * bz];
-    v.ex_fy = (T)a.face[fo];
+    v.ez_fy = a.face[fo + bx * bz];
+    v.ex_fy = a.face[fo];
   }
 }
 
@@ -632,13 +647,13 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
       dzEy = xrow<T>(rz, v.ey, v.ey_z, -1, v.ey_zz, zd);
       dzEx = xrow<T>(rz, v.ex, v.ex_z, -1, v.ex_zz, zd);
       if (rz.nbr) {
-        dzEy += rz.cn * v.ey_fz;
-        dzEx += rz.cn * v.ex_fz;
+        dzEy = pen<T>(dzEy, rz.cn, Bc.ih[2], v.ey_fz);
+        dzEx = pen<T>(dzEx, rz.cn, Bc.ih[2], v.ex_fz);
       }
     } else {
       const long long fo = Bc.fboff[k < 3 ? 4 : 5] + i + bx * j;
-      dzEy = drow<T, IFACE>(a, Ey, o, sxy, rz, fo + bx * by);
-      dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo);
+      dzEy = drow<T, IFACE>(a, Ey, o, sxy, rz, fo + bx * by, Bc.ih[2]);
+      dzEx = drow<T, IFACE>(a, Ex, o, sxy, rz, fo, Bc.ih[2]);
     }
   }
   if (!yin) {
@@ -647,13 +662,13 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
       dyEz = xrow<T>(ry, v.ez, v.ez_y, -1, v.ez_yy, yd);
       dyEx = xrow<T>(ry, v.ex, v.ex_y, -1, v.ex_yy, yd);
       if (ry.nbr) {
-        dyEz += ry.cn * v.ez_fy;
-        dyEx += ry.cn * v.ex_fy;
+        dyEz = pen<T>(dyEz, ry.cn, Bc.ih[1], v.ez_fy);
+        dyEx = pen<T>(dyEx, ry.cn, Bc.ih[1], v.ex_fy);
       }
     } else {
       const long long fo = fc.y + bx * k;
-      dyEz = drow<T, IFACE>(a, Ez, o, sx, ry, fo + bx * bz);
-      dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo);
+      dyEz = drow<T, IFACE>(a, Ez, o, sx, ry, fo + bx * bz, Bc.ih[1]);
+      dyEx = drow<T, IFACE>(a, Ex, o, sx, ry, fo, Bc.ih[1]);
     }
   }
   if (!xin) {
@@ -661,8 +676,8 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     dxEz = xrow<T>(rx, v.ez, v.ez_x, -1, v.ez_xx, xd);
     dxEy = xrow<T>(rx, v.ey, v.ey_x, -1, v.ey_xx, xd);
     if (IFACE && rx.nbr) {
-      dxEz += rx.cn * v.ez_f;
-      dxEy += rx.cn * v.ey_f;
+      dxEz = pen<T>(dxEz, rx.cn, Bc.ih[0], v.ez_f);
+      dxEy = pen<T>(dxEy, rx.cn, Bc.ih[0], v.ey_f);
     }
   }
   if constexpr (PML) {  // absorbing layers: H terms sit on the "-" grid of their axis
@@ -720,7 +735,8 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
 }
 
 // H half step over the tiles [t0, t1) of the tile list (one kind of block),
-// one node per thread in flat (i, j, k) order, plus the H part of W^n:
+// each thread marching a node column through the tile's planes, plus the H
+// part of W^n:
 // 1/2 mu w H^{n+1/2} H^{n-1/2}.  GEN: per-cell permeability or interfaces.
 template <typename T, bool GEN, bool IFACE, bool PML, bool TF = false>
 __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
@@ -853,8 +869,9 @@ struct EIn {
   T ex, ey, ez, hx, hy, hz;
   T hy_z, hx_z, hz_y, hx_y, hz_x, hy_x;
   T hz_xx, hy_xx;  // x closure rows: the value beyond the interior pair (e_xd)
-  T hz_f, hy_f;    // interface x rows: the neighbour's face values
-  T hz_yy, hx_yy, hz_fy, hx_fy;  // y rows of interface blocks: likewise
+  double hz_f, hy_f;  // interface x rows: the neighbour's face values (fp64)
+  T hz_yy, hx_yy;     // y rows of interface blocks: likewise
+  double hz_fy, hx_fy;
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
   T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
@@ -912,8 +929,8 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
 template <typename T>
 __device__ __forceinline__ void e_face(const KArgs& a, const BC<T>& c, const FaceCol& fc, int k, EIn<T>& v) {
   const long long by = c.ny + 2, fs = by * (c.nz + 2), fo = fc.x + by * k + 2 * fs;
-  v.hz_f = (T)a.face[fo + fs];
-  v.hy_f = (T)a.face[fo];
+  v.hz_f = a.face[fo + fs];
+  v.hy_f = a.face[fo];
 }
 
 // The y rows of an interface block at plane k (Hz and Hx slots of the y face).
@@ -929,8 +946,8 @@ __device__ __forceinline__ void e_yrow(const KArgs& a, const BC<T>& c, const Fac
   }
   if (ry.nbr) {
     const long long bx = c.nx + 2, fs = bx * (c.nz + 2), fo = fc.y + bx * k + 2 * fs;
-    v.hz_fy = (T)a.face[fo + fs];
-    v.hx_fy = (T)a.face[fo];
+    v.hz_fy = a.face[fo + fs];
+    v.hx_fy = a.face[fo];
   }
 }
 
@@ -963,8 +980,8 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     if (k <= nz) {
       const TRow<T> rz = row_of<T>(Bc, 2, k, false);
       const long long fs = bx * by, fo = Bc.fboff[k < 2 ? 4 : 5] + i + bx * j + 2 * fs;
-      dzHy = drow<T, IFACE>(a, Hy, o, sxy, rz, fo + fs);
-      dzHx = drow<T, IFACE>(a, Hx, o, sxy, rz, fo);
+      dzHy = drow<T, IFACE>(a, Hy, o, sxy, rz, fo + fs, Bc.ih[2]);
+      dzHx = drow<T, IFACE>(a, Hx, o, sxy, rz, fo, Bc.ih[2]);
     } else {
       dzHy = dzHx = T(0);  // Ex, Ey do not exist on plane nz+1
     }
@@ -975,13 +992,13 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
       dyHz = xrow<T>(ry, v.hz, v.hz_y, 1, v.hz_yy, yd);
       dyHx = xrow<T>(ry, v.hx, v.hx_y, 1, v.hx_yy, yd);
       if (ry.nbr) {
-        dyHz += ry.cn * v.hz_fy;
-        dyHx += ry.cn * v.hx_fy;
+        dyHz = pen<T>(dyHz, ry.cn, Bc.ih[1], v.hz_fy);
+        dyHx = pen<T>(dyHx, ry.cn, Bc.ih[1], v.hx_fy);
       }
     } else {
       const long long fs = bx * bz, fo = fc.y + bx * k + 2 * fs;
-      dyHz = drow<T, IFACE>(a, Hz, o, sx, ry, fo + fs);
-      dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo);
+      dyHz = drow<T, IFACE>(a, Hz, o, sx, ry, fo + fs, Bc.ih[1]);
+      dyHx = drow<T, IFACE>(a, Hx, o, sx, ry, fo, Bc.ih[1]);
     }
   }
   if (!xin) {
@@ -989,8 +1006,8 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
     dxHz = xrow<T>(rx, v.hz, v.hz_x, 1, v.hz_xx, xd);
     dxHy = xrow<T>(rx, v.hy, v.hy_x, 1, v.hy_xx, xd);
     if (IFACE && rx.nbr) {
-      dxHz += rx.cn * v.hz_f;
-      dxHy += rx.cn * v.hy_f;
+      dxHz = pen<T>(dxHz, rx.cn, Bc.ih[0], v.hz_f);
+      dxHy = pen<T>(dxHy, rx.cn, Bc.ih[0], v.hy_f);
     }
   }
   if constexpr (PML) {  // absorbing layers: E terms sit on the "+" grid of their axis
@@ -1087,9 +1104,11 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   return (lw.x * kxy) * mx * (ex * ex) + (lw.y * kxy) * my * (ey * ey) + (lw.z * kz) * mz * (ez * ez);
 }
 
-// E step over the tiles [t0, t1) of the tile list (one kind of block), one
-// node per thread in flat (i, j, k) order, plus the E part of W^{n+1}:
-// 1/2 eps w (E^{n+1})^2.  The last E launch of a step advances the step
+// E step over the tiles [t0, t1) of the tile list (one kind of block): each
+// thread marches a node column through the tile's planes.  The workgroup
+// adds the E part of W^n, 1/2 eps w (E^n)^2 (E^n being the centre values it
+// loads anyway), to the H partial of the same tile from the H launch; the
+// finish kernel then writes W^n to energy slot n and advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
 template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML, bool TF = false>
 __global__ __launch_bounds__(256) void k_e_update(KArgs a) {

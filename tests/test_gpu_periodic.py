@@ -3,19 +3,18 @@ oracle: real fields with zero phase, and complex fields with a Bloch phase
 (the HIP path holds the real and imaginary parts in two blocks whose
 periodic faces mix them by cos / sin alpha).
 
-Tolerances as for the other parity tests: relative L2 per component array,
-probe series and energy series, fp64 1e-12 and fp32 1e-5."""
+The bar is the one of the other parity tests (``gpu_util.check_fields``):
+relative L2 against the fp64 oracle, fp64 1e-12 per component array and per
+field, fp32 1e-5 per field, and the probe and energy series likewise."""
 import math
 
 import numpy as np
 import pytest
 
-from gpu_util import COMPS, field_errors, per_field_errors, rel_l2, write_fields
+from gpu_util import COMPS, TOL, check_fields, rel_l2, write_fields
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5}
-FLOOR = {"f64": 1e-6, "f32": 1e-1}
 
 
 @pytest.fixture(scope="module")
@@ -65,10 +64,8 @@ def _run(sbp, problem, prec, steps, init):
     return out
 
 
-def _check(g, r, prec, complex_probes):
-    errs = field_errors(g["fields"], r["fields"], FLOOR[prec])
-    assert max(errs.values()) < TOL[prec], errs
-    assert max(per_field_errors(g["fields"], r["fields"]).values()) < TOL[prec]
+def _check(g, r, prec, complex_probes, label):
+    check_fields(g["fields"], r["fields"], prec, label)
     assert rel_l2(g["energy"], r["energy"]) < TOL[prec]
     # probes sample the block of the real part
     assert rel_l2(g["probes"], np.real(r["probes"]) if complex_probes else r["probes"]) < TOL[prec]
@@ -82,7 +79,7 @@ def test_periodic_zero_phase(sbp, prec):
     steps = 40
     g = _run(sbp, prob, prec, steps, init)
     r = S.run(prob, steps=steps, init=init)
-    _check(g, r, prec, False)
+    _check(g, r, prec, False, "periodic x, z zero phase")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -96,7 +93,7 @@ def test_bloch_phase_complex_fields(sbp, prec, periodic):
     g = _run(sbp, prob, prec, steps, init)
     r = S.run(prob, steps=steps, init=init)
     assert np.iscomplexobj(r["e"])
-    _check(g, r, prec, True)
+    _check(g, r, prec, True, f"Bloch {periodic}")
 
 
 def test_bloch_energy_conserved_and_graph(sbp):
@@ -219,7 +216,6 @@ def test_bloch_box_workload_reduced(sbp, prec):
     gp = ctx.read_probe(0, 0, steps)
     ctx.close()
     r = S.run(prob, steps=steps)
-    errs = field_errors(g, r["fields"], FLOOR[prec])
-    assert max(errs.values()) < TOL[prec], errs
+    check_fields(g, r["fields"], prec, "Bloch box 16^3")
     assert rel_l2(ge, r["energy"]) < TOL[prec]
     assert rel_l2(gp, np.real(r["probes"][0])) < TOL[prec]
