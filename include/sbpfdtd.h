@@ -171,6 +171,25 @@ sbp_status sbp_set_materials(sbp_ctx *ctx, int block, const double *eps_r, const
 /* Enqueues nsteps leapfrog steps (H half step, then E step, Section V). */
 sbp_status sbp_step(sbp_ctx *ctx, long nsteps);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * while they step (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same steps as sbp_step (bitwise
+ * equal fields, probes and energies), but the per-step scratch of the
+ * kernels (the energy partial sums of every launch and the interface face
+ * buffers) lives in a fixed device array of 16 MiB per GPU (2 MiB of partial
+ * sums, 14 MiB of face values), set up by sbp_create, instead of buffers of
+ * the context.  Eager launches only: no graph is captured or replayed and no
+ * timing events are recorded (sbp_last_step_ms does not cover these steps).
+ * Calls no allocating routine.  Returns SBP_EINVAL, before enqueuing
+ * anything, if the context's launch shape needs more than 262144 partial
+ * sums or its interfaces more than 1835008 face values (then use sbp_step).
+ * Every context on a GPU uses that GPU's one array, which keeps the last
+ * call's contents; each call first clears the face-buffer part (with a
+ * kernel, no memset), and every partial sum is written before it is read.
+ * Calls that overlap in time on one GPU, from different streams or threads,
+ * race and must be serialised by the caller. */
+sbp_status sbp_step_static(sbp_ctx *ctx, long nsteps);
+
 /* Number of steps taken so far. */
 sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
 

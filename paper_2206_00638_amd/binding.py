@@ -46,6 +46,7 @@ SIGNATURES = {
     "sbp_finalize": [_P, _D, _I, _L, _DP],
     "sbp_set_materials": [_P, _I, _P, _P, _P],
     "sbp_step": [_P, _L],
+    "sbp_step_static": [_P, _L],
     "sbp_steps_done": [_P, ctypes.POINTER(_L)],
     "sbp_field_shape": [_P, _I, _I, _IP],
     "sbp_read_field": [_P, _I, _I, _P, _S],
@@ -219,6 +220,9 @@ class Context:
 
     def step(self, nsteps):
         self._chk(self._lib.sbp_step(self.h, int(nsteps)))
+
+    def step_static(self, nsteps):
+        self._chk(self._lib.sbp_step_static(self.h, int(nsteps)))
 
     def steps_done(self):
         n = ctypes.c_long()

@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -129,6 +131,8 @@ struct sbp_ctx {
   double* d_probes = nullptr;
   double* d_partials = nullptr;
   size_t partials_cap = 0;
+  size_t partials_need = 0;    // partial sums one step of the current launch shape writes
+  double* scratch = nullptr;   // this device's fixed scratch array (sbp_step_static)
   StepState* d_st = nullptr;
   double* d_face = nullptr;
   // convolutional PML (faces set to SBP_CPML): layer parameters, per-block
@@ -673,6 +677,7 @@ sbp_status build_tiles(sbp_ctx* c) {
   for (int kind = 0; kind < 2; ++kind)
     if (c->fk_t1[kind] > c->fk_t0[kind]) fsum += (size_t)grid_of(c, c->fk_t1[kind] - c->fk_t0[kind]);
   const size_t grid = 2 * sum + fsum + 8;  // partial sums of all launches of a step
+  c->partials_need = grid;
   if (grid > c->partials_cap) {
     dfree(c, c->d_partials);
     c->d_partials = (double*)dalloc(c, grid * sizeof(double));
@@ -840,6 +845,43 @@ void insert(std::vector<T>& box, const DevBlock& d, const int s[3], const double
       for (int i = 0; i < s[0]; ++i) box[(size_t)i + d.sx * j + d.sxy * k] = (T)src[q++];
 }
 
+// ------------------------------------------------ allocation-free stepping
+// Scratch memory of sbp_step_static: the energy partial sums of a step
+// (kStaticPartials doubles) followed by the interface face buffers.  One
+// copy per GPU, held until the process ends.  In host code `scratch` is a
+// host-side stand-in: its address on each device comes from
+// hipGetSymbolAddress (static_scratch), and only that address is handed to
+// kernels.
+constexpr size_t kStaticBytes = size_t(16) << 20;
+constexpr size_t kStaticDoubles = kStaticBytes / sizeof(double);
+constexpr size_t kStaticPartials = size_t(1) << 18;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device -> address of `scratch` there
+
+// Zeroes n doubles (a kernel rather than a memset, so that a caller may
+// capture the call in a graph).
+__global__ __launch_bounds__(256) void k_zero(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Address of `scratch` on `device`, which must be current: looked up once
+// per device and kept.
+hipError_t static_scratch(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = g_scratch_ptr.emplace(device, (double*)p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -858,7 +900,7 @@ sbp_status sbp_create(sbp_ctx** out, sbp_prec prec, void* hip_stream, sbp_alloc_
   c->alloc = alloc;
   c->free_fn = free_fn;
   c->user = user;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess || static_scratch(c->device, &c->scratch) != hipSuccess) {
     delete c;
     return SBP_EHIP;
   }
@@ -1497,6 +1539,41 @@ sbp_status sbp_step(sbp_ctx* c, long nsteps) {
   }
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   c->timed = true;
+  c->nstep += nsteps;
+  return SBP_OK;
+}
+
+sbp_status sbp_step_static(sbp_ctx* c, long nsteps) {
+  if (!c) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "step before finalize");
+  if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
+  if (!c->scratch) return fail(c, SBP_EHIP, "no static scratch on this device");
+  if (c->partials_need > kStaticPartials)
+    return fail(c, SBP_EINVAL,
+                "launch shape needs " + std::to_string(c->partials_need) +
+                    " partial sums; the static scratch holds " + std::to_string(kStaticPartials) +
+                    " (larger tiles, or sbp_step)");
+  if (c->face_elems > kStaticDoubles - kStaticPartials)
+    return fail(c, SBP_EINVAL,
+                "interfaces need " + std::to_string(c->face_elems) + " face values; the static scratch holds " +
+                    std::to_string(kStaticDoubles - kStaticPartials) + " (use sbp_step)");
+  if (nsteps == 0) return SBP_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  KArgs a = kargs(c);
+  a.partials = c->scratch;
+  a.face = c->scratch + kStaticPartials;
+  // the face buffers hold slots no gather writes (nodes a component does not
+  // have), which the kernels read as zero: clear what the last call left
+  const size_t nf = c->face_elems;
+  const int zb = (int)std::min<size_t>((nf + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero, dim3(zb), dim3(256), 0, c->stream, c->scratch + kStaticPartials, nf);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, launch_sources(a, c->stream));  // source values of the current step
+  for (long s = 0; s < nsteps; ++s) {
+    const sbp_status st = enqueue_step_on(c, a, false);
+    if (st != SBP_OK) return st;
+  }
+  c->timed = false;
   c->nstep += nsteps;
   return SBP_OK;
 }
