@@ -62,9 +62,10 @@ typedef enum { SBP_GAUSS = 0, SBP_MODGAUSS = 1 } sbp_wave;
 typedef void *(*sbp_alloc_fn)(size_t bytes, void *user);
 typedef void (*sbp_free_fn)(void *ptr, void *user);
 
-/* Creates a context computing fields in `prec` on HIP stream `hip_stream`
- * (NULL = default stream) of the current device.  `alloc`/`free_fn` may be
- * NULL (hipMalloc/hipFree). */
+/* Creates a context: the leapfrog state of Section V (E^n and H^{n-1/2} on
+ * the grids of Table T1, for every block added) computed in `prec` on HIP
+ * stream `hip_stream` (NULL = default stream) of the current device.
+ * `alloc`/`free_fn` may be NULL (hipMalloc/hipFree). */
 sbp_status sbp_create(sbp_ctx **out, sbp_prec prec, void *hip_stream,
                       sbp_alloc_fn alloc, sbp_free_fn free_fn, void *user);
 
@@ -154,7 +155,9 @@ sbp_status sbp_set_cpml(sbp_ctx *ctx, int cells, int order, double sigma_factor,
 sbp_status sbp_add_source(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int k,
                           sbp_wave waveform, const double p[3], double amplitude, int *id);
 
-/* Probe of one node per step: sample n is E^{n+1} (or H^{n+1/2}). */
+/* Probe of one node per step (the field records of Section VI's examples):
+ * sample n is E^{n+1} (or H^{n+1/2}), node (i,j,k) on the component's grid
+ * of Table T1. */
 sbp_status sbp_add_probe(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int k, int *id);
 
 /* Builds the plan and device buffers.  dt = cfl_fraction times the Yee limit
@@ -164,7 +167,9 @@ sbp_status sbp_add_probe(sbp_ctx *ctx, int block, sbp_comp c, int i, int j, int 
 sbp_status sbp_finalize(sbp_ctx *ctx, double cfl_fraction, int force, long history,
                         double *dt_out);
 
-/* Replaces the per-cell materials of a block after finalize (NULL = 1,1,0). */
+/* Replaces the per-cell materials of a block after finalize (NULL = 1,1,0):
+ * the eps, mu and sigma of E7-E12 and Section V's lossy update, formed per
+ * node as the mean of the cells containing the node, as at sbp_add_block. */
 sbp_status sbp_set_materials(sbp_ctx *ctx, int block, const double *eps_r, const double *mu_r,
                              const double *sigma);
 
@@ -196,8 +201,9 @@ sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
 /* Node counts (Sx, Sy, Sz) of a component of a block. */
 sbp_status sbp_field_shape(const sbp_ctx *ctx, int block, sbp_comp c, int shape[3]);
 
-/* Copies a component to / from host doubles (Sx*Sy*Sz, i fastest).  Writing
- * sets E^n or H^{n-1/2} of the current step. */
+/* Copies a component to / from host doubles (Sx*Sy*Sz on the component's
+ * grid of Table T1, i fastest).  Writing sets E^n or H^{n-1/2} of the
+ * current step (the leapfrog state of Section V). */
 sbp_status sbp_read_field(sbp_ctx *ctx, int block, sbp_comp c, double *dst, size_t count);
 sbp_status sbp_write_field(sbp_ctx *ctx, int block, sbp_comp c, const double *src, size_t count);
 
@@ -207,8 +213,9 @@ sbp_status sbp_read_energy(sbp_ctx *ctx, long first, long count, double *dst);
 /* Probe samples n = first .. first+count-1 of probe `id`. */
 sbp_status sbp_read_probe(sbp_ctx *ctx, int id, long first, long count, double *dst);
 
-/* Device-to-device snapshot of the time-stepping state: the fields, the
- * step index, the CPML recursion variables and the TF/SF incident line.
+/* Device-to-device snapshot of the time-stepping state (Section V's E^n
+ * and H^{n-1/2}, with the step index n), the CPML recursion variables and the
+ * TF/SF incident line.
  * bytes must be >= sbp_state_bytes(); sbp_load_state restores a snapshot of
  * the same context (the sources' values follow from the step index). */
 sbp_status sbp_state_bytes(const sbp_ctx *ctx, size_t *bytes);
@@ -225,7 +232,10 @@ sbp_status sbp_load_state(sbp_ctx *ctx, const void *dev_buf, size_t bytes);
  * checkpoint and runs the adjoint backwards through it.  region = {i0, i1,
  * j0, j1, k0, k1}: half-open cell box of `block`.  Writes J to *J_out (host)
  * and dJ/d eps_r of every cell of `block` to grad_eps_dev (device doubles,
- * nx*ny*nz, i fastest; the caller owns it).  Blocks must be lossless (no
+ * nx*ny*nz, i fastest; the caller owns it); the cell sums run in a fixed
+ * order, so repeated calls give the same bits.  grad_eps_dev = NULL
+ * evaluates J alone (the forward run; no checkpoints, no reverse sweep, one
+ * double of device memory).  Blocks must be lossless (no
  * conductivity, no absorbing faces): SBP_EINVAL otherwise.  Afterwards the
  * context is at the state after the N forward steps, with their energy and
  * probe samples, as after sbp_step(ctx, N).  Device memory for

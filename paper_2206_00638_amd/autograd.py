@@ -7,9 +7,11 @@ state it had when the objective was created, and returns
 
     J = dt * sum_{n=1..N} sum_{cells in region} |Ebar^n|^2
 
-as a 0-d tensor.  The forward call already runs the reverse sweep on the GPU
-(sbp_adjoint computes J and the gradient together); ``backward`` only scales
-the stored gradient.  All arithmetic runs in the HIP library.
+as a 0-d tensor.  When autograd will need the gradient, the forward call
+runs the reverse sweep on the GPU as well (sbp_adjoint computes J and the
+gradient together) and ``backward`` only scales the stored gradient;
+otherwise it runs the forward steps alone.  All arithmetic runs in the HIP
+library.
 """
 import numpy as np
 import torch
@@ -20,8 +22,9 @@ from .binding import build_problem
 class _EpsObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, eps_r, obj):
-        grad = obj._evaluate(eps_r)
-        ctx.save_for_backward(grad)
+        grad = obj._evaluate(eps_r, with_grad=ctx.needs_input_grad[0])
+        if grad is not None:
+            ctx.save_for_backward(grad)
         return torch.tensor(obj.last_J, dtype=torch.float64, device=eps_r.device)
 
     @staticmethod
@@ -52,12 +55,15 @@ class PermittivityObjective:
         self.shape = (blk["n"][2], blk["n"][1], blk["n"][0])
         self.last_J = None
 
-    def _evaluate(self, eps_r):
+    def _evaluate(self, eps_r, with_grad=True):
         if tuple(eps_r.shape) != self.shape:
             raise ValueError(f"eps_r must have shape {self.shape}")
         e = eps_r.detach().to("cpu", torch.float64).numpy()
         self.ctx.set_materials(self.block, np.ascontiguousarray(e), self._mu, self._sigma)
         self.ctx.load_state(self._start.data_ptr(), self._nbytes)
+        if not with_grad:  # J alone: the forward steps, no reverse sweep
+            self.last_J = self.ctx.adjoint(self.block, self.nsteps, self.region, None, self.ckpt_every)
+            return None
         grad = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
         self.last_J = self.ctx.adjoint(self.block, self.nsteps, self.region, grad.data_ptr(), self.ckpt_every)
         return grad.to(eps_r.device)

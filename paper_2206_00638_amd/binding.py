@@ -268,11 +268,11 @@ class Context:
 
     def adjoint(self, block, nsteps, region, grad_ptr, ckpt_every=0):
         """J and dJ/d eps_r of ``block`` (written to the device doubles at
-        ``grad_ptr``); see sbp_adjoint."""
+        ``grad_ptr``; 0 or None: J alone); see sbp_adjoint."""
         r = (ctypes.c_int * 6)(*[int(v) for v in region])
         J = ctypes.c_double()
         self._chk(self._lib.sbp_adjoint(self.h, int(block), int(nsteps), r, int(ckpt_every), ctypes.byref(J),
-                                        ctypes.c_void_p(grad_ptr)))
+                                        ctypes.c_void_p(grad_ptr or None)))
         return J.value
 
     def set_launch(self, tx, ty, cz, workgroups=0):

@@ -180,8 +180,8 @@ __global__ __launch_bounds__(256) void k_adj_source(void* apool, const void* epo
 
 // S += p^{n+1} (E^{n+1} - E^n) over the block's three E component arrays,
 // flat (n = 3 x the component stride; nodes outside a component's grid are
-// skipped in k_adj_cells).  With w_E and Cb constant in time, dJ/dCb of the
-// node is (w_E / Cb^2) S after the sweep; k_adj_cells applies the factor.
+// dropped in k_adj_node).  With w_E and Cb constant in time, dJ/dCb of the
+// node is (w_E / Cb^2) S after the sweep; k_adj_node applies the factor.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_grad(const T* __restrict__ p, const T* __restrict__ enew,
                                                  const T* __restrict__ eold, long long n, double* __restrict__ S) {
@@ -189,12 +189,16 @@ __global__ __launch_bounds__(256) void k_adj_grad(const T* __restrict__ p, const
     S[t] += (double)p[t] * ((double)enew[t] - (double)eold[t]);
 }
 
-// dJ/d eps_r per cell: sum over the E nodes of dJ/dCb * dCb/d eps_r(cell),
+// dJ/d eps_r per cell: the sum over the E nodes of dJ/dCb * dCb/d eps_r(cell),
 // with dJ/dCb = (w_E / Cb^2) S from k_adj_grad's sums and dCb/d eps_r =
-// -Cb / S_eps for each occurrence of the cell among the node's four.
+// -Cb / S_eps for each occurrence of the cell among the node's four.  Two
+// passes, no atomics, so the result does not depend on the order in which
+// workgroups run: k_adj_node turns each E node's S in place into its
+// contribution per occurrence, d = -(w_E S / Cb) / S_eps; k_adj_cells then
+// sums, for each cell, the contributions of the E nodes around it in a fixed
+// order, each as often as the cell occurs in the node's (clamped) four.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, const void* mat_eps, int block,
-                                                  const double* G, double* grad) {
+__global__ __launch_bounds__(256) void k_adj_node(const DevBlock* blocks, const void* mat_eps, int block, double* G) {
   const DevBlock& B = blocks[block];
   const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
   const long long sx = B.sx, sxy = B.sxy;
@@ -208,14 +212,59 @@ __global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, const
     const long long rr = q - k * plane;
     const int j = (int)(rr / sx), i = (int)(rr - j * sx);
     const bool valid = c == 0 ? (j <= ny && k <= nz) : (c == 1 ? (i <= nx && k <= nz) : (i <= nx && j <= ny));
-    if (!valid) continue;
     const long long o = i + sx * j + sxy * k;
-    const double sum = G[c * B.csz + o];
-    if (sum == 0.0) continue;
+    double& g = G[c * B.csz + o];
+    if (!valid || g == 0.0) {
+      g = 0.0;
+      continue;
+    }
     const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
     const double cb = node_cb(B, nc.S);
-    const double d = -(e_weight(B, c, i, j, k) * sum / cb) / nc.S;
-    for (int m = 0; m < 4; ++m) atomicAdd(&grad[nc.cell[m]], d);
+    g = -(e_weight(B, c, i, j, k) * g / cb) / nc.S;
+  }
+}
+
+// Along one axis: the node indices whose cell list holds cell `cc`, and how
+// often.  "-" grid (the component's own axis): node r lies in cell
+// clamp(r - 1), so r = cc + 1, and also 0 for the first cell and n + 1 for
+// the last.  "+" grid: node r lies in cells clamp(r - 1) and clamp(r), so
+// r = cc (twice for the first cell) and r = cc + 1 (twice for the last).
+__device__ __forceinline__ int axis_nodes(bool minus, int n, int cc, int r[3], int m[3]) {
+  if (minus) {
+    int q = 0;
+    r[q] = cc + 1;
+    m[q++] = 1;
+    if (cc == 0) { r[q] = 0; m[q++] = 1; }
+    if (cc == n - 1) { r[q] = n + 1; m[q++] = 1; }
+    return q;
+  }
+  r[0] = cc;
+  m[0] = cc == 0 ? 2 : 1;
+  r[1] = cc + 1;
+  m[1] = cc == n - 1 ? 2 : 1;
+  return 2;
+}
+
+__global__ __launch_bounds__(256) void k_adj_cells(const DevBlock* blocks, int block, const double* G, double* grad) {
+  const DevBlock& B = blocks[block];
+  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
+  const long long ncell = (long long)nx * ny * nz;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int ci = (int)(t % nx), cj = (int)((t / nx) % ny), ck = (int)(t / ((long long)nx * ny));
+    double acc = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      int rx[3], mx[3], ry[3], my[3], rz[3], mz[3];
+      const int qx = axis_nodes(c == 0, nx, ci, rx, mx);
+      const int qy = axis_nodes(c == 1, ny, cj, ry, my);
+      const int qz = axis_nodes(c == 2, nz, ck, rz, mz);
+      const double* gc = G + c * B.csz;
+      for (int a = 0; a < qz; ++a)
+        for (int b = 0; b < qy; ++b)
+          for (int d = 0; d < qx; ++d)
+            acc += (double)(mx[d] * my[b] * mz[a]) * gc[rx[d] + B.sx * ry[b] + B.sxy * rz[a]];
+    }
+    grad[t] = acc;
   }
 }
 
@@ -248,9 +297,10 @@ hipError_t launch_adj_grad(const void* p, const void* enew, const void* eold, lo
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_adj_cells(const DevBlock* blocks, const void* mat_eps, int block, const double* G, double* grad,
+hipError_t launch_adj_cells(const DevBlock* blocks, const void* mat_eps, int block, double* G, double* grad,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_cells<T>, dim3(4096), dim3(256), 0, s, blocks, mat_eps, block, G, grad);
+  hipLaunchKernelGGL(k_adj_node<T>, dim3(4096), dim3(256), 0, s, blocks, mat_eps, block, G);
+  hipLaunchKernelGGL(k_adj_cells, dim3(4096), dim3(256), 0, s, blocks, block, (const double*)G, grad);
   return hipGetLastError();
 }
 
@@ -264,7 +314,7 @@ template hipError_t launch_adj_source<double>(void*, const void*, const DevBlock
                                               double, hipStream_t);
 template hipError_t launch_adj_grad<float>(const void*, const void*, const void*, long long, double*, hipStream_t);
 template hipError_t launch_adj_grad<double>(const void*, const void*, const void*, long long, double*, hipStream_t);
-template hipError_t launch_adj_cells<float>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
-template hipError_t launch_adj_cells<double>(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
+template hipError_t launch_adj_cells<float>(const DevBlock*, const void*, int, double*, double*, hipStream_t);
+template hipError_t launch_adj_cells<double>(const DevBlock*, const void*, int, double*, double*, hipStream_t);
 
 }  // namespace sbp

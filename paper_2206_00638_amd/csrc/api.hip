@@ -34,7 +34,7 @@ hipError_t launch_adj_source(void*, const void*, const DevBlock*, const void*, i
 template <typename T>
 hipError_t launch_adj_grad(const void*, const void*, const void*, long long, double*, hipStream_t);
 template <typename T>
-hipError_t launch_adj_cells(const DevBlock*, const void*, int, const double*, double*, hipStream_t);
+hipError_t launch_adj_cells(const DevBlock*, const void*, int, double*, double*, hipStream_t);
 template <typename T>
 hipError_t launch_gather(const DevBlock*, const FaceJob*, const GatherWG*, int, const Taps*, const KArgs&, int,
                          double*, hipStream_t);
@@ -1823,7 +1823,7 @@ sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
 
 sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], long ckpt_every, double* J_out,
                        double* grad_eps_dev) {
-  if (!c || !region || !J_out || !grad_eps_dev) return SBP_EINVAL;
+  if (!c || !region || !J_out) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "adjoint before finalize");
   if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
   if (nsteps < 1) return fail(c, SBP_EINVAL, "nsteps must be >= 1");
@@ -1849,6 +1849,30 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
   const size_t ncell = (size_t)hb.n[0] * hb.n[1] * hb.n[2];
   HIPCHK(c, hipSetDevice(c->device));
   drop_graph(c);
+  if (!grad_eps_dev) {
+    // the objective alone: the forward run with J summed after every step
+    double* Jd = (double*)dalloc(c, sizeof(double));
+    if (!Jd) return fail(c, SBP_ENOMEM, "adjoint buffer allocation failed");
+    auto run_j = [&]() -> sbp_status {
+      HIPCHK(c, hipMemsetAsync(Jd, 0, sizeof(double), c->stream));
+      const long long n0 = c->nstep;
+      HIPCHK(c, launch_sources(kargs(c), c->stream));
+      for (long n = 0; n < nsteps; ++n) {
+        const sbp_status s2 = enqueue_step(c, false);
+        if (s2 != SBP_OK) return s2;
+        void* now = pool_at(c, n0 + n + 1);
+        HIPCHK(c, f64 ? launch_adj_objective<double>(now, c->d_blocks, block, region, c->dt, Jd, c->stream)
+                      : launch_adj_objective<float>(now, c->d_blocks, block, region, c->dt, Jd, c->stream));
+      }
+      HIPCHK(c, hipMemcpyAsync(J_out, Jd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      return SBP_OK;
+    };
+    const sbp_status sj = run_j();
+    dfree(c, Jd);
+    if (sj == SBP_OK) c->nstep += nsteps;
+    return sj;
+  }
   // buffers: checkpoints, one segment of forward states, the adjoint state
   // (pool, face buffers, step counter, one-slot energy / probe rings), dJ/dCb
   std::vector<void*> tmp;

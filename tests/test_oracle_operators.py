@@ -150,6 +150,22 @@ def test_interp_minus_no_linear_exact_solution():
     assert lhs - rhs == pytest.approx(-1.0 / 8.0, abs=1e-12)
 
 
-def test_paper_numbers_file_present():
+def test_head_model_memory_overhead_matches_table_t3():
+    """The oracle's grids (Table T1 shapes: a "-" axis of n cells holds n + 2
+    nodes) against the Yee grid's on the head model's 300 x 300 x 235 cells:
+    the extra field nodes come to the memory overhead Table T3 measures
+    (984.1 MB against 973.5 MB, 1.089 %) within 0.01 percentage points; a
+    transposed component shape or a dropped face node moves it by more."""
+    from oracle.system import COMPS, comp_size
     with open(os.path.join(GOLDEN, "paper_numbers.json")) as fh:
-        assert json.load(fh)["cavity_dt_ps"] == 76.98
+        d = json.load(fh)
+    n = tuple(d["head_grid"])
+    nx, ny, nz = n
+    yee = (nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz +
+           (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
+    sbp = sum(comp_size(c, n) for c in COMPS)
+    measured = 100.0 * (d["head_memory_mb_sbp"] / d["head_memory_mb_fdtd"] - 1.0)
+    assert abs(100.0 * (sbp / yee - 1.0) - measured) < 0.01
+    # a shape mistake (Ex with n+1 instead of n+2 nodes along x) misses it
+    wrong = sbp - (ny + 1) * (nz + 1)
+    assert abs(100.0 * (wrong / yee - 1.0) - measured) > 0.01
