@@ -280,6 +280,68 @@ def subgrid(steps, warmup):
             "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
+def lts_leg(coarse_steps, warmup):
+    """Local time stepping on the subgrid geometry made lossless (27 blocks,
+    fp32): the refined block takes 2 substeps per coarse step of twice the
+    global step, the others the coarse step.  Timed beside the global
+    leapfrog of the same problem over the same physical time, from the same
+    seeded fields; the energy W^{n+1/2} over a run that forms it every step."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import lossless_subgrid
+    prob, fine = lossless_subgrid(1)
+    cells = int(sum(np.prod(b["n"]) for b in prob["blocks"]))
+
+    def fresh():
+        rng = np.random.default_rng(7)
+        stream = torch.cuda.Stream()
+        ctx = build_problem(prob, prec="f32", stream=stream, history=2 * (coarse_steps + warmup) + 64)
+        for b, blk in enumerate(prob["blocks"]):
+            for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+                shp = ctx.field_shape(b, c)
+                v = rng.standard_normal(shp[::-1]) * (1.0 if c[0] == "E" else 1.0 / 377.0)
+                ctx.write_field(b, c, v)
+        return ctx
+
+    def timed(fn, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(n)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    g = fresh()
+    dt = g.dt
+    g.step(2 * warmup)
+    ms_global = timed(g.step, 2 * coarse_steps)
+    g.close()
+    rec = {"workload": prob["name"], "cells": cells, "refined_block": fine, "substeps": 2,
+           "dt_coarse_over_global": 2.0, "global_ms_per_step": ms_global}
+    for every in (0, 100):
+        c = fresh()
+        c.lts_start([fine], 2, 2.0 * dt, every)
+        c.lts_step(warmup)
+        ms = timed(c.lts_step, coarse_steps)
+        info = c.lts_info()
+        c.close()
+        rec["lts_ms_per_coarse_step" + ("" if every == 0 else f"_energy_every_{every}")] = ms
+    rec["near"] = info
+    rec["speedup_same_physical_time"] = 2.0 * ms_global / rec["lts_ms_per_coarse_step"]
+    rec["value"] = cells * 2.0 / (rec["lts_ms_per_coarse_step"] * 1e-3) / 1e6
+    rec["unit"] = "Mcell-updates/s of the global leapfrog covering the same physical time"
+    # W^{n+1/2} formed every coarse step over a shorter run
+    c = fresh()
+    c.lts_start([fine], 2, 2.0 * dt, 1)
+    n = min(coarse_steps, 200)
+    c.lts_step(n)
+    w = c.read_energy(0, n)
+    c.close()
+    rec["energy_drift_fp32"] = float(np.abs(w / w[0] - 1.0).max())
+    rec["energy_steps"] = n
+    return rec
+
+
 def adjoint_leg(prec="f32"):
     """The adjoint workload: 96^3, J over 2000 steps, checkpoints every 45
     steps; one sbp_adjoint call (forward run, segment replays, reverse
@@ -500,6 +562,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-subgrid", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-lts", action="store_true")
     ap.add_argument("--no-bloch", action="store_true")
     ap.add_argument("--no-cpml", action="store_true")
     ap.add_argument("--no-tfsf", action="store_true")
@@ -569,6 +632,8 @@ def main():
             out["batched"]["accuracy"] = batched_accuracy()
     if not args.no_subgrid:
         out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+    if not args.no_lts:
+        out["lts"] = lts_leg(min(args.steps, 500), max(args.warmup, 10))
     out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpml:
         out["cpml"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20))

@@ -198,6 +198,47 @@ sbp_status sbp_step_static(sbp_ctx *ctx, long nsteps);
 /* Number of steps taken so far. */
 sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
 
+/* Local time stepping at 1:p for refined blocks.  The paper leaves the
+ * coupling of blocks of different mesh sizes to later work (Sections I and
+ * VII); the scheme here is the explicit, energy-conserving two-level local
+ * time stepping of Diaz and Grote on the E-only form of Section V's lossless
+ * leapfrog, E^{n+1} - 2 E^n + E^{n-1} = -dt^2 L E^n, L = -eps^-1 K_eh mu^-1
+ * K_he (E7-E12 with the SAT rows).  With P the projector onto the E nodes of
+ * the blocks listed in `refined`, a coarse step of length dt_coarse takes
+ * w = L (I - P) E^n and `substeps` substeps of dt_coarse / substeps in which
+ * only P q changes, then E^{n+1} = -E^{n-1} + 2 q_p, so the refined blocks
+ * advance with the short step and the others with the coarse one.  The
+ * scheme conserves W^{n+1/2} = 1/2 |E^{n+1} - E^n|_M^2 / dt^2
+ * + 1/2 <E^{n+1}, M (2 E^n - E^{n+1} - E^{n-1})> / dt^2 (M the E16 weights
+ * times eps); substeps = 1, or no refined block, is the leapfrog.
+ * It runs as the ordinary step of length dt_coarse on every block plus a
+ * correction on the refined blocks and the nodes of other blocks within a
+ * few cells of them; the H arrays hold the auxiliary H^{n+1/2} = H^{n-1/2}
+ * + dt B E^n of that step, which equals the leapfrog's H only where no
+ * correction has reached.
+ * sbp_lts_start takes the current state (E^0, H^{-1/2}); sbp_lts_step
+ * enqueues nsteps coarse steps, advancing the step index by one per coarse
+ * step.  With energy_every = K > 0, energy slot n holds W^{n+1/2} for the
+ * steps n that K divides and NaN for the others (K = 0: NaN throughout);
+ * forming it reads every E array twice more.  The context then holds E^n
+ * (read with sbp_read_field) and steps only by sbp_lts_step: sbp_step,
+ * sbp_step_static, sbp_save_state, sbp_load_state, sbp_set_fused,
+ * sbp_autotune and sbp_adjoint return SBP_ESTATE.  Device memory for up to
+ * seven more field pools is taken at sbp_lts_start.  Errors: SBP_EINVAL for
+ * substeps outside 1..64, a non-positive dt_coarse, a negative energy_every,
+ * a bad refined block, a lossy block (conductivity, absorbing face or
+ * layer), periodic faces, sources, a TF/SF box or the one-pass step;
+ * SBP_ESTATE before sbp_finalize or on a second sbp_lts_start. */
+sbp_status sbp_lts_start(sbp_ctx *ctx, const int *refined, int nrefined, int substeps, double dt_coarse,
+                         long energy_every);
+sbp_status sbp_lts_step(sbp_ctx *ctx, long nsteps);
+/* The extent of the correction of local time stepping: out[0] tiles of the
+ * correction's operator steps of all out[1] tiles of a step, out[2] nodes in
+ * the near boxes (the refined blocks whole, and the nodes of other blocks
+ * within three of their cells of a refined block) of all out[3] nodes of the
+ * node boxes.  SBP_ESTATE before sbp_lts_start. */
+sbp_status sbp_lts_info(const sbp_ctx *ctx, long out[4]);
+
 /* Node counts (Sx, Sy, Sz) of a component of a block. */
 sbp_status sbp_field_shape(const sbp_ctx *ctx, int block, sbp_comp c, int shape[3]);
 

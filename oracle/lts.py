@@ -112,9 +112,15 @@ def start(lts, e0, h_half, dt):
     return e0 - dt * lts.inv_eps * (sysm.K_eh @ h_half)
 
 
-def run(problem, fine, p, steps, dt, init=None, band=0):
+def run(problem, fine, p, steps, dt, init=None, band=0, dtype=np.float64):
     """E^0 .. E^steps of the scheme from init (E^0, H^{-1/2}); returns the
-    E vectors at every step and W^{n+1/2} for n = 0 .. steps-1."""
+    E vectors at every step and W^{n+1/2} for n = 0 .. steps-1.
+
+    dtype=np.float32 runs the same recursion with the operators, vectors and
+    arithmetic in float32 (the energy still in fp64).  It is not a
+    reference: its distance from the fp64 run measures the rounding the
+    scheme itself incurs in that precision, which sizes the tolerance of an
+    fp32 implementation."""
     lts = Lts(problem, fine, p, band)
     sysm = lts.sys
     if init is None:
@@ -122,12 +128,31 @@ def run(problem, fine, p, steps, dt, init=None, band=0):
         h = np.zeros(sysm.nh)
     else:
         e, h = sysm.join(init)
-    e_prev = start(lts, e, h, dt)
+    if dtype is np.float64:
+        e_prev = start(lts, e, h, dt)
+        step = lts.step
+    else:
+        A = sysm.K_eh.multiply(lts.inv_eps[:, None]).tocsr().astype(dtype)
+        B = sysm.K_he.multiply(lts.inv_mu[:, None]).tocsr().astype(dtype)
+        P = lts.P.astype(dtype)
+        e, h = e.astype(dtype), h.astype(dtype)
+        e_prev = (e - dtype(dt) * (A @ h)).astype(dtype)
+        tau2 = dtype(dt / lts.p) ** 2
+
+        def L(v):
+            return -(A @ (B @ v))
+
+        def step(ep, en, _dt):
+            w = L((1 - P) * en)
+            q_prev, q = en, en - dtype(0.5) * tau2 * (w + L(P * en))
+            for _ in range(1, lts.p):
+                q, q_prev = dtype(2) * q - q_prev - tau2 * (w + L(P * q)), q
+            return -ep + dtype(2) * q
     hist = [e.copy()]
     energy = np.zeros(steps)
     for n in range(steps):
-        e_new = lts.step(e_prev, e, dt)
-        energy[n] = lts.energy(e_new, e, dt)
+        e_new = step(e_prev, e, dt)
+        energy[n] = lts.energy(e_new.astype(np.float64), e.astype(np.float64), dt)
         e_prev, e = e, e_new
         hist.append(e.copy())
     return {"e": hist, "energy": energy, "lts": lts}

@@ -47,6 +47,9 @@ SIGNATURES = {
     "sbp_set_materials": [_P, _I, _P, _P, _P],
     "sbp_step": [_P, _L],
     "sbp_step_static": [_P, _L],
+    "sbp_lts_start": [_P, _IP, _I, _I, ctypes.c_double, _L],
+    "sbp_lts_step": [_P, _L],
+    "sbp_lts_info": [_P, ctypes.POINTER(ctypes.c_long)],
     "sbp_steps_done": [_P, ctypes.POINTER(_L)],
     "sbp_field_shape": [_P, _I, _I, _IP],
     "sbp_read_field": [_P, _I, _I, _P, _S],
@@ -223,6 +226,24 @@ class Context:
 
     def step_static(self, nsteps):
         self._chk(self._lib.sbp_step_static(self.h, int(nsteps)))
+
+    def lts_start(self, refined, substeps, dt_coarse, energy_every=1):
+        """Local time stepping of the blocks in ``refined`` with ``substeps``
+        substeps per coarse step ``dt_coarse``; W^{n+1/2} every
+        ``energy_every`` coarse steps (0: none); see sbp_lts_start."""
+        r = (ctypes.c_int * max(len(refined), 1))(*[int(b) for b in refined])
+        self._chk(self._lib.sbp_lts_start(self.h, r, len(refined), int(substeps), float(dt_coarse),
+                                          int(energy_every)))
+
+    def lts_step(self, nsteps):
+        self._chk(self._lib.sbp_lts_step(self.h, int(nsteps)))
+
+    def lts_info(self):
+        """{near_tiles, tiles, near_nodes, nodes}: the extent of the local
+        time stepping's correction; see sbp_lts_info."""
+        out = (ctypes.c_long * 4)()
+        self._chk(self._lib.sbp_lts_info(self.h, out))
+        return dict(zip(("near_tiles", "tiles", "near_nodes", "nodes"), [int(v) for v in out]))
 
     def steps_done(self):
         n = ctypes.c_long()

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbpfdtd.so")
-SOURCES = ["api.hip", "step.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "step.hip", "adjoint.hip", "lts.hip"]
 ARCH = os.environ.get("SBP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -47,58 +47,6 @@ __device__ double cell_mean(const T* comp, const DevBlock& B, int c, int ci, int
                  ((double)comp[o + st[a2]] + (double)comp[o + st[a1] + st[a2]]));
 }
 
-// Sum S of eps_r over the four clamped cells around E node (i, j, k) of
-// component c (Ex: {ci0} x {cj0, cj1} x {ck0, ck1}; Ey: {ci0, ci1} x {cj0} x
-// {ck0, ck1}; Ez: {ci0, ci1} x {cj0, cj1} x {ck0}, ci0 = clamp(i-1),
-// ci1 = clamp(i), ...), and the four cells (repeated where clamped).
-struct NodeCells {
-  double S;
-  int cell[4];  // block-local cell indices ci + nx (cj + ny ck)
-};
-
-template <typename T>
-__device__ __forceinline__ const T* cells_of_block(const void* mat_eps, const DevBlock& B) {
-  return mat_eps ? (const T*)mat_eps + B.coff : nullptr;
-}
-
-// Norm weight w_E of E node (i, j, k) of component c: the product of the 1D
-// weights (Appendix P+, P-) with h.  The full geometric weight (not w / h^3)
-// keeps the adjoint variables of blocks of different mesh sizes consistent.
-__device__ __forceinline__ double e_weight(const DevBlock& B, int c, int i, int j, int k) {
-  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-  const double wx = c == 0 ? wm1(nx, i) : wp1(nx, i);
-  const double wy = c == 1 ? wm1(ny, j) : wp1(ny, j);
-  const double wz = c == 2 ? wm1(nz, k) : wp1(nz, k);
-  return (wx * B.h[0]) * (wy * B.h[1]) * (wz * B.h[2]);
-}
-
-// dte0x4 / S: the E-update coefficient Cb of a lossless node (double).
-__device__ __forceinline__ double node_cb(const DevBlock& B, double S) { return B.dte0x4 / S; }
-
-template <typename T>
-__device__ NodeCells node_cells_t(const DevBlock& B, const void* mat_eps, int c, int i, int j, int k) {
-  const T* cv = cells_of_block<T>(mat_eps, B);
-  const bool has_eps = (B.mat & MAT_EPS) && cv;
-  const int nx = B.n[0], ny = B.n[1], nz = B.n[2];
-  NodeCells r;
-  const int ci0 = clampi(i - 1, 0, nx - 1), ci1 = clampi(i, 0, nx - 1);
-  const int cj0 = clampi(j - 1, 0, ny - 1), cj1 = clampi(j, 0, ny - 1);
-  const int ck0 = clampi(k - 1, 0, nz - 1), ck1 = clampi(k, 0, nz - 1);
-  int q = 0;
-  r.S = 0.0;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      int ci, cj, ck;
-      if (c == 0) { ci = ci0; cj = a ? cj1 : cj0; ck = b ? ck1 : ck0; }
-      else if (c == 1) { ci = a ? ci1 : ci0; cj = cj0; ck = b ? ck1 : ck0; }
-      else { ci = a ? ci1 : ci0; cj = b ? cj1 : cj0; ck = ck0; }
-      const int cell = ci + nx * (cj + ny * ck);
-      r.cell[q++] = cell;
-      r.S += has_eps ? (double)cv[cell] : B.eps_r0;
-    }
-  return r;
-}
-
 }  // namespace
 
 // J += dt sum_{cells in region} |Ebar|^2 of the state in `pool` (one workgroup).

@@ -25,6 +25,17 @@ namespace sbp {
 template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
 hipError_t launch_finish(const KArgs&, int, int, hipStream_t);
+template <typename T>
+hipError_t lts_prep(void*, const void*, const void*, int, const Tile*, int, const DevBlock*, const LtsBox*, int, int,
+                    hipStream_t);
+template <typename T>
+hipError_t lts_box(int, int, void*, const void*, void*, const void*, const void*, void*, void*, double,
+                   const DevBlock*, const LtsBox*, hipStream_t);
+template <typename T>
+hipError_t lts_whole(int, int, const void*, void*, const void*, const void*, double, const DevBlock*, const void*,
+                     double, double*, hipStream_t);
+hipError_t lts_store(const double*, int, double*, hipStream_t);
+constexpr int kLtsGrid = 64;
 template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
 hipError_t launch_sources(const KArgs&, hipStream_t);
 template <typename T>
@@ -117,6 +128,33 @@ struct sbp_ctx {
   int kind_t0[32] = {}, kind_t1[32] = {};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
   int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
+  // local time stepping (sbp_lts_start / sbp_lts_step): the scratch state on
+  // which L is applied (with its own face buffers, step counter and one-slot
+  // energy ring), w = L (I - P) E^n, two substep vectors, E^{n-1} (the last
+  // three on the near boxes only), two E copies for the energy, per-block
+  // unit-time-step and coarse-time-step descriptors and near boxes, the
+  // tiles that meet the wider boxes (ranges per kind; rebuilt when the tile
+  // list changes) and energy partials
+  bool lts = false;
+  int lts_p = 1;
+  double lts_dt = 0.0;
+  long lts_every = 0;
+  void *lts_s = nullptr, *lts_w = nullptr, *lts_qa = nullptr, *lts_qb = nullptr, *lts_ep = nullptr;
+  void* lts_x[2] = {nullptr, nullptr};
+  double* lts_face = nullptr;
+  StepState* lts_st = nullptr;
+  double* lts_ring = nullptr;
+  double* lts_part = nullptr;
+  DevBlock* lts_blocks = nullptr;   // unit time step (L u)
+  DevBlock* lts_cblocks = nullptr;  // the coarse time step (the ordinary step)
+  LtsBox* lts_boxes = nullptr;
+  std::vector<LtsBox> lts_hbox;  // near boxes (the recursion's nodes)
+  std::vector<LtsBox> lts_tbox;  // wider boxes (the operator's tiles)
+  Tile* d_near = nullptr;
+  size_t near_cap = 0;
+  int nnear = 0;
+  int nk_t0[32] = {}, nk_t1[32] = {};
+  bool near_dirty = true;
   FTile* d_ftiles = nullptr;
   FTile* d_ftiles_bare = nullptr;
   size_t ftiles_cap = 0;
@@ -583,6 +621,7 @@ bool tf_tile(const sbp_ctx* c, long long sx, long long q0, int threads, int z0, 
 
 sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
+  c->near_dirty = true;
   const int threads = c->tx * c->ty;
   for (int kind = 0; kind < 32; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
@@ -753,8 +792,12 @@ void* pool_other(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool : c->
 // One leapfrog step of the state that `a` points at (pool, face buffers,
 // energy / probe rings, step counter): the forward state (kargs(c)) or the
 // adjoint state of sbp_adjoint.
-sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
+sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const int* kt0 = nullptr, const int* kt1 = nullptr) {
   const int threads = c->tx * c->ty;
+  if (!kt0) {
+    kt0 = c->kind_t0;
+    kt1 = c->kind_t1;
+  }
   const bool f64 = c->prec == SBP_FP64;
   hipError_t e;
   double* face = const_cast<double*>(a.face);
@@ -763,7 +806,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
     return SBP_OK;
   };
   // kinds stepped by the two-pass kernels: all, or only the general ones
-  auto two_pass = [&](int kind) { return c->kind_t1[kind] > c->kind_t0[kind] && (!c->fused || (kind & 2)); };
+  auto two_pass = [&](int kind) { return kt1[kind] > kt0[kind] && (!c->fused || (kind & 2)); };
   if (c->njobs_e) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream)
             : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream);
@@ -779,8 +822,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   a.hpoff = -1;
   for (int kind = 0; kind < 32; ++kind) {
     if (!two_pass(kind)) continue;
-    a.t0 = c->kind_t0[kind];
-    a.t1 = c->kind_t1[kind];
+    a.t0 = kt0[kind];
+    a.t1 = kt1[kind];
     a.poff = hpoff[kind] = nparts;
     const int grid = grid_of(c, a.t1 - a.t0);
     nparts += grid;
@@ -797,8 +840,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events) {
   if ((st = mark()) != SBP_OK) return st;
   for (int kind = 0; kind < 32; ++kind) {
     if (!two_pass(kind)) continue;
-    a.t0 = c->kind_t0[kind];
-    a.t1 = c->kind_t1[kind];
+    a.t0 = kt0[kind];
+    a.t1 = kt1[kind];
     a.poff = nparts;
     a.hpoff = hpoff[kind];
     const int grid = grid_of(c, a.t1 - a.t0);
@@ -843,6 +886,118 @@ void insert(std::vector<T>& box, const DevBlock& d, const int s[3], const double
   for (int k = 0; k < s[2]; ++k)
     for (int j = 0; j < s[1]; ++j)
       for (int i = 0; i < s[0]; ++i) box[(size_t)i + d.sx * j + d.sxy * k] = (T)src[q++];
+}
+
+// L u of local time stepping: one step with unit time step of the scratch
+// state (E = u, H = 0, prepared in lts_s) with its own face buffers, step
+// counter and energy ring, on the tiles that meet the near boxes (all tiles:
+// `whole`), without source / probe flags: the E part afterwards holds
+// u - L u there.
+sbp_status lts_apply(sbp_ctx* c, bool whole) {
+  KArgs a = kargs(c);
+  a.blocks = c->lts_blocks;
+  a.pool = a.pool2 = c->lts_s;
+  a.face = c->lts_face;
+  a.st = c->lts_st;
+  a.energy = a.probes = c->lts_ring;
+  a.ecap = a.pcap = 1;
+  a.tiles = whole ? c->d_tiles_bare : c->d_near;
+  a.ftiles = c->d_ftiles_bare;
+  a.nsrc = 0;
+  a.dt = 1.0;
+  a.tf = nullptr;
+  return whole ? enqueue_step_on(c, a, false) : enqueue_step_on(c, a, false, c->nk_t0, c->nk_t1);
+}
+
+// Boxes of local time stepping: a refined block whole; in another block the
+// nodes within `reach` of its own cells of a refined block's box (the
+// bounding box over the refined blocks).  The near boxes (reach 2) hold
+// every E node where the scheme's E^{n+1} differs from the ordinary step's
+// (those within one cell); the operator's tiles meet the wider boxes
+// (reach 4), so that the H and E values the near boxes read (one cell
+// farther each) are formed from nonzero input.
+constexpr int kLtsNear = 2, kLtsWide = 4;
+std::vector<LtsBox> lts_boxes(const sbp_ctx* c, const std::vector<int>& refined, int reach) {
+  const int nb = (int)c->blocks.size();
+  std::vector<LtsBox> out(nb, LtsBox{{0, 0, 0}, {-1, -1, -1}, 0, 0});
+  for (int y = 0; y < nb; ++y) {
+    const HostBlock& Y = c->blocks[y];
+    LtsBox& bx = out[y];
+    if (refined[y]) {
+      for (int a = 0; a < 3; ++a) {
+        bx.lo[a] = 0;
+        bx.hi[a] = Y.n[a] + 1;
+      }
+      bx.on = bx.refined = 1;
+      continue;
+    }
+    for (int f = 0; f < nb; ++f) {
+      if (!refined[f]) continue;
+      const HostBlock& F = c->blocks[f];
+      int lo[3], hi[3];
+      bool hit = true;
+      for (int a = 0; a < 3 && hit; ++a) {
+        const double h = Y.h[a], tol = 1e-9 * h;
+        const double flo = F.x0[a] - reach * h, fhi = F.x0[a] + F.n[a] * F.h[a] + reach * h;
+        const double ylo = Y.x0[a], yhi = Y.x0[a] + Y.n[a] * h;
+        const double l = std::max(flo, ylo), u = std::min(fhi, yhi);
+        if (l > u + tol) {
+          hit = false;
+          break;
+        }
+        // cells [cl, cu] of Y meet the interval; their nodes, with one more
+        // on each side for the "-" grid's half-cell offsets
+        const int cl = (int)std::floor((l - ylo) / h + 1e-9), cu = (int)std::ceil((u - ylo) / h - 1e-9);
+        lo[a] = std::max(0, cl - 1);
+        hi[a] = std::min(Y.n[a] + 1, cu + 1);
+      }
+      if (!hit) continue;
+      for (int a = 0; a < 3; ++a) {
+        bx.lo[a] = bx.on ? std::min(bx.lo[a], lo[a]) : lo[a];
+        bx.hi[a] = bx.on ? std::max(bx.hi[a], hi[a]) : hi[a];
+      }
+      bx.on = 1;
+    }
+  }
+  return out;
+}
+
+// The tiles (of the flag-free list) that meet a wider box, ranges per kind.
+sbp_status lts_near_tiles(sbp_ctx* c) {
+  const int threads = c->tx * c->ty;
+  std::vector<Tile> nt;
+  for (int kind = 0; kind < 32; ++kind) {
+    c->nk_t0[kind] = (int)nt.size();
+    for (int t = c->kind_t0[kind]; t < c->kind_t1[kind]; ++t) {
+      const Tile& tl = c->bare[t];
+      const LtsBox& bx = c->lts_tbox[tl.block];
+      if (!bx.on) continue;
+      const HostBlock& b = c->blocks[tl.block];
+      const long long sx = b.n[0] + 2, plane = sx * (b.n[1] + 2);
+      bool hit = false;
+      for (int k = tl.z0; k < tl.z0 + c->cz && !hit; ++k) {
+        if (k < bx.lo[2] || k > bx.hi[2]) continue;
+        for (long long q = tl.q0; q < std::min<long long>(tl.q0 + threads, plane) && !hit; ++q) {
+          const int j = (int)(q / sx), i = (int)(q - j * sx);
+          hit = i >= bx.lo[0] && i <= bx.hi[0] && j >= bx.lo[1] && j <= bx.hi[1];
+        }
+      }
+      if (hit) nt.push_back(tl);
+    }
+    c->nk_t1[kind] = (int)nt.size();
+  }
+  if (nt.size() > c->near_cap) {
+    dfree(c, c->d_near);
+    c->d_near = (Tile*)dalloc(c, nt.size() * sizeof(Tile));
+    if (!c->d_near) return fail(c, SBP_ENOMEM, "tile list allocation failed");
+    c->near_cap = nt.size();
+  }
+  c->nnear = (int)nt.size();
+  if (!nt.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_near, nt.data(), nt.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // nt is a local
+  c->near_dirty = false;
+  return SBP_OK;
 }
 
 // ------------------------------------------------ allocation-free stepping
@@ -1469,6 +1624,7 @@ sbp_status sbp_set_cpml(sbp_ctx* c, int cells, int order, double sigma_factor, d
 
 sbp_status sbp_set_fused(sbp_ctx* c, int enable, int planes) {
   if (!c) return SBP_EINVAL;
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (planes < 4 || planes > 4096) return fail(c, SBP_EINVAL, "planes per one-pass tile must be 4..4096");
   c->fz = planes;
   drop_graph(c);
@@ -1501,6 +1657,7 @@ sbp_status sbp_get_launch(const sbp_ctx* c, int out[4]) {
 sbp_status sbp_step(sbp_ctx* c, long nsteps) {
   if (!c) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "step before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
   if (nsteps == 0) return SBP_OK;
   HIPCHK(c, hipSetDevice(c->device));
@@ -1546,6 +1703,7 @@ sbp_status sbp_step(sbp_ctx* c, long nsteps) {
 sbp_status sbp_step_static(sbp_ctx* c, long nsteps) {
   if (!c) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "step before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
   if (!c->scratch) return fail(c, SBP_EHIP, "no static scratch on this device");
   if (c->partials_need > kStaticPartials)
@@ -1575,6 +1733,220 @@ sbp_status sbp_step_static(sbp_ctx* c, long nsteps) {
   }
   c->timed = false;
   c->nstep += nsteps;
+  return SBP_OK;
+}
+
+sbp_status sbp_lts_start(sbp_ctx* c, const int* refined, int nrefined, int substeps, double dt_coarse,
+                          long energy_every) {
+  if (!c) return SBP_EINVAL;
+  if (!c->finalized) return fail(c, SBP_ESTATE, "local time stepping before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "local time stepping already started");
+  if (substeps < 1 || substeps > 64) return fail(c, SBP_EINVAL, "substeps must be 1..64");
+  if (!(dt_coarse > 0.0) || !std::isfinite(dt_coarse)) return fail(c, SBP_EINVAL, "dt_coarse must be positive");
+  if (energy_every < 0) return fail(c, SBP_EINVAL, "energy_every must be >= 0");
+  if (nrefined < 0 || (nrefined > 0 && !refined)) return fail(c, SBP_EINVAL, "bad refined-block list");
+  if (c->fused) return fail(c, SBP_EINVAL, "local time stepping takes the two-pass step (sbp_set_fused 0)");
+  if (!c->srcs.empty() || c->tf_on) return fail(c, SBP_EINVAL, "local time stepping takes no sources or TF/SF box");
+  const int nb = (int)c->blocks.size();
+  std::vector<int> flag(nb, 0);
+  for (int q = 0; q < nrefined; ++q) {
+    if (!check_block(c, refined[q])) return fail(c, SBP_EINVAL, "bad refined block");
+    flag[refined[q]] = 1;
+  }
+  for (const HostBlock& b : c->blocks) {
+    bool lossy = false;
+    for (double v : b.sig) lossy = lossy || v != 0.0;
+    for (int f = 0; f < 6; ++f) {
+      lossy = lossy || (b.iface[f] < 0 && (b.faces[f] == SBP_ABC1 || b.faces[f] == SBP_CPML));
+      if (b.iface[f] >= 0 && c->ifaces[b.iface[f]].a == c->ifaces[b.iface[f]].b)
+        return fail(c, SBP_EINVAL, "local time stepping takes no periodic faces");
+    }
+    if (lossy) return fail(c, SBP_EINVAL, "local time stepping covers lossless blocks (no conductivity, no absorbing faces)");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  drop_graph(c);
+  const size_t pb = c->pool_elems * elem_size(c);
+  const bool sub = substeps > 1 && nrefined > 0;  // the recursion differs from the leapfrog
+  const bool track = energy_every > 0;
+  auto take = [&](size_t bytes) { return dalloc(c, bytes); };
+  c->lts_s = take(pb);
+  if (sub) {
+    c->lts_w = take(pb);
+    c->lts_qa = take(pb);
+    c->lts_qb = take(pb);
+    c->lts_ep = take(pb);
+  }
+  if (track) {
+    c->lts_x[0] = take(pb);
+    c->lts_x[1] = take(pb);
+  }
+  c->lts_face = (double*)take(c->face_elems * sizeof(double));
+  c->lts_st = (StepState*)take(sizeof(StepState));
+  c->lts_ring = (double*)take(2 * sizeof(double));
+  c->lts_part = (double*)take((size_t)kLtsGrid * nb * sizeof(double));
+  c->lts_blocks = (DevBlock*)take((size_t)nb * sizeof(DevBlock));
+  c->lts_cblocks = (DevBlock*)take((size_t)nb * sizeof(DevBlock));
+  c->lts_boxes = (LtsBox*)take((size_t)nb * sizeof(LtsBox));
+  if (!c->lts_s || (sub && (!c->lts_w || !c->lts_qa || !c->lts_qb || !c->lts_ep)) ||
+      (track && (!c->lts_x[0] || !c->lts_x[1])) || !c->lts_face || !c->lts_st || !c->lts_ring || !c->lts_part ||
+      !c->lts_blocks || !c->lts_cblocks || !c->lts_boxes)
+    return fail(c, SBP_ENOMEM, "local time stepping buffer allocation failed");
+  // descriptors with a unit time step (one step of the scratch state applies
+  // B and then A: Section V's update with dt = 1) and with the coarse one
+  std::vector<DevBlock> ub(c->hblocks), cb(c->hblocks);
+  auto with_dt = [](DevBlock& d, double dt) {
+    d.db_u = dt / (kMu0 * d.mu_r0);
+    d.cb_u = dt / (kEps0 * d.eps_r0);
+    d.dte0x4 = 4.0 * dt / kEps0;
+    d.hdte0 = dt / (2.0 * kEps0);
+    d.dtm0x2 = 2.0 * dt / kMu0;
+  };
+  for (size_t q = 0; q < ub.size(); ++q) {
+    with_dt(ub[q], 1.0);
+    with_dt(cb[q], dt_coarse);
+  }
+  c->lts_hbox = lts_boxes(c, flag, kLtsNear);
+  c->lts_tbox = lts_boxes(c, flag, kLtsWide);
+  if (!sub)
+    for (LtsBox& x : c->lts_hbox) x.on = 0;
+  HIPCHK(c, hipMemcpyAsync(c->lts_blocks, ub.data(), ub.size() * sizeof(DevBlock), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->lts_cblocks, cb.data(), cb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->lts_boxes, c->lts_hbox.data(), nb * sizeof(LtsBox), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lts_face, 0, c->face_elems * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lts_st, 0, sizeof(StepState), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lts_ring, 0, 2 * sizeof(double), c->stream));
+  for (void* p : {c->lts_s, c->lts_w, c->lts_qa, c->lts_qb, c->lts_ep, c->lts_x[0], c->lts_x[1]})
+    if (p) HIPCHK(c, hipMemsetAsync(p, 0, pb, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->lts_p = sub ? substeps : 1;
+  c->lts_dt = dt_coarse;
+  c->lts_every = energy_every;
+  c->lts = true;
+  if (!sub) {
+    for (LtsBox& x : c->lts_tbox) x.on = 0;
+  }
+  sbp_status st = lts_near_tiles(c);
+  if (st != SBP_OK) return st;
+  if (sub || track) {
+    // E^{-1} = E^0 - dt A H^{-1/2} (on the near boxes; everywhere for the
+    // energy): the scratch state (E = 0, H = H^{-1/2}) after one unit step
+    // on all tiles holds A H^{-1/2}; the scratch state is cleared again
+    // afterwards (it is zero away from the operator's tiles from here on)
+    const bool f64 = c->prec == SBP_FP64;
+    void* M = pool_at(c, c->nstep);
+    const int threads = c->tx * c->ty;
+    HIPCHK(c, f64 ? lts_prep<double>(c->lts_s, M, nullptr, 2, c->d_tiles_bare, c->ntiles, c->lts_blocks,
+                                     c->lts_boxes, threads, c->cz, c->stream)
+                  : lts_prep<float>(c->lts_s, M, nullptr, 2, c->d_tiles_bare, c->ntiles, c->lts_blocks, c->lts_boxes,
+                                    threads, c->cz, c->stream));
+    st = lts_apply(c, true);
+    if (st != SBP_OK) return st;
+    if (sub)
+      HIPCHK(c, f64 ? lts_box<double>(5, nb, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, dt_coarse,
+                                      c->d_blocks, c->lts_boxes, c->stream)
+                    : lts_box<float>(5, nb, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, dt_coarse,
+                                     c->d_blocks, c->lts_boxes, c->stream));
+    if (track)
+      HIPCHK(c, f64 ? lts_whole<double>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
+                                        0.0, nullptr, c->stream)
+                    : lts_whole<float>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
+                                       0.0, nullptr, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->lts_s, 0, pb, c->stream));
+  }
+  return SBP_OK;
+}
+
+sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
+  if (!c) return SBP_EINVAL;
+  if (!c->lts) return fail(c, SBP_ESTATE, "sbp_lts_step before sbp_lts_start");
+  if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->near_dirty) {
+    const sbp_status st = lts_near_tiles(c);
+    if (st != SBP_OK) return st;
+  }
+  const bool f64 = c->prec == SBP_FP64;
+  const int nb = (int)c->blocks.size(), p = c->lts_p, threads = c->tx * c->ty;
+  const double dt = c->lts_dt, tau = dt / p, tau2 = tau * tau;
+  const long K = c->lts_every;
+  const KArgs ka = kargs(c);
+  auto prep = [&](int mode, const void* M, const void* Q) {
+    return f64 ? lts_prep<double>(c->lts_s, M, Q, mode, c->d_near, c->nnear, c->lts_blocks, c->lts_boxes, threads,
+                                  c->cz, c->stream)
+               : lts_prep<float>(c->lts_s, M, Q, mode, c->d_near, c->nnear, c->lts_blocks, c->lts_boxes, threads,
+                                 c->cz, c->stream);
+  };
+  auto box = [&](int op, void* M, const void* Qm, const void* Qp, void* Qo) {
+    return f64 ? lts_box<double>(op, nb, M, c->lts_s, c->lts_w, Qm, Qp, Qo, c->lts_ep, tau2, c->d_blocks,
+                                 c->lts_boxes, c->stream)
+               : lts_box<float>(op, nb, M, c->lts_s, c->lts_w, Qm, Qp, Qo, c->lts_ep, tau2, c->d_blocks,
+                                c->lts_boxes, c->stream);
+  };
+  auto whole = [&](int op, const void* M, void* X, const void* Y, double d) {
+    return f64 ? lts_whole<double>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
+                                   c->stream)
+               : lts_whole<float>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
+                                  c->stream);
+  };
+  for (long s = 0; s < nsteps; ++s) {
+    const long long n = c->nstep;
+    void* M = pool_at(c, n);  // E^n, H^{n-1/2} (the two-pass step keeps one pool)
+    sbp_status st;
+    if (p > 1) {
+      // w = L (I - P) E^n
+      HIPCHK(c, prep(0, M, nullptr));
+      if ((st = lts_apply(c, false)) != SBP_OK) return st;
+      HIPCHK(c, box(0, M, nullptr, nullptr, nullptr));
+      // q_1 from q_0 = E^n; then q_{m+1} from q_m, q_{m-1} (q_m in lts_qa for
+      // odd m, lts_qb for even m > 0)
+      HIPCHK(c, prep(1, M, M));
+      if ((st = lts_apply(c, false)) != SBP_OK) return st;
+      HIPCHK(c, box(1, M, nullptr, nullptr, c->lts_qa));
+      for (int m = 1; m < p; ++m) {
+        void* qm = (m & 1) ? c->lts_qa : c->lts_qb;
+        const void* qp = m == 1 ? M : ((m & 1) ? c->lts_qb : c->lts_qa);
+        void* qo = (m & 1) ? c->lts_qb : c->lts_qa;
+        HIPCHK(c, prep(1, M, qm));
+        if ((st = lts_apply(c, false)) != SBP_OK) return st;
+        HIPCHK(c, box(2, M, qm, qp, qo));
+      }
+      // E^{n+1} = -E^{n-1} + 2 q_p on the near boxes (held in w); E^{n-1} <- E^n
+      HIPCHK(c, box(3, M, (p & 1) ? c->lts_qa : c->lts_qb, nullptr, nullptr));
+    }
+    // copies of E^n for the energy of this step or the next
+    const bool form = K > 0 && n % K == 0;
+    if (K > 0 && (form || (n + 1) % K == 0)) HIPCHK(c, whole(0, M, c->lts_x[n & 1], nullptr, 0.0));
+    // the ordinary step of length dt: H^{n+1/2}, E^n + dt A H^{n+1/2}
+    KArgs a = ka;
+    a.blocks = c->lts_cblocks;
+    a.dt = dt;
+    if ((st = enqueue_step_on(c, a, false)) != SBP_OK) return st;
+    // the scheme's E^{n+1} on the near boxes
+    if (p > 1) HIPCHK(c, box(4, M, nullptr, nullptr, nullptr));
+    double* slot = ka.energy + (int)(n % ka.ecap);
+    if (form) {
+      HIPCHK(c, whole(2, M, c->lts_x[(n + 1) & 1], c->lts_x[n & 1], 0.5 / (dt * dt)));
+      HIPCHK(c, lts_store(c->lts_part, kLtsGrid * nb, slot, c->stream));
+    } else {
+      HIPCHK(c, lts_store(c->lts_part, 0, slot, c->stream));
+    }
+    c->nstep += 1;
+  }
+  return SBP_OK;
+}
+
+sbp_status sbp_lts_info(const sbp_ctx* c, long out[4]) {
+  if (!c || !out) return SBP_EINVAL;
+  if (!c->lts) return SBP_ESTATE;
+  out[0] = c->nnear;
+  out[1] = c->ntiles;
+  out[2] = out[3] = 0;
+  for (size_t b = 0; b < c->blocks.size(); ++b) {
+    const HostBlock& hb = c->blocks[b];
+    const LtsBox& x = c->lts_hbox[b];
+    if (x.on) out[2] += (long)(x.hi[0] - x.lo[0] + 1) * (x.hi[1] - x.lo[1] + 1) * (x.hi[2] - x.lo[2] + 1);
+    out[3] += (long)(hb.n[0] + 2) * (hb.n[1] + 2) * (hb.n[2] + 2);
+  }
   return SBP_OK;
 }
 
@@ -1677,6 +2049,7 @@ sbp_status sbp_state_bytes(const sbp_ctx* c, size_t* bytes) {
 }
 
 sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
+  if (c && c->lts) return fail(c, SBP_ESTATE, "the saved state does not hold local time stepping's E^{n-1}");
   if (!c || !dev_buf) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "save_state before finalize");
   size_t need;
@@ -1697,6 +2070,7 @@ sbp_status sbp_save_state(sbp_ctx* c, void* dev_buf, size_t bytes) {
 }
 
 sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
+  if (c && c->lts) return fail(c, SBP_ESTATE, "the saved state does not hold local time stepping's E^{n-1}");
   if (!c || !dev_buf) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "load_state before finalize");
   size_t need;
@@ -1767,6 +2141,7 @@ sbp_status sbp_kernel_ms(sbp_ctx* c, double out[3]) {
 sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
   if (!c) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "autotune before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (steps_per_trial < 1) steps_per_trial = 5;
   size_t bytes;
   sbp_state_bytes(c, &bytes);
@@ -1825,6 +2200,7 @@ sbp_status sbp_adjoint(sbp_ctx* c, int block, long nsteps, const int region[6], 
                        double* grad_eps_dev) {
   if (!c || !region || !J_out) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "adjoint before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
   if (nsteps < 1) return fail(c, SBP_EINVAL, "nsteps must be >= 1");
   const HostBlock& hb = c->blocks[block];

@@ -261,5 +261,21 @@ def bloch_box(n=192, frac=0.05, theta=0.6, phi=0.3, scale=1):
             "probes": [_ez_cell(0, (n // 4, n // 2, n // 2))], "wave_vector": kv}
 
 
+def lossless_subgrid(scale=1):
+    """The 1:2 subgrid geometry of config3 with its absorbing faces made PEC,
+    no conductivity and no source or probe: the case local time stepping
+    covers.  Returns (problem, index of the refined block)."""
+    prob = config3(scale)
+    blocks = []
+    for b in prob["blocks"]:
+        b = dict(b)
+        b["faces"] = ["pec" if f == "abc" else f for f in b["faces"]]
+        b["sigma"] = None
+        blocks.append(b)
+    return ({"name": prob["name"] + "-lossless", "prec": prob["prec"], "cfl": prob["cfl"], "steps": prob["steps"],
+             "blocks": blocks, "interfaces": prob["interfaces"], "sources": [], "probes": []},
+            prob["fine_block"])
+
+
 def make_config(k, scale=1):
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k](scale)

@@ -1,0 +1,228 @@
+"""GPU local time stepping (sbp_lts_start / sbp_lts_step) against the
+oracle's scheme (``oracle.lts``, pinned in test_oracle_lts.py).
+
+- A coarse block with a 1:2 refined block on its face along each axis, with
+  per-cell permittivity, at 1.5x the global step (beyond the refined block's
+  own limit), two substeps: E of both blocks after the run and W^{n+1/2} of
+  every coarse step against the oracle, to the parity bar; W^{n+1/2} stays
+  constant.
+- The 27-block 1:2 subgrid geometry made lossless (reduced), three
+  substeps, the energy formed every fifth step (NaN between).
+- One substep is the leapfrog: bitwise the E of sbp_step at the same step.
+- The near boxes cut the work: the corrected tiles are a fraction of all.
+- Errors: the cases the scheme does not cover, and the state rules.
+
+The H arrays of a context under local time stepping hold an auxiliary
+field (the ordinary step's H), which the E-only scheme has no counterpart
+for, so only E and the energy are compared.
+
+fp32 bar: the parity bar (1e-5), or twice the rounding the scheme itself
+incurs in fp32 where that is larger: the distance of the oracle's recursion
+run in float32 from its fp64 run on the same case.  Beyond the refined
+block's own limit the E-only recursion amplifies fp32 rounding (its
+three-level update differences nearly equal terms for the fastest modes),
+so random fields over 40 coarse steps reach about 1.1e-5 in the oracle's
+own float32 run.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import COMPS, TOL, check_fields, rel_l2, write_fields
+from oracle import lts as T
+from oracle import system as S
+
+pytestmark = pytest.mark.gpu
+
+E_COMPS = ("Ex", "Ey", "Ez")
+
+
+@pytest.fixture(scope="module")
+def sbp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_00638_amd as p
+    p.lib()
+    return p
+
+
+def _pair(axis, seed):
+    """A 2 mm coarse block (10, 7, 6) cells with a 1 mm block of 8 cells
+    across and twice the tangential cells on its + face along `axis`;
+    seeded permittivity in [1, 3] on the coarse cells; PEC / PMC faces."""
+    rng = np.random.default_rng(seed)
+    nA = [10, 7, 6]
+    nB = [2 * v for v in nA]
+    nB[axis] = 8
+    oB = [0.0, 0.0, 0.0]
+    oB[axis] = nA[axis] * 2e-3
+    fa = ["pec", "pmc", "pec", "pec", "pmc", "pec"]
+    fb = ["pmc", "pec", "pec", "pmc", "pec", "pec"]
+    fa[2 * axis + 1] = "iface"
+    fb[2 * axis] = "iface"
+    A = {"n": tuple(nA), "h": (2e-3,) * 3, "origin": (0.0, 0.0, 0.0),
+         "eps_r": rng.uniform(1.0, 3.0, size=(nA[2], nA[1], nA[0])), "mu_r": None, "sigma": None, "faces": fa}
+    B = {"n": tuple(nB), "h": (1e-3,) * 3, "origin": tuple(oB), "eps_r": None, "mu_r": None, "sigma": None,
+         "faces": fb}
+    return {"blocks": [A, B], "interfaces": [(0, 2 * axis + 1, 1, 2 * axis, 2)], "cfl": 0.9, "sources": [],
+            "probes": []}
+
+
+def _subgrid_lossless(scale):
+    from sbp_inputs import lossless_subgrid
+    return lossless_subgrid(scale)
+
+
+def _init(prob, seed):
+    rng = np.random.default_rng(seed)
+    out = {}
+    for b, blk in enumerate(prob["blocks"]):
+        for c in COMPS:
+            sx, sy, sz = S.comp_shape(c, tuple(blk["n"]))
+            v = rng.standard_normal((sz, sy, sx))
+            out[(b, c)] = v / 377.0 if c[0] == "H" else v
+    return out
+
+
+def _f32_bar(prob, fine, p, steps, dt, init, ref):
+    """max(1e-5, 2x the oracle's own float32 rounding) for fp32 fields;
+    (bar, that rounding)."""
+    r32 = T.run(prob, fine, p, steps, dt, init, dtype=np.float32)
+    own = rel_l2(r32["e"][-1].astype(np.float64), ref["e"][-1])
+    return max(TOL["f32"], 2.0 * own), own
+
+
+def _oracle_e(prob, e):
+    """E vector of the oracle as {(block, comp): array}."""
+    sysm = S.System(prob)
+    f = sysm.split(e, np.zeros(sysm.nh))
+    return {k: v for k, v in f.items() if k[1] in E_COMPS}
+
+
+def _gpu_lts(sbp, prob, prec, refined, p, dt, steps, init, every=1):
+    ctx = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    try:
+        write_fields(ctx, init)
+        ctx.lts_start(refined, p, dt, every)
+        ctx.lts_step(steps)
+        e = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"])) for c in E_COMPS}
+        w = ctx.read_energy(0, steps)
+    finally:
+        ctx.close()
+    return e, w
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_lts_pair_matches_oracle(sbp, axis, prec):
+    prob = _pair(axis, 10 + axis)
+    init = _init(prob, 20 + axis)
+    dt = 1.5 * S.cfl_dt(prob["blocks"], 0.9)  # 1.35x the refined block's own limit
+    steps = 40
+    ref = T.run(prob, [1], 2, steps, dt, init)
+    e, w = _gpu_lts(sbp, prob, prec, [1], 2, dt, steps, init)
+    tol, own = _f32_bar(prob, [1], 2, steps, dt, init, ref) if prec == "f32" else (TOL[prec], 0.0)
+    check_fields(e, _oracle_e(prob, ref["e"][-1]), prec,
+                 f"LTS 1:2 pair, axis {axis}, step {steps} (oracle's own fp32 rounding {own:.2e})", tol=tol)
+    assert rel_l2(w, ref["energy"]) < TOL[prec], (prec, rel_l2(w, ref["energy"]))
+    drift = float(np.abs(w / w[0] - 1).max())
+    assert drift < (1e-11 if prec == "f64" else 1e-5), drift
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lts_subgrid_reduced_matches_oracle(sbp, prec):
+    prob, fine = _subgrid_lossless(8)
+    init = _init(prob, 31)
+    dt = 2.0 * S.cfl_dt(prob["blocks"], 0.9)  # the coarse blocks' own step
+    steps = 24
+    ref = T.run(prob, [fine], 3, steps, dt, init)
+    e, w = _gpu_lts(sbp, prob, prec, [fine], 3, dt, steps, init, every=5)
+    tol, own = _f32_bar(prob, [fine], 3, steps, dt, init, ref) if prec == "f32" else (TOL[prec], 0.0)
+    check_fields(e, _oracle_e(prob, ref["e"][-1]), prec,
+                 f"LTS 27-block subgrid (reduced), step {steps} (oracle's own fp32 rounding {own:.2e})", tol=tol)
+    formed = np.arange(steps) % 5 == 0
+    assert np.all(np.isnan(w[~formed]))
+    assert rel_l2(w[formed], ref["energy"][formed]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_substep_is_the_leapfrog_bitwise(sbp, prec):
+    prob = _pair(0, 3)
+    init = _init(prob, 4)
+    steps = 25
+    a = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    b = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    try:
+        write_fields(a, init)
+        write_fields(b, init)
+        a.step(steps)
+        b.lts_start([1], 1, a.dt, 1)
+        b.lts_step(steps)
+        for blk in range(2):
+            for c in E_COMPS:
+                assert np.array_equal(a.read_field(blk, c), b.read_field(blk, c)), (blk, c)
+        w = b.read_energy(0, steps)
+    finally:
+        a.close()
+        b.close()
+    ref = T.run(prob, [1], 1, steps, a.dt, init)
+    assert rel_l2(w, ref["energy"]) < TOL[prec]
+
+
+def test_lts_near_tiles_are_a_fraction(sbp):
+    """At full size the correction runs on the refined block and a few cells
+    of its neighbours: the corrected E nodes are well below all."""
+    prob, fine = _subgrid_lossless(1)
+    ctx = sbp.build_problem(prob, prec="f32", history=16)
+    try:
+        dt = 2.0 * ctx.dt
+        ctx.lts_start([fine], 2, dt, 0)
+        ctx.lts_step(2)
+        info = ctx.lts_info()
+        w = ctx.read_energy(0, 2)
+    finally:
+        ctx.close()
+    total = sum(int(np.prod([v + 2 for v in b["n"]])) for b in prob["blocks"])
+    fine_nodes = int(np.prod([v + 2 for v in prob["blocks"][fine]["n"]]))
+    assert info["nodes"] == total
+    assert fine_nodes <= info["near_nodes"] < 0.3 * total, info
+    assert info["near_tiles"] < 0.5 * info["tiles"], info
+    assert np.all(np.isnan(w))
+
+
+def test_lts_errors(sbp):
+    from paper_2206_00638_amd.binding import SBP_EINVAL, SBP_ESTATE, SbpError
+    prob = _pair(0, 1)
+
+    def status(fn):
+        with pytest.raises(SbpError) as ei:
+            fn()
+        return ei.value.status
+
+    ctx = sbp.build_problem(prob, prec="f64", history=16)
+    try:
+        dt = ctx.dt
+        assert status(lambda: ctx.lts_step(1)) == SBP_ESTATE
+        for args in [([1], 0, dt), ([1], 65, dt), ([1], 2, 0.0), ([1], 2, -dt), ([5], 2, dt)]:
+            assert status(lambda: ctx.lts_start(*args)) == SBP_EINVAL, args
+        assert status(lambda: ctx.lts_start([1], 2, dt, -1)) == SBP_EINVAL
+        ctx.lts_start([1], 2, dt)
+        assert status(lambda: ctx.lts_start([1], 2, dt)) == SBP_ESTATE
+        assert status(lambda: ctx.step(1)) == SBP_ESTATE
+        assert status(lambda: ctx.set_fused(1)) == SBP_ESTATE
+        ctx.lts_step(2)
+    finally:
+        ctx.close()
+    lossy = _pair(0, 1)
+    lossy["blocks"][0]["sigma"] = np.full(lossy["blocks"][0]["eps_r"].shape, 0.01)
+    absorbing = _pair(0, 1)
+    absorbing["blocks"][0]["faces"][0] = "abc"
+    src = _pair(0, 1)
+    src["sources"] = [{"block": 0, "comp": "Ez", "node": (3, 3, 3), "waveform": "gauss", "tw": 1e-10, "t0": 3e-10,
+                       "f0": 0.0, "amp": 1.0}]
+    for bad in (lossy, absorbing, src):
+        c2 = sbp.build_problem(bad, prec="f64", history=16)
+        try:
+            assert status(lambda: c2.lts_start([1], 2, c2.dt)) == SBP_EINVAL
+        finally:
+            c2.close()

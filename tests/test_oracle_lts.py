@@ -125,3 +125,62 @@ def test_second_order_convergence():
         errs.append(np.linalg.norm(r["e"][-1] - ref) / np.linalg.norm(ref))
     assert errs[0] < 0.2
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def _node_distance(prob, fine):
+    """Chebyshev distance, in the block's own cells, of every E node from the
+    box of the refined block (0 inside)."""
+    sysm = S.System(prob)
+    F = prob["blocks"][fine]
+    lo = np.array(F["origin"])
+    hi = lo + np.array(F["n"]) * np.array(F["h"])
+    dist = np.zeros(sysm.ne)
+    for b, blk in enumerate(prob["blocks"]):
+        n, h, x0 = blk["n"], blk["h"], blk["origin"]
+        for c in ("Ex", "Ey", "Ez"):
+            xs = [_positions(S.GRID[c][a], n[a], h[a], x0[a]) for a in range(3)]
+            d = [np.maximum(np.maximum(lo[a] - xs[a], xs[a] - hi[a]), 0.0) / h[a] for a in range(3)]
+            D = np.maximum(np.maximum(d[2][:, None, None], d[1][None, :, None]), d[0][None, None, :])
+            o = sysm.e_off[(b, c)]
+            dist[o:o + D.size] = D.reshape(-1)
+    return dist
+
+
+def test_refined_coupling_reaches_one_cell():
+    """The 27-block 1:2 subgrid geometry (reduced, absorbing faces made PEC):
+    L P x vanishes on every E node more than one of its block's cells from
+    the refined block, and the refined rows of L E read no E beyond one
+    cell.  A correction that only touches the refined block's neighbourhood
+    (a few cells wide) therefore carries the whole difference between the
+    local and the global step."""
+    from sbp_inputs import lossless_subgrid
+    prob, fine = lossless_subgrid(8)
+    lts = T.Lts(prob, [fine], 2)
+    dist = _node_distance(prob, fine)
+    rng = np.random.default_rng(5)
+    y = lts.L(lts.P * rng.standard_normal(lts.sys.ne))
+    reach = dist[np.abs(y) > 0].max()
+    assert 0.5 < reach <= 1.0 + 1e-9, reach
+    e = rng.standard_normal(lts.sys.ne)
+    ref = lts.P * lts.L(e)
+    got = lts.P * lts.L(e * (dist <= 1.0 + 1e-9))
+    assert np.array_equal(got, ref)
+    # and the reach is real: cutting at half a cell changes the refined rows
+    cut = lts.P * lts.L(e * (dist <= 0.4))
+    assert np.abs(cut - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_float32_run_follows_the_fp64_run():
+    """The float32 mode (which sizes the fp32 tolerance of the GPU path) is
+    the same recursion: close to the fp64 run, not equal to it, and its
+    energy constant to fp32 rounding."""
+    prob = _problem()
+    init = _random_init(prob, 2)
+    dt = 1.5 * S.cfl_dt(prob["blocks"], 0.9)
+    r64 = T.run(prob, [1], 2, 40, dt, init)
+    r32 = T.run(prob, [1], 2, 40, dt, init, dtype=np.float32)
+    assert r32["e"][-1].dtype == np.float32
+    err = np.linalg.norm(r32["e"][-1] - r64["e"][-1]) / np.linalg.norm(r64["e"][-1])
+    assert 1e-8 < err < 1e-4, err
+    w = r32["energy"]
+    assert np.abs(w / w[0] - 1).max() < 1e-4
