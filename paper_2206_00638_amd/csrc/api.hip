@@ -26,11 +26,8 @@ template <typename T> hipError_t launch_h(const KArgs&, int, int, int, hipStream
 template <typename T> hipError_t launch_e(const KArgs&, int, int, int, hipStream_t);
 hipError_t launch_finish(const KArgs&, int, int, hipStream_t);
 template <typename T>
-hipError_t lts_prep(void*, const void*, const void*, int, const Tile*, int, const DevBlock*, const LtsBox*, int, int,
-                    hipStream_t);
-template <typename T>
-hipError_t lts_box(int, int, void*, const void*, void*, const void*, const void*, void*, void*, double,
-                   const DevBlock*, const LtsBox*, hipStream_t);
+hipError_t lts_phase(int, int, int, void*, void*, void*, const void*, const void*, void*, void*, double, double,
+                     const Tile*, int, const DevBlock*, const LtsBox*, int, int, hipStream_t);
 template <typename T>
 hipError_t lts_whole(int, int, const void*, void*, const void*, const void*, double, const DevBlock*, const void*,
                      double, double*, hipStream_t);
@@ -150,11 +147,15 @@ struct sbp_ctx {
   LtsBox* lts_boxes = nullptr;
   std::vector<LtsBox> lts_hbox;  // near boxes (the recursion's nodes)
   std::vector<LtsBox> lts_tbox;  // wider boxes (the operator's tiles)
-  Tile* d_near = nullptr;
-  size_t near_cap = 0;
-  int nnear = 0;
-  int nk_t0[32] = {}, nk_t1[32] = {};
-  bool near_dirty = true;
+  Tile* d_near = nullptr;  // tiles meeting the wider boxes (the operator and the phases)
+  Tile* d_far = nullptr;   // tiles of the blocks that are not refined (the ordinary step)
+  size_t near_cap = 0, far_cap = 0;
+  int nnear = 0, nfar = 0;
+  int nk_t0[32] = {}, nk_t1[32] = {}, fk_t0x[32] = {}, fk_t1x[32] = {};
+  GatherWG* d_nwg[2] = {nullptr, nullptr};  // gather workgroups whose face nodes meet a wider box (E, H)
+  GatherWG* d_fwg[2] = {nullptr, nullptr};  // gather workgroups of faces between blocks that are not refined
+  int nnwg[2] = {0, 0}, nfwg[2] = {0, 0};
+  bool near_dirty = true, near_built = false;
   FTile* d_ftiles = nullptr;
   FTile* d_ftiles_bare = nullptr;
   size_t ftiles_cap = 0;
@@ -187,6 +188,8 @@ struct sbp_ctx {
   GatherWG* d_wg_e = nullptr;  // per-workgroup job tables of the two gathers
   GatherWG* d_wg_h = nullptr;
   int nwg_e = 0, nwg_h = 0;
+  std::vector<FaceJob> hjobs[2];  // host copies (E, H)
+  std::vector<GatherWG> hwg[2];
   Taps* d_taps = nullptr;
   // total-field / scattered-field injection (sbp_set_tfsf): the block, cell
   // box, propagation axis, E polarisation, line margin, the incident source
@@ -792,12 +795,22 @@ void* pool_other(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool : c->
 // One leapfrog step of the state that `a` points at (pool, face buffers,
 // energy / probe rings, step counter): the forward state (kargs(c)) or the
 // adjoint state of sbp_adjoint.
-sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const int* kt0 = nullptr, const int* kt1 = nullptr) {
+// Tile ranges per kind and gather workgroup tables of a step over part of
+// the blocks (local time stepping); null: the context's own.
+struct StepLists {
+  const int *kt0, *kt1;
+  const GatherWG *wg_e, *wg_h;
+  int nwg_e, nwg_h;
+  bool finish;  // false: no finish kernel (no energy, step index or sources)
+};
+
+sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* lists = nullptr) {
   const int threads = c->tx * c->ty;
-  if (!kt0) {
-    kt0 = c->kind_t0;
-    kt1 = c->kind_t1;
-  }
+  const int* kt0 = lists ? lists->kt0 : c->kind_t0;
+  const int* kt1 = lists ? lists->kt1 : c->kind_t1;
+  const GatherWG* wg_e = lists ? lists->wg_e : c->d_wg_e;
+  const GatherWG* wg_h = lists ? lists->wg_h : c->d_wg_h;
+  const int nwg_e = lists ? lists->nwg_e : c->nwg_e, nwg_h = lists ? lists->nwg_h : c->nwg_h;
   const bool f64 = c->prec == SBP_FP64;
   hipError_t e;
   double* face = const_cast<double*>(a.face);
@@ -808,8 +821,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const int* kt0 = nu
   // kinds stepped by the two-pass kernels: all, or only the general ones
   auto two_pass = [&](int kind) { return kt1[kind] > kt0[kind] && (!c->fused || (kind & 2)); };
   if (c->njobs_e) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_e, c->d_wg_e, c->nwg_e, c->d_taps, a, 0, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, wg_e, nwg_e, c->d_taps, a, 0, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_e, wg_e, nwg_e, c->d_taps, a, 0, face, c->stream);
     HIPCHK(c, e);
   }
   sbp_status st = mark();
@@ -833,8 +846,8 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const int* kt0 = nu
   const int nh = nparts;
   if ((st = mark()) != SBP_OK) return st;
   if (c->njobs_h) {
-    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream)
-            : launch_gather<float>(c->d_blocks, c->d_jobs_h, c->d_wg_h, c->nwg_h, c->d_taps, a, 1, face, c->stream);
+    e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_h, wg_h, nwg_h, c->d_taps, a, 1, face, c->stream)
+            : launch_gather<float>(c->d_blocks, c->d_jobs_h, wg_h, nwg_h, c->d_taps, a, 1, face, c->stream);
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
@@ -865,6 +878,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const int* kt0 = nu
     }
   }
   if ((st = mark()) != SBP_OK) return st;
+  if (lists && !lists->finish) return SBP_OK;
   HIPCHK(c, launch_finish(a, nh, nparts, c->stream));  // W^n into ring slot n; n += 1; sources of step n+1
   return SBP_OK;
 }
@@ -906,7 +920,9 @@ sbp_status lts_apply(sbp_ctx* c, bool whole) {
   a.nsrc = 0;
   a.dt = 1.0;
   a.tf = nullptr;
-  return whole ? enqueue_step_on(c, a, false) : enqueue_step_on(c, a, false, c->nk_t0, c->nk_t1);
+  if (whole) return enqueue_step_on(c, a, false);
+  const StepLists near{c->nk_t0, c->nk_t1, c->d_nwg[0], c->d_nwg[1], c->nnwg[0], c->nnwg[1], false};
+  return enqueue_step_on(c, a, false, &near);
 }
 
 // Boxes of local time stepping: a refined block whole; in another block the
@@ -962,14 +978,20 @@ std::vector<LtsBox> lts_boxes(const sbp_ctx* c, const std::vector<int>& refined,
   return out;
 }
 
-// The tiles (of the flag-free list) that meet a wider box, ranges per kind.
-sbp_status lts_near_tiles(sbp_ctx* c) {
+// The lists of local time stepping: the tiles (of the flag-free list) that
+// meet a wider box and those of the blocks that are not refined, ranges per
+// kind; the gather workgroups whose own face nodes meet a wider box.  The
+// scratch state is cleared when the lists are rebuilt (it must be zero off
+// the tiles of the operator).
+sbp_status lts_lists(sbp_ctx* c) {
   const int threads = c->tx * c->ty;
-  std::vector<Tile> nt;
+  std::vector<Tile> nt, ft;
   for (int kind = 0; kind < 32; ++kind) {
     c->nk_t0[kind] = (int)nt.size();
+    c->fk_t0x[kind] = (int)ft.size();
     for (int t = c->kind_t0[kind]; t < c->kind_t1[kind]; ++t) {
       const Tile& tl = c->bare[t];
+      if (!c->lts_tbox[tl.block].refined) ft.push_back(tl);
       const LtsBox& bx = c->lts_tbox[tl.block];
       if (!bx.on) continue;
       const HostBlock& b = c->blocks[tl.block];
@@ -985,18 +1007,62 @@ sbp_status lts_near_tiles(sbp_ctx* c) {
       if (hit) nt.push_back(tl);
     }
     c->nk_t1[kind] = (int)nt.size();
+    c->fk_t1x[kind] = (int)ft.size();
   }
-  if (nt.size() > c->near_cap) {
-    dfree(c, c->d_near);
-    c->d_near = (Tile*)dalloc(c, nt.size() * sizeof(Tile));
-    if (!c->d_near) return fail(c, SBP_ENOMEM, "tile list allocation failed");
-    c->near_cap = nt.size();
+  // gather workgroups: own face nodes (r0, r1) along the job's tangential
+  // axes, the face at node 0 or at the far end of its normal axis
+  std::vector<GatherWG> gw[2], fw[2];
+  for (int g = 0; g < 2; ++g)
+    for (const GatherWG& w : c->hwg[g]) {
+      const FaceJob& J = c->hjobs[g][w.job];
+      // the ordinary step needs no face of or from a refined block: those
+      // values reach only E nodes of the near boxes, which the recursion
+      // replaces
+      if (!c->lts_tbox[J.block].refined && !c->lts_tbox[J.nb].refined) fw[g].push_back(w);
+      const LtsBox& bx = c->lts_tbox[J.block];
+      if (!bx.on) continue;
+      const int ax = J.face >> 1, n = c->blocks[J.block].n[ax];
+      if ((J.face & 1) ? bx.hi[ax] < n : bx.lo[ax] > 0) continue;
+      const long long tot = (long long)J.ext[0] * J.ext[1];
+      bool hit = false;
+      for (long long id = w.first; id < std::min<long long>(w.first + 256, tot) && !hit; ++id) {
+        const int r0 = (int)(id % J.ext[0]), r1 = (int)(id / J.ext[0]);
+        hit = r0 >= bx.lo[J.t_axis[0]] && r0 <= bx.hi[J.t_axis[0]] && r1 >= bx.lo[J.t_axis[1]] &&
+              r1 <= bx.hi[J.t_axis[1]];
+      }
+      if (hit) gw[g].push_back(w);
+    }
+  auto upload = [&](auto& dst, size_t& cap, const auto& src) -> bool {
+    using E = typename std::decay<decltype(src)>::type::value_type;
+    if (src.size() > cap || !dst) {
+      dfree(c, dst);
+      dst = (std::remove_reference_t<decltype(dst)>)dalloc(c, std::max<size_t>(src.size(), 1) * sizeof(E));
+      if (!dst) return false;
+      cap = std::max<size_t>(src.size(), 1);
+    }
+    return src.empty() || hipMemcpyAsync(dst, src.data(), src.size() * sizeof(E), hipMemcpyHostToDevice,
+                                         c->stream) == hipSuccess;
+  };
+  size_t gcap[4] = {0, 0, 0, 0};
+  for (int g = 0; g < 2; ++g) {
+    dfree(c, c->d_nwg[g]);
+    dfree(c, c->d_fwg[g]);
+    c->d_nwg[g] = c->d_fwg[g] = nullptr;
   }
+  if (!upload(c->d_near, c->near_cap, nt) || !upload(c->d_far, c->far_cap, ft) ||
+      !upload(c->d_nwg[0], gcap[0], gw[0]) || !upload(c->d_nwg[1], gcap[1], gw[1]) ||
+      !upload(c->d_fwg[0], gcap[2], fw[0]) || !upload(c->d_fwg[1], gcap[3], fw[1]))
+    return fail(c, SBP_ENOMEM, "local time stepping list allocation failed");
   c->nnear = (int)nt.size();
-  if (!nt.empty())
-    HIPCHK(c, hipMemcpyAsync(c->d_near, nt.data(), nt.size() * sizeof(Tile), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));  // nt is a local
+  c->nfar = (int)ft.size();
+  for (int g = 0; g < 2; ++g) {
+    c->nnwg[g] = (int)gw[g].size();
+    c->nfwg[g] = (int)fw[g].size();
+  }
+  if (c->near_built) HIPCHK(c, hipMemsetAsync(c->lts_s, 0, c->pool_elems * elem_size(c), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the host lists are locals
   c->near_dirty = false;
+  c->near_built = true;
   return SBP_OK;
 }
 
@@ -1529,6 +1595,10 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   const std::vector<GatherWG> we = wg_table(je), wh = wg_table(jh);
   c->nwg_e = (int)we.size();
   c->nwg_h = (int)wh.size();
+  c->hjobs[0] = je;
+  c->hjobs[1] = jh;
+  c->hwg[0] = we;
+  c->hwg[1] = wh;
   if (!je.empty()) {
     c->d_jobs_e = (FaceJob*)dalloc(c, je.size() * sizeof(FaceJob));
     c->d_jobs_h = (FaceJob*)dalloc(c, jh.size() * sizeof(FaceJob));
@@ -1822,36 +1892,34 @@ sbp_status sbp_lts_start(sbp_ctx* c, const int* refined, int nrefined, int subst
   c->lts_dt = dt_coarse;
   c->lts_every = energy_every;
   c->lts = true;
-  if (!sub) {
-    for (LtsBox& x : c->lts_tbox) x.on = 0;
-  }
-  sbp_status st = lts_near_tiles(c);
+  if (!sub)
+    for (LtsBox& x : c->lts_tbox) x.on = x.refined = 0;
+  sbp_status st = lts_lists(c);
   if (st != SBP_OK) return st;
   if (sub || track) {
     // E^{-1} = E^0 - dt A H^{-1/2} (on the near boxes; everywhere for the
     // energy): the scratch state (E = 0, H = H^{-1/2}) after one unit step
-    // on all tiles holds A H^{-1/2}; the scratch state is cleared again
-    // afterwards (it is zero away from the operator's tiles from here on)
+    // on all tiles holds A H^{-1/2}; the scratch state and its face buffers
+    // are cleared again afterwards
     const bool f64 = c->prec == SBP_FP64;
     void* M = pool_at(c, c->nstep);
     const int threads = c->tx * c->ty;
-    HIPCHK(c, f64 ? lts_prep<double>(c->lts_s, M, nullptr, 2, c->d_tiles_bare, c->ntiles, c->lts_blocks,
-                                     c->lts_boxes, threads, c->cz, c->stream)
-                  : lts_prep<float>(c->lts_s, M, nullptr, 2, c->d_tiles_bare, c->ntiles, c->lts_blocks, c->lts_boxes,
-                                    threads, c->cz, c->stream));
-    st = lts_apply(c, true);
-    if (st != SBP_OK) return st;
-    if (sub)
-      HIPCHK(c, f64 ? lts_box<double>(5, nb, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, dt_coarse,
-                                      c->d_blocks, c->lts_boxes, c->stream)
-                    : lts_box<float>(5, nb, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, dt_coarse,
-                                     c->d_blocks, c->lts_boxes, c->stream));
+    auto phase = [&](int op, int nmode, const Tile* tiles, int ntiles) {
+      return f64 ? lts_phase<double>(op, nmode, 0, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, 0.0,
+                                     dt_coarse, tiles, ntiles, c->d_blocks, c->lts_boxes, threads, c->cz, c->stream)
+                 : lts_phase<float>(op, nmode, 0, M, c->lts_s, nullptr, nullptr, nullptr, nullptr, c->lts_ep, 0.0,
+                                    dt_coarse, tiles, ntiles, c->d_blocks, c->lts_boxes, threads, c->cz, c->stream);
+    };
+    HIPCHK(c, phase(-1, 2, c->d_tiles_bare, c->ntiles));
+    if ((st = lts_apply(c, true)) != SBP_OK) return st;
+    if (sub) HIPCHK(c, phase(4, -1, c->d_near, c->nnear));
     if (track)
       HIPCHK(c, f64 ? lts_whole<double>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
                                         0.0, nullptr, c->stream)
                     : lts_whole<float>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
                                        0.0, nullptr, c->stream));
     HIPCHK(c, hipMemsetAsync(c->lts_s, 0, pb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->lts_face, 0, c->face_elems * sizeof(double), c->stream));
   }
   return SBP_OK;
 }
@@ -1860,9 +1928,10 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
   if (!c) return SBP_EINVAL;
   if (!c->lts) return fail(c, SBP_ESTATE, "sbp_lts_step before sbp_lts_start");
   if (nsteps < 0) return fail(c, SBP_EINVAL, "negative step count");
+  if (nsteps == 0) return SBP_OK;
   HIPCHK(c, hipSetDevice(c->device));
   if (c->near_dirty) {
-    const sbp_status st = lts_near_tiles(c);
+    const sbp_status st = lts_lists(c);
     if (st != SBP_OK) return st;
   }
   const bool f64 = c->prec == SBP_FP64;
@@ -1870,17 +1939,11 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
   const double dt = c->lts_dt, tau = dt / p, tau2 = tau * tau;
   const long K = c->lts_every;
   const KArgs ka = kargs(c);
-  auto prep = [&](int mode, const void* M, const void* Q) {
-    return f64 ? lts_prep<double>(c->lts_s, M, Q, mode, c->d_near, c->nnear, c->lts_blocks, c->lts_boxes, threads,
-                                  c->cz, c->stream)
-               : lts_prep<float>(c->lts_s, M, Q, mode, c->d_near, c->nnear, c->lts_blocks, c->lts_boxes, threads,
-                                 c->cz, c->stream);
-  };
-  auto box = [&](int op, void* M, const void* Qm, const void* Qp, void* Qo) {
-    return f64 ? lts_box<double>(op, nb, M, c->lts_s, c->lts_w, Qm, Qp, Qo, c->lts_ep, tau2, c->d_blocks,
-                                 c->lts_boxes, c->stream)
-               : lts_box<float>(op, nb, M, c->lts_s, c->lts_w, Qm, Qp, Qo, c->lts_ep, tau2, c->d_blocks,
-                                c->lts_boxes, c->stream);
+  auto phase = [&](int op, int nmode, int last, void* M, const void* qm, const void* qp, void* qo) {
+    return f64 ? lts_phase<double>(op, nmode, last, M, c->lts_s, c->lts_w, qm, qp, qo, c->lts_ep, tau2, dt, c->d_near,
+                                   c->nnear, c->d_blocks, c->lts_boxes, threads, c->cz, c->stream)
+               : lts_phase<float>(op, nmode, last, M, c->lts_s, c->lts_w, qm, qp, qo, c->lts_ep, tau2, dt, c->d_near,
+                                  c->nnear, c->d_blocks, c->lts_boxes, threads, c->cz, c->stream);
   };
   auto whole = [&](int op, const void* M, void* X, const void* Y, double d) {
     return f64 ? lts_whole<double>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
@@ -1888,41 +1951,47 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
                : lts_whole<float>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
                                   c->stream);
   };
+  sbp_status st;
+  // the scratch state of the first operator step: E = (I - P) E^n
+  if (p > 1) HIPCHK(c, phase(-1, 0, 0, pool_at(c, c->nstep), nullptr, nullptr, nullptr));
   for (long s = 0; s < nsteps; ++s) {
     const long long n = c->nstep;
     void* M = pool_at(c, n);  // E^n, H^{n-1/2} (the two-pass step keeps one pool)
-    sbp_status st;
     if (p > 1) {
-      // w = L (I - P) E^n
-      HIPCHK(c, prep(0, M, nullptr));
+      // w = L (I - P) E^n; q_1; then q_{m+1} from q_m, q_{m-1} (q_m in
+      // lts_qa for odd m, lts_qb for even m > 0); the last substep leaves
+      // E^{n+1} in lts_w
       if ((st = lts_apply(c, false)) != SBP_OK) return st;
-      HIPCHK(c, box(0, M, nullptr, nullptr, nullptr));
-      // q_1 from q_0 = E^n; then q_{m+1} from q_m, q_{m-1} (q_m in lts_qa for
-      // odd m, lts_qb for even m > 0)
-      HIPCHK(c, prep(1, M, M));
+      HIPCHK(c, phase(0, 1, 0, M, nullptr, nullptr, nullptr));
       if ((st = lts_apply(c, false)) != SBP_OK) return st;
-      HIPCHK(c, box(1, M, nullptr, nullptr, c->lts_qa));
+      HIPCHK(c, phase(1, 1, 0, M, nullptr, nullptr, c->lts_qa));
       for (int m = 1; m < p; ++m) {
         void* qm = (m & 1) ? c->lts_qa : c->lts_qb;
         const void* qp = m == 1 ? M : ((m & 1) ? c->lts_qb : c->lts_qa);
         void* qo = (m & 1) ? c->lts_qb : c->lts_qa;
-        HIPCHK(c, prep(1, M, qm));
+        const bool last = m == p - 1;
         if ((st = lts_apply(c, false)) != SBP_OK) return st;
-        HIPCHK(c, box(2, M, qm, qp, qo));
+        HIPCHK(c, phase(2, last ? -1 : 1, last ? 1 : 0, M, qm, qp, qo));
       }
-      // E^{n+1} = -E^{n-1} + 2 q_p on the near boxes (held in w); E^{n-1} <- E^n
-      HIPCHK(c, box(3, M, (p & 1) ? c->lts_qa : c->lts_qb, nullptr, nullptr));
     }
     // copies of E^n for the energy of this step or the next
     const bool form = K > 0 && n % K == 0;
     if (K > 0 && (form || (n + 1) % K == 0)) HIPCHK(c, whole(0, M, c->lts_x[n & 1], nullptr, 0.0));
-    // the ordinary step of length dt: H^{n+1/2}, E^n + dt A H^{n+1/2}
+    // the ordinary step of length dt on the blocks that are not refined
     KArgs a = ka;
     a.blocks = c->lts_cblocks;
     a.dt = dt;
-    if ((st = enqueue_step_on(c, a, false)) != SBP_OK) return st;
-    // the scheme's E^{n+1} on the near boxes
-    if (p > 1) HIPCHK(c, box(4, M, nullptr, nullptr, nullptr));
+    if (p > 1) {
+      a.tiles = c->d_far;
+      const StepLists far{c->fk_t0x, c->fk_t1x, c->d_fwg[0], c->d_fwg[1], c->nfwg[0], c->nfwg[1], true};
+      st = enqueue_step_on(c, a, false, &far);
+    } else {
+      a.tiles = c->d_tiles_bare;
+      st = enqueue_step_on(c, a, false);
+    }
+    if (st != SBP_OK) return st;
+    // the scheme's E^{n+1} on the near boxes, and the next step's scratch state
+    if (p > 1) HIPCHK(c, phase(3, s + 1 < nsteps ? 0 : -1, 0, M, nullptr, nullptr, nullptr));
     double* slot = ka.energy + (int)(n % ka.ecap);
     if (form) {
       HIPCHK(c, whole(2, M, c->lts_x[(n + 1) & 1], c->lts_x[n & 1], 0.5 / (dt * dt)));

@@ -14,18 +14,21 @@
 // E^{n+1} differs from the leapfrog's (with H^{n+1/2} = H^{n-1/2} + dt B E^n,
 // E^{n+1} = E^n + dt A H^{n+1/2}) only on E nodes within a cell of a refined
 // block: L P reaches that far and no farther, and the refined rows of L read
-// E no farther.  So a coarse step is the ordinary step of length dt on every
-// block, followed by the recursion above on a near box (the refined blocks
-// whole and the nodes of other blocks within two of their cells of a refined
-// block), whose result replaces the ordinary step's there.  The H arrays
-// keep the ordinary step's H, which the E-only scheme has no use for; away
-// from the near boxes it is the leapfrog's.
+// E no farther.  So a coarse step is the ordinary step of length dt on the
+// blocks that are not refined, followed by the recursion above, in its own
+// order of operations, on a near box (the refined blocks whole and the nodes
+// of other blocks within two of their cells of a refined block), whose
+// result replaces the ordinary step's there.  The H arrays keep the ordinary
+// step's H, which the E-only scheme has no use for; away from the near boxes
+// it is the leapfrog's; on the refined blocks it is not stepped.
 //
 // The operator is applied by one leapfrog step of unit time step on a
 // scratch state holding E = u and H = 0: the H pass leaves B u, the E pass
 // u + A B u = u - L u.  Those steps run on the tiles that meet a wider box
 // (four cells), so that every H and E value the near box reads is formed
-// from nonzero input; the scratch state is zero elsewhere.
+// from nonzero input; the scratch state is zero elsewhere.  The element-wise
+// parts of the recursion run over the same tiles, each fused with the
+// preparation of the next scratch state.
 #include <hip/hip_runtime.h>
 
 #include "plan.h"
@@ -43,89 +46,87 @@ __device__ __forceinline__ bool e_valid(const DevBlock& B, int c, int i, int j, 
   return i <= nx && j <= ny && k <= nz + 1;
 }
 
-// Scratch state on the nodes of a tile list (one workgroup per tile;
-// `threads` node columns x cz planes per tile):
-//   mode 0: E = (I - P) E^n (the pool's E off the refined blocks);  H = 0
-//   mode 1: E = P q (Q's E on the refined blocks; Q may be the pool);  H = 0
-//   mode 2: E = 0;  H = the pool's H
+__device__ __forceinline__ bool in_box(const LtsBox& x, int i, int j, int k) {
+  return x.on && i >= x.lo[0] && i <= x.hi[0] && j >= x.lo[1] && j <= x.hi[1] && k >= x.lo[2] && k <= x.hi[2];
+}
+
+// One phase of a coarse step on the nodes of a tile list (one workgroup per
+// tile; `threads` node columns x cz planes per tile).  E^n is the pool's E
+// (until the ordinary step), S = u - L u for the u of the preceding scratch
+// state.  First, on the E nodes of the near boxes:
+//   op 0 (u = (I - P) E^n): W = L (I - P) E^n = (I - P) E^n - S
+//   op 1 (u = P E^n): q_1 = E^n - tau2/2 (W + L P E^n), L P E^n = P E^n - S;
+//        into Qo
+//   op 2 (u = P q_m): q_{m+1} = 2 Qm - Qp - tau2 (W + L P q_m),
+//        L P q_m = P q_m - S (Qp = q_{m-1}, the pool for m = 1); into Qo, or
+//        with `last`: W = E^{n+1} = 2 q_{m+1} - Ep and Ep = E^n
+//   op 3: the pool's E = W (after the ordinary step)
+//   op 4: Ep = E^n - dt S (E^{-1}, S holding A H^{-1/2})
+// Then the next scratch state on every node of the tiles (nmode):
+//   0: E = (I - P) E (the pool's);  1: E = P q, q = E^n after op 0, the q
+//   just formed after ops 1 and 2;  2: E = 0, H = the pool's H;
+//   H = 0 in modes 0 and 1.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lts_prep(T* S, const T* pool, const T* Q, int mode, const Tile* tiles,
-                                                 const DevBlock* blocks, const LtsBox* boxes, int threads, int cz) {
+__global__ __launch_bounds__(256) void k_lts_phase(int op, int nmode, int last, T* pool, T* S, T* W, const T* Qm,
+                                                  const T* Qp, T* Qo, T* Ep, double tau2, double dt,
+                                                  const Tile* tiles, const DevBlock* blocks, const LtsBox* boxes,
+                                                  int threads, int cz) {
   const Tile tl = tiles[blockIdx.x];
   const DevBlock& B = blocks[tl.block];
-  const int refined = boxes[tl.block].refined;
+  const LtsBox bx = boxes[tl.block];
   const long long sx = B.sx, sxy = B.sxy, csz = B.csz;
   const long long plane = sx * (B.n[1] + 2);
   const int nz2 = B.n[2] + 2;
+  const T t2 = (T)tau2, tdt = (T)dt;
   for (int idx = threadIdx.x; idx < threads * cz; idx += blockDim.x) {
     const long long q = tl.q0 + idx % threads;
     const int k = tl.z0 + idx / threads;
     if (q >= plane || k >= nz2) continue;
     const int j = (int)(q / sx), i = (int)(q - j * sx);
     const long long o = B.foff + q + sxy * k;
+    const bool near = in_box(bx, i, j, k);
     for (int c = 0; c < 3; ++c) {
       const long long e = o + c * csz, h = o + (3 + c) * csz;
-      T v = T(0);
-      if (e_valid(B, c, i, j, k)) {
-        if (mode == 0 && !refined) v = pool[e];
-        if (mode == 1 && refined) v = Q[e];
+      const bool valid = e_valid(B, c, i, j, k);
+      T qnext = T(0);
+      if (valid && near) {
+        if (op == 0) {
+          const T en = pool[e];
+          W[e] = (bx.refined ? T(0) : en) - S[e];
+          qnext = en;
+        } else if (op == 1) {
+          const T en = pool[e];
+          const T lpq = (bx.refined ? en : T(0)) - S[e];
+          const T q1 = en - (T(0.5) * t2) * (W[e] + lpq);
+          Qo[e] = q1;
+          qnext = q1;
+        } else if (op == 2) {
+          const T qm = Qm[e];
+          const T lpq = (bx.refined ? qm : T(0)) - S[e];
+          const T qn = (T(2) * qm - Qp[e]) - t2 * (W[e] + lpq);
+          if (last) {
+            const T en = pool[e];
+            W[e] = T(2) * qn - Ep[e];
+            Ep[e] = en;
+          } else {
+            Qo[e] = qn;
+            qnext = qn;
+          }
+        } else if (op == 3) {
+          pool[e] = W[e];
+        } else if (op == 4) {
+          Ep[e] = pool[e] - tdt * S[e];
+        }
       }
-      S[e] = v;
-      S[h] = mode == 2 ? pool[h] : T(0);
-    }
-  }
-}
-
-// Element-wise steps over the near boxes (grid row y = block), E^n the
-// pool's E, S = u - L u for the u of the preceding prep:
-//   op 0: W = L (I - P) E^n = (I - P) E^n - S
-//   op 1: first substep: Qo = E^n - tau2/2 (W + L P E^n), L P E^n = P E^n - S
-//   op 2: later substep: Qo = 2 Qm - Qp - tau2 (W + L P Qm), L P Qm = P Qm - S
-//         (Qp may be the pool, Qo may be Qp)
-//   op 3: before the ordinary step: W = -Ep + 2 Qm (E^{n+1}); Ep = E^n
-//   op 4: after it: E = W
-//   op 5: Ep = E^n - coef S (E^{-1} = E^0 - dt A H^{-1/2}, S holding A H^{-1/2})
-template <typename T>
-__global__ __launch_bounds__(256) void k_lts_box(int op, T* pool, const T* S, T* W, const T* Qm, const T* Qp, T* Qo,
-                                                T* Ep, double coef, const DevBlock* blocks, const LtsBox* boxes) {
-  const DevBlock& B = blocks[blockIdx.y];
-  const LtsBox bx = boxes[blockIdx.y];
-  if (!bx.on) return;
-  const int ex = bx.hi[0] - bx.lo[0] + 1, ey = bx.hi[1] - bx.lo[1] + 1, ez = bx.hi[2] - bx.lo[2] + 1;
-  const long long per = (long long)ex * ey * ez;
-  const T cf = (T)coef;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * per;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / per);
-    long long r = t - c * per;
-    const int kk = (int)(r / ((long long)ex * ey));
-    r -= (long long)kk * ex * ey;
-    const int jj = (int)(r / ex), ii = (int)(r - (long long)jj * ex);
-    const int i = bx.lo[0] + ii, j = bx.lo[1] + jj, k = bx.lo[2] + kk;
-    if (!e_valid(B, c, i, j, k)) continue;
-    const long long e = B.foff + c * B.csz + i + B.sx * j + B.sxy * k;
-    switch (op) {
-      case 0: W[e] = (bx.refined ? T(0) : pool[e]) - S[e]; break;
-      case 1: {
-        const T en = pool[e];
-        const T lpq = (bx.refined ? en : T(0)) - S[e];
-        Qo[e] = en - (T(0.5) * cf) * (W[e] + lpq);
-        break;
+      if (nmode >= 0) {
+        T v = T(0);
+        if (valid) {
+          if (nmode == 0 && !bx.refined) v = pool[e];
+          if (nmode == 1 && bx.refined) v = qnext;
+        }
+        S[e] = v;
+        S[h] = nmode == 2 ? pool[h] : T(0);
       }
-      case 2: {
-        const T qm = Qm[e];
-        const T lpq = (bx.refined ? qm : T(0)) - S[e];
-        Qo[e] = (T(2) * qm - Qp[e]) - cf * (W[e] + lpq);
-        break;
-      }
-      case 3: {
-        const T en = pool[e];
-        W[e] = T(2) * Qm[e] - Ep[e];
-        Ep[e] = en;
-        break;
-      }
-      case 4: pool[e] = W[e]; break;
-      default: Ep[e] = pool[e] - cf * S[e]; break;
     }
   }
 }
@@ -146,22 +147,24 @@ __global__ __launch_bounds__(256) void k_lts_whole(int op, const T* pool, T* X, 
   double acc = 0.0;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * csz;
        t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / csz);
-    const long long o = t - c * csz;
-    const int k = (int)(o / sxy);
-    const long long r = o - k * sxy;
-    const int j = (int)(r / sx), i = (int)(r - j * sx);
     const long long e = B.foff + t;
     if (op == 0) {
       X[e] = pool[e];
     } else if (op == 1) {
       X[e] = pool[e] - (T)d * S[e];
-    } else if (r < plane && e_valid(B, c, i, j, k)) {
-      const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
-      const double mw = eps0 * (0.25 * nc.S) * e_weight(B, c, i, j, k);
-      const double eo = (double)X[e], en = (double)Y[e], enew = (double)pool[e];
-      const double df = enew - en;
-      acc += mw * (df * df + enew * (2.0 * en - enew - eo));
+    } else {
+      const int c = (int)(t / csz);
+      const long long o = t - c * csz;
+      const int k = (int)(o / sxy);
+      const long long r = o - k * sxy;
+      const int j = (int)(r / sx), i = (int)(r - j * sx);
+      if (r < plane && e_valid(B, c, i, j, k)) {
+        const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
+        const double mw = eps0 * (0.25 * nc.S) * e_weight(B, c, i, j, k);
+        const double eo = (double)X[e], en = (double)Y[e], enew = (double)pool[e];
+        const double df = enew - en;
+        acc += mw * (df * df + enew * (2.0 * en - enew - eo));
+      }
     }
   }
   if (op != 2) return;
@@ -195,22 +198,15 @@ __global__ __launch_bounds__(256) void k_lts_store(const double* partials, int n
 
 }  // namespace
 
-constexpr int kLtsGrid = 64;  // workgroups per block row of the box and whole-part kernels
+constexpr int kLtsGrid = 64;  // workgroups per block row of the whole-part kernel
 
 template <typename T>
-hipError_t lts_prep(void* S, const void* pool, const void* Q, int mode, const Tile* tiles, int ntiles,
-                    const DevBlock* blocks, const LtsBox* boxes, int threads, int cz, hipStream_t s) {
+hipError_t lts_phase(int op, int nmode, int last, void* pool, void* S, void* Y, const void* Qm, const void* Qp,
+                     void* Qo, void* Ep, double tau2, double dt, const Tile* tiles, int ntiles, const DevBlock* blocks,
+                     const LtsBox* boxes, int threads, int cz, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lts_prep<T>, dim3(ntiles), dim3(256), 0, s, (T*)S, (const T*)pool, (const T*)Q, mode, tiles,
-                     blocks, boxes, threads, cz);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t lts_box(int op, int nblocks, void* pool, const void* S, void* W, const void* Qm, const void* Qp, void* Qo,
-                   void* Ep, double coef, const DevBlock* blocks, const LtsBox* boxes, hipStream_t s) {
-  hipLaunchKernelGGL(k_lts_box<T>, dim3(kLtsGrid, nblocks), dim3(256), 0, s, op, (T*)pool, (const T*)S, (T*)W,
-                     (const T*)Qm, (const T*)Qp, (T*)Qo, (T*)Ep, coef, blocks, boxes);
+  hipLaunchKernelGGL(k_lts_phase<T>, dim3(ntiles), dim3(256), 0, s, op, nmode, last, (T*)pool, (T*)S, (T*)Y,
+                     (const T*)Qm, (const T*)Qp, (T*)Qo, (T*)Ep, tau2, dt, tiles, blocks, boxes, threads, cz);
   return hipGetLastError();
 }
 
@@ -228,10 +224,9 @@ hipError_t lts_store(const double* partials, int nparts, double* slot, hipStream
 }
 
 #define SBP_LTS_INST(T)                                                                                             \
-  template hipError_t lts_prep<T>(void*, const void*, const void*, int, const Tile*, int, const DevBlock*,           \
-                                  const LtsBox*, int, int, hipStream_t);                                             \
-  template hipError_t lts_box<T>(int, int, void*, const void*, void*, const void*, const void*, void*, void*, double, \
-                                 const DevBlock*, const LtsBox*, hipStream_t);                                       \
+  template hipError_t lts_phase<T>(int, int, int, void*, void*, void*, const void*, const void*, void*, void*,       \
+                                   double, double, const Tile*, int, const DevBlock*, const LtsBox*, int, int,       \
+                                   hipStream_t);                                                                     \
   template hipError_t lts_whole<T>(int, int, const void*, void*, const void*, const void*, double, const DevBlock*, \
                                    const void*, double, double*, hipStream_t);
 SBP_LTS_INST(float)
