@@ -29,10 +29,11 @@ template <typename T>
 hipError_t lts_phase(int, int, int, void*, void*, void*, const void*, const void*, void*, void*, double, double,
                      const Tile*, int, const DevBlock*, const LtsBox*, int, int, hipStream_t);
 template <typename T>
-hipError_t lts_whole(int, int, const void*, void*, const void*, const void*, double, const DevBlock*, const void*,
-                     double, double*, hipStream_t);
+hipError_t lts_whole(int, int, const void*, void*, const void*, double, const DevBlock*, hipStream_t);
+template <typename T>
+hipError_t lts_energy(const void*, const void*, const void*, double, const Tile*, int, const DevBlock*, const void*,
+                      double, int, int, double*, hipStream_t);
 hipError_t lts_store(const double*, int, double*, hipStream_t);
-constexpr int kLtsGrid = 64;
 template <typename T> hipError_t launch_fused(const KArgs&, int, int, hipStream_t);
 hipError_t launch_sources(const KArgs&, hipStream_t);
 template <typename T>
@@ -1053,6 +1054,10 @@ sbp_status lts_lists(sbp_ctx* c) {
       !upload(c->d_nwg[0], gcap[0], gw[0]) || !upload(c->d_nwg[1], gcap[1], gw[1]) ||
       !upload(c->d_fwg[0], gcap[2], fw[0]) || !upload(c->d_fwg[1], gcap[3], fw[1]))
     return fail(c, SBP_ENOMEM, "local time stepping list allocation failed");
+  // energy partial sums: one per tile of the whole list
+  dfree(c, c->lts_part);
+  c->lts_part = (double*)dalloc(c, std::max<size_t>(c->bare.size(), 1) * sizeof(double));
+  if (!c->lts_part) return fail(c, SBP_ENOMEM, "local time stepping list allocation failed");
   c->nnear = (int)nt.size();
   c->nfar = (int)ft.size();
   for (int g = 0; g < 2; ++g) {
@@ -1853,12 +1858,12 @@ sbp_status sbp_lts_start(sbp_ctx* c, const int* refined, int nrefined, int subst
   c->lts_face = (double*)take(c->face_elems * sizeof(double));
   c->lts_st = (StepState*)take(sizeof(StepState));
   c->lts_ring = (double*)take(2 * sizeof(double));
-  c->lts_part = (double*)take((size_t)kLtsGrid * nb * sizeof(double));
+  c->lts_part = nullptr;  // sized with the tile list (lts_lists)
   c->lts_blocks = (DevBlock*)take((size_t)nb * sizeof(DevBlock));
   c->lts_cblocks = (DevBlock*)take((size_t)nb * sizeof(DevBlock));
   c->lts_boxes = (LtsBox*)take((size_t)nb * sizeof(LtsBox));
   if (!c->lts_s || (sub && (!c->lts_w || !c->lts_qa || !c->lts_qb || !c->lts_ep)) ||
-      (track && (!c->lts_x[0] || !c->lts_x[1])) || !c->lts_face || !c->lts_st || !c->lts_ring || !c->lts_part ||
+      (track && (!c->lts_x[0] || !c->lts_x[1])) || !c->lts_face || !c->lts_st || !c->lts_ring ||
       !c->lts_blocks || !c->lts_cblocks || !c->lts_boxes)
     return fail(c, SBP_ENOMEM, "local time stepping buffer allocation failed");
   // descriptors with a unit time step (one step of the scratch state applies
@@ -1914,10 +1919,8 @@ sbp_status sbp_lts_start(sbp_ctx* c, const int* refined, int nrefined, int subst
     if ((st = lts_apply(c, true)) != SBP_OK) return st;
     if (sub) HIPCHK(c, phase(4, -1, c->d_near, c->nnear));
     if (track)
-      HIPCHK(c, f64 ? lts_whole<double>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
-                                        0.0, nullptr, c->stream)
-                    : lts_whole<float>(1, nb, M, c->lts_x[1], nullptr, c->lts_s, dt_coarse, c->d_blocks, nullptr,
-                                       0.0, nullptr, c->stream));
+      HIPCHK(c, f64 ? lts_whole<double>(1, nb, M, c->lts_x[1], c->lts_s, dt_coarse, c->d_blocks, c->stream)
+                    : lts_whole<float>(1, nb, M, c->lts_x[1], c->lts_s, dt_coarse, c->d_blocks, c->stream));
     HIPCHK(c, hipMemsetAsync(c->lts_s, 0, pb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->lts_face, 0, c->face_elems * sizeof(double), c->stream));
   }
@@ -1945,11 +1948,16 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
                : lts_phase<float>(op, nmode, last, M, c->lts_s, c->lts_w, qm, qp, qo, c->lts_ep, tau2, dt, c->d_near,
                                   c->nnear, c->d_blocks, c->lts_boxes, threads, c->cz, c->stream);
   };
-  auto whole = [&](int op, const void* M, void* X, const void* Y, double d) {
-    return f64 ? lts_whole<double>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
-                                   c->stream)
-               : lts_whole<float>(op, nb, M, X, Y, nullptr, d, c->d_blocks, c->mat[0], kEps0, c->lts_part,
-                                  c->stream);
+  auto copy = [&](const void* M, void* X) {
+    return f64 ? lts_whole<double>(0, nb, M, X, nullptr, 0.0, c->d_blocks, c->stream)
+               : lts_whole<float>(0, nb, M, X, nullptr, 0.0, c->d_blocks, c->stream);
+  };
+  auto energy = [&](const void* M, const void* X, const void* Y) {
+    const double scale = 0.5 / (dt * dt);
+    return f64 ? lts_energy<double>(M, X, Y, scale, c->d_tiles_bare, c->ntiles, c->d_blocks, c->mat[0], kEps0,
+                                    threads, c->cz, c->lts_part, c->stream)
+               : lts_energy<float>(M, X, Y, scale, c->d_tiles_bare, c->ntiles, c->d_blocks, c->mat[0], kEps0,
+                                   threads, c->cz, c->lts_part, c->stream);
   };
   sbp_status st;
   // the scratch state of the first operator step: E = (I - P) E^n
@@ -1976,7 +1984,7 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
     }
     // copies of E^n for the energy of this step or the next
     const bool form = K > 0 && n % K == 0;
-    if (K > 0 && (form || (n + 1) % K == 0)) HIPCHK(c, whole(0, M, c->lts_x[n & 1], nullptr, 0.0));
+    if (K > 0 && (form || (n + 1) % K == 0)) HIPCHK(c, copy(M, c->lts_x[n & 1]));
     // the ordinary step of length dt on the blocks that are not refined
     KArgs a = ka;
     a.blocks = c->lts_cblocks;
@@ -1994,8 +2002,8 @@ sbp_status sbp_lts_step(sbp_ctx* c, long nsteps) {
     if (p > 1) HIPCHK(c, phase(3, s + 1 < nsteps ? 0 : -1, 0, M, nullptr, nullptr, nullptr));
     double* slot = ka.energy + (int)(n % ka.ecap);
     if (form) {
-      HIPCHK(c, whole(2, M, c->lts_x[(n + 1) & 1], c->lts_x[n & 1], 0.5 / (dt * dt)));
-      HIPCHK(c, lts_store(c->lts_part, kLtsGrid * nb, slot, c->stream));
+      HIPCHK(c, energy(M, c->lts_x[(n + 1) & 1], c->lts_x[n & 1]));
+      HIPCHK(c, lts_store(c->lts_part, c->ntiles, slot, c->stream));
     } else {
       HIPCHK(c, lts_store(c->lts_part, 0, slot, c->stream));
     }

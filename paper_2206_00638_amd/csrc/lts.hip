@@ -74,15 +74,15 @@ __global__ __launch_bounds__(256) void k_lts_phase(int op, int nmode, int last, 
   const Tile tl = tiles[blockIdx.x];
   const DevBlock& B = blocks[tl.block];
   const LtsBox bx = boxes[tl.block];
-  const long long sx = B.sx, sxy = B.sxy, csz = B.csz;
-  const long long plane = sx * (B.n[1] + 2);
+  const long long sxy = B.sxy, csz = B.csz;
+  const int sx = (int)B.sx, plane = sx * (B.n[1] + 2);
   const int nz2 = B.n[2] + 2;
   const T t2 = (T)tau2, tdt = (T)dt;
   for (int idx = threadIdx.x; idx < threads * cz; idx += blockDim.x) {
-    const long long q = tl.q0 + idx % threads;
+    const int q = tl.q0 + idx % threads;
     const int k = tl.z0 + idx / threads;
     if (q >= plane || k >= nz2) continue;
-    const int j = (int)(q / sx), i = (int)(q - j * sx);
+    const int j = q / sx, i = q - j * sx;
     const long long o = B.foff + q + sxy * k;
     const bool near = in_box(bx, i, j, k);
     for (int c = 0; c < 3; ++c) {
@@ -134,40 +134,49 @@ __global__ __launch_bounds__(256) void k_lts_phase(int op, int nmode, int last, 
 // Whole E parts of every block (grid row y = block):
 //   op 0: X = E (the pool)
 //   op 1: X = E - dt S  (E^{-1} = E^0 - dt A H^{-1/2}, S holding A H^{-1/2})
-//   op 2: energy W^{n+1/2} = sum M [(E^{n+1} - E^n)^2 + E^{n+1} (2 E^n - E^{n+1} - E^{n-1})] / (2 dt^2)
-//         from X = E^{n-1}, Y = E^n, the pool = E^{n+1}: fp64 per workgroup
-//         into partials[y * gridDim.x + x]
 template <typename T>
-__global__ __launch_bounds__(256) void k_lts_whole(int op, const T* pool, T* X, const T* Y, const T* S, double d,
-                                                  const DevBlock* blocks, const void* mat_eps, double eps0,
-                                                  double* partials) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(256) void k_lts_whole(int op, const T* pool, T* X, const T* S, double d,
+                                                  const DevBlock* blocks) {
   const DevBlock& B = blocks[blockIdx.y];
-  const long long csz = B.csz, sx = B.sx, sxy = B.sxy, plane = sx * (B.n[1] + 2);
-  double acc = 0.0;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * csz;
+  const T dd = (T)d;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * B.csz;
        t += (long long)gridDim.x * blockDim.x) {
     const long long e = B.foff + t;
-    if (op == 0) {
-      X[e] = pool[e];
-    } else if (op == 1) {
-      X[e] = pool[e] - (T)d * S[e];
-    } else {
-      const int c = (int)(t / csz);
-      const long long o = t - c * csz;
-      const int k = (int)(o / sxy);
-      const long long r = o - k * sxy;
-      const int j = (int)(r / sx), i = (int)(r - j * sx);
-      if (r < plane && e_valid(B, c, i, j, k)) {
-        const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
-        const double mw = eps0 * (0.25 * nc.S) * e_weight(B, c, i, j, k);
-        const double eo = (double)X[e], en = (double)Y[e], enew = (double)pool[e];
-        const double df = enew - en;
-        acc += mw * (df * df + enew * (2.0 * en - enew - eo));
-      }
+    X[e] = op == 0 ? pool[e] : pool[e] - dd * S[e];
+  }
+}
+
+// The energy W^{n+1/2} = sum M [(E^{n+1} - E^n)^2 + E^{n+1} (2 E^n - E^{n+1} - E^{n-1})] / (2 dt^2)
+// (M the E16 weights times eps) from X = E^{n-1}, Y = E^n and the pool's
+// E^{n+1}, over the nodes of a tile list (one workgroup per tile): fp64 per
+// workgroup into partials[blockIdx.x], times `scale`.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lts_energy(const T* pool, const T* X, const T* Y, double scale,
+                                                   const Tile* tiles, const DevBlock* blocks, const void* mat_eps,
+                                                   double eps0, int threads, int cz, double* partials) {
+  __shared__ double red[4];
+  const Tile tl = tiles[blockIdx.x];
+  const DevBlock& B = blocks[tl.block];
+  const long long sxy = B.sxy, csz = B.csz;
+  const int sx = (int)B.sx, plane = sx * (B.n[1] + 2);
+  const int nz2 = B.n[2] + 2;
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < threads * cz; idx += blockDim.x) {
+    const int q = tl.q0 + idx % threads;
+    const int k = tl.z0 + idx / threads;
+    if (q >= plane || k >= nz2) continue;
+    const int j = q / sx, i = q - j * sx;
+    const long long o = B.foff + q + sxy * k;
+    for (int c = 0; c < 3; ++c) {
+      if (!e_valid(B, c, i, j, k)) continue;
+      const long long e = o + c * csz;
+      const NodeCells nc = node_cells_t<T>(B, mat_eps, c, i, j, k);
+      const double mw = eps0 * (0.25 * nc.S) * e_weight(B, c, i, j, k);
+      const double eo = (double)X[e], en = (double)Y[e], enew = (double)pool[e];
+      const double df = enew - en;
+      acc += mw * (df * df + enew * (2.0 * en - enew - eo));
     }
   }
-  if (op != 2) return;
   acc = wave_sum(acc);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) red[wid] = acc;
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(256) void k_lts_whole(int op, const T* pool, T* X, 
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
-    partials[blockIdx.y * gridDim.x + blockIdx.x] = d * sum;
+    partials[blockIdx.x] = scale * sum;
   }
 }
 
@@ -198,7 +207,7 @@ __global__ __launch_bounds__(256) void k_lts_store(const double* partials, int n
 
 }  // namespace
 
-constexpr int kLtsGrid = 64;  // workgroups per block row of the whole-part kernel
+constexpr int kLtsGrid = 512;  // workgroups per block row of the copy kernel
 
 template <typename T>
 hipError_t lts_phase(int op, int nmode, int last, void* pool, void* S, void* Y, const void* Qm, const void* Qp,
@@ -211,10 +220,20 @@ hipError_t lts_phase(int op, int nmode, int last, void* pool, void* S, void* Y, 
 }
 
 template <typename T>
-hipError_t lts_whole(int op, int nblocks, const void* pool, void* X, const void* Y, const void* S, double d,
-                     const DevBlock* blocks, const void* mat_eps, double eps0, double* partials, hipStream_t s) {
+hipError_t lts_whole(int op, int nblocks, const void* pool, void* X, const void* S, double d, const DevBlock* blocks,
+                     hipStream_t s) {
   hipLaunchKernelGGL(k_lts_whole<T>, dim3(kLtsGrid, nblocks), dim3(256), 0, s, op, (const T*)pool, (T*)X,
-                     (const T*)Y, (const T*)S, d, blocks, mat_eps, eps0, partials);
+                     (const T*)S, d, blocks);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lts_energy(const void* pool, const void* X, const void* Y, double scale, const Tile* tiles, int ntiles,
+                      const DevBlock* blocks, const void* mat_eps, double eps0, int threads, int cz, double* partials,
+                      hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lts_energy<T>, dim3(ntiles), dim3(256), 0, s, (const T*)pool, (const T*)X, (const T*)Y, scale,
+                     tiles, blocks, mat_eps, eps0, threads, cz, partials);
   return hipGetLastError();
 }
 
@@ -227,8 +246,9 @@ hipError_t lts_store(const double* partials, int nparts, double* slot, hipStream
   template hipError_t lts_phase<T>(int, int, int, void*, void*, void*, const void*, const void*, void*, void*,       \
                                    double, double, const Tile*, int, const DevBlock*, const LtsBox*, int, int,       \
                                    hipStream_t);                                                                     \
-  template hipError_t lts_whole<T>(int, int, const void*, void*, const void*, const void*, double, const DevBlock*, \
-                                   const void*, double, double*, hipStream_t);
+  template hipError_t lts_whole<T>(int, int, const void*, void*, const void*, double, const DevBlock*, hipStream_t); \
+  template hipError_t lts_energy<T>(const void*, const void*, const void*, double, const Tile*, int, const DevBlock*, \
+                                    const void*, double, int, int, double*, hipStream_t);
 SBP_LTS_INST(float)
 SBP_LTS_INST(double)
 #undef SBP_LTS_INST
