@@ -465,6 +465,28 @@ def copy_ceiling():
             "note": "1 GiB fp32 arrays: device-to-device copy (1 read + 1 write) and c = a + b (2 reads + 1 write)"}
 
 
+def pattern_ceiling(h_ms, e_ms):
+    """The update kernels' own access patterns on the 256^3 node box (the
+    probe library: same loads, stores, tiles and tile walk, no closure rows,
+    energy or probes), timed in this process; the algorithmic bytes of the H
+    and E launches over the probe times give the pattern's attainable rate,
+    and the kernels' times over the probe times the cost of everything else."""
+    import ctypes
+    import os
+    from sbp_inputs import make_config
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2206_00638_amd",
+                                   "libsbppattern.so"))
+    out = (ctypes.c_double * 2)()
+    rc = lib.sbp_pattern_time(256, 128, 8, 50, out)
+    if rc != 0:
+        raise RuntimeError(f"pattern probe failed: HIP error {rc}")
+    hb, eb, _ = algorithmic_bytes(make_config(2), 4)
+    return {"h_pattern_ms": out[0], "e_pattern_ms": out[1],
+            "h_pattern_gbs": hb / (out[0] * 1e-3) / 1e9, "e_pattern_gbs": eb / (out[1] * 1e-3) / 1e9,
+            "h_kernel_over_pattern": h_ms / out[0], "e_kernel_over_pattern": e_ms / out[1],
+            "note": "128 threads x 8 planes, grouped tile walk; algorithmic bytes of the 256^3 H and E launches"}
+
+
 def host_cpu():
     """CPU model and the number of cores this process may use."""
     model = "unknown"
@@ -635,6 +657,7 @@ def main():
     if not args.no_lts:
         out["lts"] = lts_leg(min(args.steps, 500), max(args.warmup, 10))
     out["copy_ceiling"] = copy_ceiling()
+    out["pattern_ceiling"] = pattern_ceiling(h_ms, e_ms)
     if not args.no_cpml:
         out["cpml"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20))
     if not args.no_tfsf:

@@ -1,4 +1,6 @@
-"""Builds the HIP library libsbpfdtd.so in-tree for gfx950 (hipcc)."""
+"""Builds the HIP library libsbpfdtd.so in-tree for gfx950 (hipcc), and the
+access-pattern probe libsbppattern.so that the benchmark uses as a bandwidth
+reference (not loaded by the library)."""
 import os
 import subprocess
 import sys
@@ -8,6 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbpfdtd.so")
 SOURCES = ["api.hip", "step.hip", "adjoint.hip", "lts.hip"]
+PATTERN_LIB = os.path.join(HERE, "libsbppattern.so")
+PATTERN_SOURCES = ["pattern.hip"]
 ARCH = os.environ.get("SBP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -18,14 +22,19 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose=False):
+def _link(sources, lib, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    tmp = lib + ".tmp"
+    cmd = [hipcc] + HIPCC_FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    _link(SOURCES, LIB, verbose)
+    _link(PATTERN_SOURCES, PATTERN_LIB, verbose)
     return LIB
 
 
