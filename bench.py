@@ -678,6 +678,12 @@ def main():
     if not args.no_accuracy:
         out["accuracy"] = accuracy(4)
     out["paper"] = paper_context(prob)
+    pc = out["pattern_ceiling"]
+    out["paper"]["this_closure_rows_and_energy_overhead_pct"] = 100.0 * (
+        (h_ms + e_ms) / (pc["h_pattern_ms"] + pc["e_pattern_ms"]) - 1.0)
+    out["paper"]["this_overhead_note"] = (
+        "the 256^3 step's H and E launches against the same access pattern without the closure / SAT rows, "
+        "the energy sums and probes (pattern_ceiling); the paper's figure compares whole solvers")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
