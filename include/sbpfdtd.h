@@ -222,8 +222,9 @@ sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
  * steps n that K divides and NaN for the others (K = 0: NaN throughout);
  * forming it reads every E array twice more.  The context then holds E^n
  * (read with sbp_read_field) and steps only by sbp_lts_step: sbp_step,
- * sbp_step_static, sbp_save_state, sbp_load_state, sbp_set_fused,
- * sbp_autotune and sbp_adjoint return SBP_ESTATE.  Device memory for up to
+ * sbp_step_static, sbp_save_state, sbp_load_state, sbp_write_field,
+ * sbp_set_materials, sbp_set_fused, sbp_autotune and sbp_adjoint return
+ * SBP_ESTATE.  Device memory for up to
  * seven more field pools is taken at sbp_lts_start.  Errors: SBP_EINVAL for
  * substeps outside 1..64, a non-positive dt_coarse, a negative energy_every,
  * a bad refined block, a lossy block (conductivity, absorbing face or

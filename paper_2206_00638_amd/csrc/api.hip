@@ -1645,6 +1645,7 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
                              const double* sigma) {
   if (!c) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "set_materials before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (!check_block(c, block)) return fail(c, SBP_EINVAL, "bad block");
   HostBlock& b = c->blocks[block];
   const size_t nc = (size_t)b.n[0] * b.n[1] * b.n[2];
@@ -2066,6 +2067,7 @@ sbp_status sbp_read_field(sbp_ctx* c, int block, sbp_comp comp, double* dst, siz
 sbp_status sbp_write_field(sbp_ctx* c, int block, sbp_comp comp, const double* srcp, size_t count) {
   if (!c || !srcp) return SBP_EINVAL;
   if (!c->finalized) return fail(c, SBP_ESTATE, "write_field before finalize");
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
   if (!check_block(c, block) || comp < SBP_EX || comp > SBP_HZ) return fail(c, SBP_EINVAL, "bad block or component");
   int s[3];
   sbp_field_shape(c, block, comp, s);

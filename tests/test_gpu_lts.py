@@ -210,6 +210,8 @@ def test_lts_errors(sbp):
         assert status(lambda: ctx.lts_start([1], 2, dt)) == SBP_ESTATE
         assert status(lambda: ctx.step(1)) == SBP_ESTATE
         assert status(lambda: ctx.set_fused(1)) == SBP_ESTATE
+        assert status(lambda: ctx.write_field(1, "Ez", np.zeros(ctx.field_shape(1, "Ez")[::-1]))) == SBP_ESTATE
+        assert status(lambda: ctx.set_materials(0, eps_r=prob["blocks"][0]["eps_r"])) == SBP_ESTATE
         ctx.lts_step(2)
     finally:
         ctx.close()
