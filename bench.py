@@ -280,28 +280,22 @@ def subgrid(steps, warmup):
             "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
-def lts_leg(coarse_steps, warmup):
-    """Local time stepping on the subgrid geometry made lossless (27 blocks,
-    fp32): the refined block takes 2 substeps per coarse step of twice the
-    global step, the others the coarse step.  Timed beside the global
-    leapfrog of the same problem over the same physical time, from the same
-    seeded fields; the energy W^{n+1/2} over a run that forms it every step."""
+def _lts_case(prob, fine, coarse_steps, warmup, init_blocks):
+    """Global leapfrog against local time stepping (refined block substepped
+    twice per coarse step of twice the global step) on one problem, from the
+    same seeded fields in `init_blocks` (zero elsewhere); energy not formed."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
-    from sbp_inputs import lossless_subgrid
-    prob, fine = lossless_subgrid(1)
     cells = int(sum(np.prod(b["n"]) for b in prob["blocks"]))
 
     def fresh():
         rng = np.random.default_rng(7)
-        stream = torch.cuda.Stream()
-        ctx = build_problem(prob, prec="f32", stream=stream, history=2 * (coarse_steps + warmup) + 64)
-        for b, blk in enumerate(prob["blocks"]):
+        ctx = build_problem(prob, prec="f32", stream=torch.cuda.Stream(), history=2 * (coarse_steps + warmup) + 64)
+        for b in init_blocks:
             for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
                 shp = ctx.field_shape(b, c)
-                v = rng.standard_normal(shp[::-1]) * (1.0 if c[0] == "E" else 1.0 / 377.0)
-                ctx.write_field(b, c, v)
+                ctx.write_field(b, c, rng.standard_normal(shp[::-1]) * (1.0 if c[0] == "E" else 1.0 / 377.0))
         return ctx
 
     def timed(fn, n):
@@ -316,29 +310,60 @@ def lts_leg(coarse_steps, warmup):
     g.step(2 * warmup)
     ms_global = timed(g.step, 2 * coarse_steps)
     g.close()
-    rec = {"workload": prob["name"], "cells": cells, "refined_block": fine, "substeps": 2,
-           "dt_coarse_over_global": 2.0, "global_ms_per_step": ms_global}
-    for every in (0, 100):
-        c = fresh()
-        c.lts_start([fine], 2, 2.0 * dt, every)
-        c.lts_step(warmup)
-        ms = timed(c.lts_step, coarse_steps)
-        info = c.lts_info()
-        c.close()
-        rec["lts_ms_per_coarse_step" + ("" if every == 0 else f"_energy_every_{every}")] = ms
-    rec["near"] = info
-    rec["speedup_same_physical_time"] = 2.0 * ms_global / rec["lts_ms_per_coarse_step"]
-    rec["value"] = cells * 2.0 / (rec["lts_ms_per_coarse_step"] * 1e-3) / 1e6
-    rec["unit"] = "Mcell-updates/s of the global leapfrog covering the same physical time"
-    # W^{n+1/2} formed every coarse step over a shorter run
     c = fresh()
-    c.lts_start([fine], 2, 2.0 * dt, 1)
-    n = min(coarse_steps, 200)
-    c.lts_step(n)
-    w = c.read_energy(0, n)
+    c.lts_start([fine], 2, 2.0 * dt, 0)
+    c.lts_step(warmup)
+    ms = timed(c.lts_step, coarse_steps)
+    info = c.lts_info()
     c.close()
-    rec["energy_drift_fp32"] = float(np.abs(w / w[0] - 1.0).max())
-    rec["energy_steps"] = n
+    return {"workload": prob["name"], "cells": cells, "refined_block": fine,
+            "refined_cells_frac": float(np.prod(prob["blocks"][fine]["n"])) / cells, "substeps": 2,
+            "dt_coarse_over_global": 2.0, "global_ms_per_step": ms_global, "lts_ms_per_coarse_step": ms,
+            "near": info, "speedup_same_physical_time": 2.0 * ms_global / ms,
+            "value": cells * 2.0 / (ms * 1e-3) / 1e6,
+            "unit": "Mcell-updates/s of the global leapfrog covering the same physical time"}
+
+
+def lts_leg(coarse_steps, warmup):
+    """Local time stepping (lossless problems, fp32; the refined block takes 2
+    substeps per coarse step of twice the global step), timed beside the
+    global leapfrog over the same physical time: the subgrid geometry of
+    config 3 made lossless (the refined block 11% of the cells; seeded random
+    fields everywhere), with the cost of forming W^{n+1/2} every 100 steps
+    and its drift over a run that forms it every step; and a 384^3 coarse
+    region with a 24-cell refined cube at its centre (0.2% of the cells;
+    seeded random fields in the refined block)."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import embedded_refinement, lossless_subgrid
+    prob, fine = lossless_subgrid(1)
+    rec = _lts_case(prob, fine, coarse_steps, warmup, range(len(prob["blocks"])))
+    # the energy: every 100 steps (cost) and every step (drift)
+    rng = np.random.default_rng(7)
+    for every in (100, 1):
+        c = build_problem(prob, prec="f32", stream=torch.cuda.Stream(), history=2 * (coarse_steps + warmup) + 64)
+        for b in range(len(prob["blocks"])):
+            for comp in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+                shp = c.field_shape(b, comp)
+                c.write_field(b, comp, rng.standard_normal(shp[::-1]) * (1.0 if comp[0] == "E" else 1.0 / 377.0))
+        c.lts_start([fine], 2, 2.0 * c.dt, every)
+        if every == 100:
+            c.lts_step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.lts_step(coarse_steps)
+            torch.cuda.synchronize()
+            rec["lts_ms_per_coarse_step_energy_every_100"] = (time.perf_counter() - t0) * 1e3 / coarse_steps
+        else:
+            n = min(coarse_steps, 200)
+            c.lts_step(n)
+            w = c.read_energy(0, n)
+            rec["energy_drift_fp32"] = float(np.abs(w / w[0] - 1.0).max())
+            rec["energy_steps"] = n
+        c.close()
+    prob2, fine2 = embedded_refinement(384, 24)
+    rec["embedded_refinement"] = _lts_case(prob2, fine2, min(coarse_steps, 100), warmup, [fine2])
     return rec
 
 

@@ -277,5 +277,44 @@ def lossless_subgrid(scale=1):
             prob["fine_block"])
 
 
+def embedded_refinement(side=384, fine=24, h=1e-3):
+    """A lossless coarse cube of `side` cells (PEC outer faces) with a cube of
+    `fine` coarse cells at its centre refined 1:2: 27 blocks split
+    (side - fine)/2 + fine + (side - fine)/2 per axis, the refined block
+    holding 2 * fine cells per axis; no source or probe.  The shape of a
+    small subgridded region in a large domain (where local time stepping
+    pays).  Returns (problem, index of the refined block)."""
+    a = (side - fine) // 2
+    split = [a, fine, side - fine - a]
+    starts = [0, split[0], split[0] + split[1]]
+    blocks, index = [], {}
+    for c in range(3):
+        for b in range(3):
+            for a3 in range(3):
+                pos = (a3, b, c)
+                refined = pos == (1, 1, 1)
+                n = tuple((2 * split[pos[t]] if refined else split[pos[t]]) for t in range(3))
+                hh = h / 2 if refined else h
+                index[pos] = len(blocks)
+                blocks.append({"n": n, "h": (hh, hh, hh), "origin": tuple(starts[pos[t]] * h for t in range(3)),
+                               "eps_r": None, "mu_r": None, "sigma": None, "faces": ["pec"] * 6})
+    interfaces = []
+    for pos, ib in index.items():
+        for t in range(3):
+            nb = list(pos)
+            nb[t] += 1
+            if nb[t] > 2:
+                continue
+            jb = index[tuple(nb)]
+            if pos == (1, 1, 1):
+                interfaces.append((jb, 2 * t, ib, 2 * t + 1, 2))
+            elif tuple(nb) == (1, 1, 1):
+                interfaces.append((ib, 2 * t + 1, jb, 2 * t, 2))
+            else:
+                interfaces.append((ib, 2 * t + 1, jb, 2 * t, 1))
+    return ({"name": f"embedded-refinement-{side}^3-{fine}^3-1:2-fp32", "prec": "f32", "cfl": 0.9, "steps": 100,
+             "blocks": blocks, "interfaces": interfaces, "sources": [], "probes": []}, index[(1, 1, 1)])
+
+
 def make_config(k, scale=1):
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k](scale)

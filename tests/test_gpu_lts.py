@@ -228,3 +228,21 @@ def test_lts_errors(sbp):
             assert status(lambda: c2.lts_start([1], 2, c2.dt)) == SBP_EINVAL
         finally:
             c2.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lts_embedded_refinement_matches_oracle(sbp, prec):
+    """A 40-cell coarse cube with an 8-cell cube at its centre refined 1:2
+    (27 blocks; the near boxes take a few cells of 16-cell coarse blocks),
+    p = 2 at twice the global step, E and W^{n+1/2} against the oracle."""
+    from sbp_inputs import embedded_refinement
+    prob, fine = embedded_refinement(40, 8)
+    init = _init(prob, 41)
+    dt = 2.0 * S.cfl_dt(prob["blocks"], 0.9)
+    steps = 16
+    ref = T.run(prob, [fine], 2, steps, dt, init)
+    e, w = _gpu_lts(sbp, prob, prec, [fine], 2, dt, steps, init)
+    tol, own = _f32_bar(prob, [fine], 2, steps, dt, init, ref) if prec == "f32" else (TOL[prec], 0.0)
+    check_fields(e, _oracle_e(prob, ref["e"][-1]), prec,
+                 f"LTS embedded refinement 40/8, step {steps} (oracle's own fp32 rounding {own:.2e})", tol=tol)
+    assert rel_l2(w, ref["energy"]) < TOL[prec]
