@@ -246,3 +246,30 @@ def test_lts_embedded_refinement_matches_oracle(sbp, prec):
     check_fields(e, _oracle_e(prob, ref["e"][-1]), prec,
                  f"LTS embedded refinement 40/8, step {steps} (oracle's own fp32 rounding {own:.2e})", tol=tol)
     assert rel_l2(w, ref["energy"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lts_launch_change_midway_bitwise(sbp, prec):
+    """A launch shape changed between two sbp_lts_step calls rebuilds the
+    operator's tile lists (and clears the scratch state): E is bitwise the
+    same as without the change, and the coupled 1:2 pair with the refined
+    block on +y and a 3-substep recursion gives the same."""
+    prob = _pair(1, 7)
+    init = _init(prob, 8)
+    dt = 1.5 * S.cfl_dt(prob["blocks"], 0.9)
+    out = []
+    for change in (None, (64, 1, 3, 0), (256, 1, 11, 16)):
+        ctx = sbp.build_problem(prob, prec=prec, history=64)
+        try:
+            write_fields(ctx, init)
+            ctx.lts_start([1], 3, dt, 0)
+            ctx.lts_step(9)
+            if change:
+                ctx.set_launch(*change)
+            ctx.lts_step(12)
+            out.append({(b, c): ctx.read_field(b, c) for b in range(2) for c in E_COMPS})
+        finally:
+            ctx.close()
+    for got in out[1:]:
+        for k in out[0]:
+            assert np.array_equal(got[k], out[0][k]), k
