@@ -228,7 +228,7 @@ sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
  * seven more field pools is taken at sbp_lts_start.  Errors: SBP_EINVAL for
  * substeps outside 1..64, a non-positive dt_coarse, a negative energy_every,
  * a bad refined block, a lossy block (conductivity, absorbing face or
- * layer), periodic faces, sources, a TF/SF box or the one-pass step;
+ * layer), periodic faces, sources, probes, a TF/SF box or the one-pass step;
  * SBP_ESTATE before sbp_finalize or on a second sbp_lts_start. */
 sbp_status sbp_lts_start(sbp_ctx *ctx, const int *refined, int nrefined, int substeps, double dt_coarse,
                          long energy_every);

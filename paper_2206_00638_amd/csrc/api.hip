@@ -1823,6 +1823,7 @@ sbp_status sbp_lts_start(sbp_ctx* c, const int* refined, int nrefined, int subst
   if (nrefined < 0 || (nrefined > 0 && !refined)) return fail(c, SBP_EINVAL, "bad refined-block list");
   if (c->fused) return fail(c, SBP_EINVAL, "local time stepping takes the two-pass step (sbp_set_fused 0)");
   if (!c->srcs.empty() || c->tf_on) return fail(c, SBP_EINVAL, "local time stepping takes no sources or TF/SF box");
+  if (!c->prbs.empty()) return fail(c, SBP_EINVAL, "local time stepping records no probes (read the fields instead)");
   const int nb = (int)c->blocks.size();
   std::vector<int> flag(nb, 0);
   for (int q = 0; q < nrefined; ++q) {

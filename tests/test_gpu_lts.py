@@ -222,7 +222,9 @@ def test_lts_errors(sbp):
     src = _pair(0, 1)
     src["sources"] = [{"block": 0, "comp": "Ez", "node": (3, 3, 3), "waveform": "gauss", "tw": 1e-10, "t0": 3e-10,
                        "f0": 0.0, "amp": 1.0}]
-    for bad in (lossy, absorbing, src):
+    probe = _pair(0, 1)
+    probe["probes"] = [{"block": 1, "comp": "Ez", "node": (2, 2, 2)}]
+    for bad in (lossy, absorbing, src, probe):
         c2 = sbp.build_problem(bad, prec="f64", history=16)
         try:
             assert status(lambda: c2.lts_start([1], 2, c2.dt)) == SBP_EINVAL
