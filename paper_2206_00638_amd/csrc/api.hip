@@ -560,10 +560,11 @@ int grid_of(const sbp_ctx* c, int ntiles) {
 
 // Kind of a block for the step kernels: bit 0 = per-cell permittivity,
 // bit 1 = general (conductivity, absorbing faces, per-cell permeability,
-// interface faces or absorbing layers), bit 2 = interface or periodic faces
-// (the interface rows are compiled only into that variant), bit 3 = CPML
-// layers, bit 4 = the TF/SF box (its corrections are compiled only into
-// that variant); plain PEC/PMC blocks take the lean kernels.
+// absorbing layers or the TF/SF box), bit 2 = interface or periodic faces
+// (the interface rows are compiled only into those variants; without bit 1
+// the loss and absorbing terms are left out), bit 3 = CPML layers, bit 4 =
+// the TF/SF box (its corrections are compiled only into that variant);
+// plain PEC/PMC blocks take the lean kernels.
 bool has_pml(const HostBlock& b) {
   for (int f = 0; f < 6; ++f)
     if (b.iface[f] < 0 && b.faces[f] == SBP_CPML) return true;
@@ -574,7 +575,7 @@ int block_kind(const HostBlock& b) {
   bool gen = !b.mu.empty() || !b.sig.empty(), iface = false;
   for (int f = 0; f < 6; ++f) {
     iface = iface || b.iface[f] >= 0;
-    gen = gen || b.iface[f] >= 0 || b.faces[f] == SBP_ABC1;
+    gen = gen || b.faces[f] == SBP_ABC1;
   }
   const bool pml = has_pml(b);
   gen = gen || b.tfsf;
@@ -627,11 +628,21 @@ sbp_status build_tiles(sbp_ctx* c) {
   std::vector<Tile> tl;
   c->near_dirty = true;
   const int threads = c->tx * c->ty;
+  // lossless interface blocks take the lean interface kernels unless another
+  // block needs the general interface ones: then they join that kind, so that
+  // a half step stays one launch (two back-to-back launches cost more than
+  // the general terms the lossless blocks skip at run time)
+  bool gen_iface = false;
+  for (const HostBlock& b : c->blocks) gen_iface = gen_iface || (block_kind(b) & 6) == 6;
+  auto kind_of = [&](const HostBlock& b) {
+    const int k = block_kind(b);
+    return (gen_iface && (k & 30) == 4) ? (k | 2) : k;
+  };
   for (int kind = 0; kind < 32; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
-      if (block_kind(b) != kind) continue;
+      if (kind_of(b) != kind) continue;
       const long long sx = b.n[0] + 2, sxy = sx * (b.n[1] + 2);
       for (int z0 = 0; z0 < b.n[2] + 2; z0 += c->cz)
         for (long long q0 = 0; q0 < sxy; q0 += threads) {
@@ -820,7 +831,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* li
     return SBP_OK;
   };
   // kinds stepped by the two-pass kernels: all, or only the general ones
-  auto two_pass = [&](int kind) { return kt1[kind] > kt0[kind] && (!c->fused || (kind & 2)); };
+  auto two_pass = [&](int kind) { return kt1[kind] > kt0[kind] && (!c->fused || (kind & 6)); };
   if (c->njobs_e) {
     e = f64 ? launch_gather<double>(c->d_blocks, c->d_jobs_e, wg_e, nwg_e, c->d_taps, a, 0, face, c->stream)
             : launch_gather<float>(c->d_blocks, c->d_jobs_e, wg_e, nwg_e, c->d_taps, a, 0, face, c->stream);

@@ -1489,9 +1489,10 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 
 // ------------------------------------------------------------- launchers
 // kind bit 0: per-cell permittivity; bit 1: general block (loss, absorbing
-// faces, per-cell permeability, interfaces or absorbing layers); bit 2:
-// interface faces (periodic faces included); bit 3: absorbing layers.  Bits
-// 2 and 3 imply bit 1.
+// faces, per-cell permeability, absorbing layers or the TF/SF box); bit 2:
+// interface faces (periodic faces included); bit 3: absorbing layers; bit 4:
+// the TF/SF box.  Bits 3 and 4 imply bit 1; bit 2 alone (lossless interface
+// blocks) takes the interface rows without the general terms.
 template <typename T>
 hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
   const dim3 g(grid), b(threads);
@@ -1500,6 +1501,7 @@ hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t
     case 18: hipLaunchKernelGGL((k_h_update<T, true, false, false, true>), g, b, 0, s, a); break;
     case 26: hipLaunchKernelGGL((k_h_update<T, true, false, true, true>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_h_update<T, true, false, false>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_h_update<T, false, true, false>), g, b, 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_h_update<T, true, true, false>), g, b, 0, s, a); break;
     case 10: hipLaunchKernelGGL((k_h_update<T, true, false, true>), g, b, 0, s, a); break;
     default: hipLaunchKernelGGL((k_h_update<T, true, true, true>), g, b, 0, s, a); break;
@@ -1518,6 +1520,8 @@ hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t
     case 1: hipLaunchKernelGGL((k_e_update<T, true, false, false, false>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_e_update<T, false, true, false, false>), g, b, 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_e_update<T, true, true, false, false>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_e_update<T, false, false, true, false>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_e_update<T, true, false, true, false>), g, b, 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_e_update<T, false, true, true, false>), g, b, 0, s, a); break;
     case 7: hipLaunchKernelGGL((k_e_update<T, true, true, true, false>), g, b, 0, s, a); break;
     case 10: hipLaunchKernelGGL((k_e_update<T, false, true, false, true>), g, b, 0, s, a); break;
