@@ -45,11 +45,29 @@ def plain(block):
             and all(f in ("pec", "pmc") for f in block["faces"]))
 
 
+_TABLED = {}
+
+
+def tabled(block, elem):
+    """Whether the library holds the block's permittivity as byte indices
+    into a table: at most 64 distinct values in the field precision."""
+    eps = block.get("eps_r")
+    if eps is None:
+        return False
+    key = (id(eps), elem)
+    if key not in _TABLED:
+        import numpy as np
+        dt = np.float32 if elem == 4 else np.float64
+        _TABLED[key] = (eps, np.unique(np.asarray(eps, dtype=dt)).size <= 64)
+    return _TABLED[key][1]
+
+
 def algorithmic_bytes(problem, elem, fused=False):
     """Bytes each launch group must move per step: every node read once and
     written once per update, the other field read once (two passes) or both
-    fields read and written once (one pass), per-cell materials read once.
-    Returns (H pass, E pass, one pass)."""
+    fields read and written once (one pass), per-cell materials read once
+    (the permittivity of a plain block with at most 64 distinct values as one
+    byte per cell: its table index).  Returns (H pass, E pass, one pass)."""
     eb = hb = fb = 0
     iface = {a for (a, _, b, _, _) in problem.get("interfaces", [])} | \
         {b for (_, _, b, _, _) in problem.get("interfaces", [])}
@@ -61,7 +79,9 @@ def algorithmic_bytes(problem, elem, fused=False):
         if fused and plain(b) and q not in iface:
             fb += elem * (2 * ne + 2 * nh + e_mats * cells)
         else:
-            eb += elem * (2 * ne + nh + e_mats * cells)
+            tf = (problem.get("tfsf") or {}).get("block")
+            lean = plain(b) and q not in iface and tf != q and tabled(b, elem)
+            eb += elem * (2 * ne + nh + e_mats * cells) - ((elem - 1) * cells if lean else 0)
             hb += elem * (2 * nh + ne + h_mats * cells)
     return hb, eb, fb
 
@@ -495,20 +515,26 @@ def pattern_ceiling(h_ms, e_ms):
     probe library: same loads, stores, tiles and tile walk, no closure rows,
     energy or probes), timed in this process; the algorithmic bytes of the H
     and E launches over the probe times give the pattern's attainable rate,
-    and the kernels' times over the probe times the cost of everything else."""
+    and the kernels' times over the probe times the cost of everything else.
+    The stream probe keeps the E launch's bytes (six components and the
+    cells' permittivity table indices read, three components written in
+    place) without the neighbour reads: the rate that mix of streams reaches
+    on its own."""
     import ctypes
     import os
     from sbp_inputs import make_config
     lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2206_00638_amd",
                                    "libsbppattern.so"))
-    out = (ctypes.c_double * 2)()
+    out = (ctypes.c_double * 3)()
     rc = lib.sbp_pattern_time(256, 128, 8, 50, out)
     if rc != 0:
         raise RuntimeError(f"pattern probe failed: HIP error {rc}")
     hb, eb, _ = algorithmic_bytes(make_config(2), 4)
-    return {"h_pattern_ms": out[0], "e_pattern_ms": out[1],
+    return {"h_pattern_ms": out[0], "e_pattern_ms": out[1], "e_streams_ms": out[2],
             "h_pattern_gbs": hb / (out[0] * 1e-3) / 1e9, "e_pattern_gbs": eb / (out[1] * 1e-3) / 1e9,
+            "e_streams_gbs": eb / (out[2] * 1e-3) / 1e9,
             "h_kernel_over_pattern": h_ms / out[0], "e_kernel_over_pattern": e_ms / out[1],
+            "e_kernel_over_streams": e_ms / out[2],
             "note": "128 threads x 8 planes, grouped tile walk; algorithmic bytes of the 256^3 H and E launches"}
 
 

@@ -223,9 +223,9 @@ sbp_status sbp_steps_done(const sbp_ctx *ctx, long *n);
  * forming it reads every E array twice more.  The context then holds E^n
  * (read with sbp_read_field) and steps only by sbp_lts_step: sbp_step,
  * sbp_step_static, sbp_save_state, sbp_load_state, sbp_write_field,
- * sbp_set_materials, sbp_set_fused, sbp_autotune and sbp_adjoint return
- * SBP_ESTATE.  Device memory for up to
- * seven more field pools is taken at sbp_lts_start.  Errors: SBP_EINVAL for
+ * sbp_set_materials, sbp_set_fused, sbp_set_cell_tables, sbp_autotune and
+ * sbp_adjoint return SBP_ESTATE.  Device memory for up to seven more field
+ * pools is taken at sbp_lts_start.  Errors: SBP_EINVAL for
  * substeps outside 1..64, a non-positive dt_coarse, a negative energy_every,
  * a bad refined block, a lossy block (conductivity, absorbing face or
  * layer), periodic faces, sources, probes, a TF/SF box or the one-pass step;
@@ -296,6 +296,20 @@ sbp_status sbp_adjoint(sbp_ctx *ctx, int block, long nsteps, const int region[6]
  * than 2048 tiles of 8 planes. */
 sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
 sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
+
+/* Storage of the per-cell permittivity that the E update reads (E7-E9: Cb
+ * from the sum of the four cells around an E node).  A plain block (PEC /
+ * PMC faces, no conductivity, no per-cell permeability, no interfaces, no
+ * TF/SF box) whose cells take at most 64 distinct values in the field
+ * precision also holds them as one byte per cell, an index into a table of
+ * those values, and its E update reads the bytes (1 B per cell instead of 4
+ * (fp32) or 8 (fp64)) when the launch shape takes one workgroup per tile of
+ * 8 or more planes.  The values, and so every result, are the same either
+ * way.  enable != 0 (the default) tables the blocks that qualify, enable = 0
+ * keeps every block on the cell array.  Before or after sbp_finalize
+ * (afterwards the tile lists are rebuilt and a captured step graph is
+ * dropped); SBP_ESTATE under local time stepping. */
+sbp_status sbp_set_cell_tables(sbp_ctx *ctx, int enable);
 
 /* Selects how plain blocks (PEC / PMC faces, no conductivity, no per-cell
  * permeability, no interfaces) are stepped: enable != 0 runs both half steps

@@ -62,6 +62,7 @@ SIGNATURES = {
     "sbp_adjoint": [_P, _I, _L, _IP, _L, _DP, _P],
     "sbp_set_launch": [_P, _I, _I, _I, _I],
     "sbp_set_fused": [_P, _I, _I],
+    "sbp_set_cell_tables": [_P, _I],
     "sbp_get_launch": [_P, _IP],
     "sbp_autotune": [_P, _I, _DP],
     "sbp_use_graph": [_P, _I],
@@ -298,6 +299,9 @@ class Context:
 
     def set_launch(self, tx, ty, cz, workgroups=0):
         self._chk(self._lib.sbp_set_launch(self.h, tx, ty, cz, workgroups))
+
+    def set_cell_tables(self, enable):
+        self._chk(self._lib.sbp_set_cell_tables(self.h, int(bool(enable))))
 
     def set_fused(self, enable, planes=32):
         self._chk(self._lib.sbp_set_fused(self.h, int(bool(enable)), int(planes)))

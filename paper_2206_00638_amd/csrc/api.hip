@@ -58,6 +58,11 @@ constexpr double kMu0 = 4e-7 * kPi;
 constexpr double kC0 = 299792458.0;
 const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
 
+// Kernel kinds of a block (bit 0 per-cell permittivity, 1 general terms,
+// 2 interfaces, 3 absorbing layers, 4 TF/SF box, 5 tabled permittivity: set
+// by the tile lists for the launch shapes where it pays).
+constexpr int kKinds = 64;
+
 struct HostBlock {
   int n[3];
   double h[3], x0[3];
@@ -68,6 +73,9 @@ struct HostBlock {
   // the other part, and whether this block holds the imaginary part
   int part_of = -1, imag = 0;
   int tfsf = 0;  // holds the total-field / scattered-field box
+  // the per-cell permittivity takes at most kCellTab values (in the field
+  // precision): byte indices and a table are uploaded beside the cells
+  bool tabled = false;
 };
 
 // A coupled pair of faces.  Interfaces join two blocks; a periodic axis
@@ -114,6 +122,10 @@ struct sbp_ctx {
   void* pool2 = nullptr;
   size_t pool_elems = 0;
   void* mat[3] = {nullptr, nullptr, nullptr};
+  unsigned char* d_midx = nullptr;  // byte index per cell (tabled blocks)
+  void* d_mtab = nullptr;           // kCellTab values per block
+  size_t mtab_blocks = 0;
+  bool tables_off = false;  // sbp_set_cell_tables(ctx, 0)
   size_t ncells = 0;
   DevBlock* d_blocks = nullptr;
   std::vector<DevBlock> hblocks;
@@ -123,7 +135,7 @@ struct sbp_ctx {
   std::vector<FTile> fbare;
   size_t bare_cap = 0;
   int ntiles = 0;
-  int kind_t0[32] = {}, kind_t1[32] = {};  // tile ranges per block kind
+  int kind_t0[kKinds] = {}, kind_t1[kKinds] = {};  // tile ranges per block kind
   // one-pass step of the plain kinds (0, 1): tile list, ranges per kind
   int fused = 0, fz = 8;  // two passes by default: measured faster on the 256^3 workload
   // local time stepping (sbp_lts_start / sbp_lts_step): the scratch state on
@@ -152,7 +164,7 @@ struct sbp_ctx {
   Tile* d_far = nullptr;   // tiles of the blocks that are not refined (the ordinary step)
   size_t near_cap = 0, far_cap = 0;
   int nnear = 0, nfar = 0;
-  int nk_t0[32] = {}, nk_t1[32] = {}, fk_t0x[32] = {}, fk_t1x[32] = {};
+  int nk_t0[kKinds] = {}, nk_t1[kKinds] = {}, fk_t0x[kKinds] = {}, fk_t1x[kKinds] = {};
   GatherWG* d_nwg[2] = {nullptr, nullptr};  // gather workgroups whose face nodes meet a wider box (E, H)
   GatherWG* d_fwg[2] = {nullptr, nullptr};  // gather workgroups of faces between blocks that are not refined
   int nnwg[2] = {0, 0}, nfwg[2] = {0, 0};
@@ -493,6 +505,65 @@ void put_cells(std::vector<T>& dst, size_t off, const std::vector<double>& src) 
   for (size_t q = 0; q < src.size(); ++q) dst[off + q] = (T)src[q];
 }
 
+// A block's per-cell permittivity as byte indices into a table of at most
+// kCellTab values in the field precision (the very values the kernels would
+// read from the cell array, so results are unchanged); false if the cells
+// take more values.
+template <typename T>
+bool table_cells(const std::vector<double>& eps, unsigned char* idx, T* tab) {
+  int n = 0, li = -1;
+  T last = T(0);
+  for (size_t q = 0; q < eps.size(); ++q) {
+    const T v = (T)eps[q];
+    if (li < 0 || v != last) {
+      li = -1;
+      for (int e = 0; e < n && li < 0; ++e)
+        if (tab[e] == v) li = e;
+      if (li < 0) {
+        if (n == kCellTab) return false;
+        tab[n] = v;
+        li = n++;
+      }
+      last = v;
+    }
+    idx[q] = (unsigned char)li;
+  }
+  return true;
+}
+
+template <typename T>
+sbp_status upload_tables(sbp_ctx* c) {
+  const size_t nb = c->blocks.size();
+  std::vector<unsigned char> idx;
+  std::vector<T> tab(nb * kCellTab, T(1));
+  bool any = false;
+  size_t off = 0;
+  for (size_t bi = 0; bi < nb; ++bi) {
+    HostBlock& b = c->blocks[bi];
+    b.tabled = false;
+    if (!b.eps.empty() && !c->tables_off) {
+      if (idx.empty()) idx.assign(c->ncells, 0);
+      b.tabled = table_cells<T>(b.eps, idx.data() + off, tab.data() + bi * kCellTab);
+      any = any || b.tabled;
+    }
+    off += (size_t)b.n[0] * b.n[1] * b.n[2];
+  }
+  if (!any) return SBP_OK;
+  if (!c->d_midx) {
+    c->d_midx = (unsigned char*)dalloc(c, c->ncells);
+    if (!c->d_midx) return fail(c, SBP_ENOMEM, "material allocation failed");
+  }
+  if (!c->d_mtab) {
+    c->d_mtab = dalloc(c, nb * kCellTab * sizeof(T));
+    if (!c->d_mtab) return fail(c, SBP_ENOMEM, "material allocation failed");
+    c->mtab_blocks = nb;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_midx, idx.data(), idx.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_mtab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SBP_OK;
+}
+
 sbp_status upload_materials(sbp_ctx* c) {
   const bool fp64 = c->prec == SBP_FP64;
   for (int kind = 0; kind < 3; ++kind) {
@@ -529,6 +600,8 @@ sbp_status upload_materials(sbp_ctx* c) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
   }
+  const sbp_status ts = fp64 ? upload_tables<double>(c) : upload_tables<float>(c);
+  if (ts != SBP_OK) return ts;
   // flags per block
   for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
     const HostBlock& b = c->blocks[bi];
@@ -632,13 +705,21 @@ sbp_status build_tiles(sbp_ctx* c) {
   // block needs the general interface ones: then they join that kind, so that
   // a half step stays one launch (two back-to-back launches cost more than
   // the general terms the lossless blocks skip at run time)
+  // Plain blocks with a permittivity table take the tabled E kernel (kind
+  // bit 5) with one workgroup per tile of at least 8 planes: measured on the
+  // 256^3 dielectric block, the E launch gains 1.5% there, and loses 2.5%
+  // at 4 planes per tile and 17% with resident workgroups (2048 x 128
+  // threads), where the byte loads and table reads cost more than the bytes
+  // they save.
+  const bool tables = c->wgs == 0 && c->cz >= 8;
   bool gen_iface = false;
   for (const HostBlock& b : c->blocks) gen_iface = gen_iface || (block_kind(b) & 6) == 6;
   auto kind_of = [&](const HostBlock& b) {
     const int k = block_kind(b);
+    if (k == 1 && b.tabled && tables) return k | 32;
     return (gen_iface && (k & 30) == 4) ? (k | 2) : k;
   };
-  for (int kind = 0; kind < 32; ++kind) {
+  for (int kind = 0; kind < kKinds; ++kind) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
@@ -687,7 +768,7 @@ sbp_status build_tiles(sbp_ctx* c) {
     c->fk_t0[kind] = (int)ft.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
-      if (block_kind(b) != kind) continue;
+      if (block_kind(b) != kind) continue;  // the one-pass kernel reads the cells themselves
       std::vector<int> xs, xl, xh, ys, yl, yh, zl, zh;
       windows(b.n[0] + 2, b.n[0], FX, xs, xl, xh);
       windows(b.n[1] + 2, b.n[1], FY, ys, yl, yh);
@@ -725,7 +806,7 @@ sbp_status build_tiles(sbp_ctx* c) {
                              c->stream));
   }
   size_t sum = 0;
-  for (int kind = 0; kind < 32; ++kind)
+  for (int kind = 0; kind < kKinds; ++kind)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
   size_t fsum = 0;
   for (int kind = 0; kind < 2; ++kind)
@@ -766,6 +847,8 @@ KArgs kargs(sbp_ctx* c) {
   a.pool = c->pool;
   a.pool2 = c->pool2;
   a.mat_eps = c->mat[0];
+  a.mat_idx = c->d_midx;
+  a.mat_tab = c->d_mtab;
   a.mat_mu = c->mat[1];
   a.mat_sig = c->mat[2];
   a.face = c->d_face;
@@ -842,10 +925,10 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* li
   // partial sums: the H launches write slots [0, nh); each E workgroup adds
   // the H partial of its tile (same tile list and grid) to its own, so the
   // finish sums the E and one-pass slots [nh, nparts) only
-  int nparts = 0, hpoff[32];
+  int nparts = 0, hpoff[kKinds];
   for (int& v : hpoff) v = -1;
   a.hpoff = -1;
-  for (int kind = 0; kind < 32; ++kind) {
+  for (int kind = 0; kind < kKinds; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = kt0[kind];
     a.t1 = kt1[kind];
@@ -863,7 +946,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* li
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
-  for (int kind = 0; kind < 32; ++kind) {
+  for (int kind = 0; kind < kKinds; ++kind) {
     if (!two_pass(kind)) continue;
     a.t0 = kt0[kind];
     a.t1 = kt1[kind];
@@ -998,7 +1081,7 @@ std::vector<LtsBox> lts_boxes(const sbp_ctx* c, const std::vector<int>& refined,
 sbp_status lts_lists(sbp_ctx* c) {
   const int threads = c->tx * c->ty;
   std::vector<Tile> nt, ft;
-  for (int kind = 0; kind < 32; ++kind) {
+  for (int kind = 0; kind < kKinds; ++kind) {
     c->nk_t0[kind] = (int)nt.size();
     c->fk_t0x[kind] = (int)ft.size();
     for (int t = c->kind_t0[kind]; t < c->kind_t1[kind]; ++t) {
@@ -1668,6 +1751,7 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
   for (double x : m) if (!(x > 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "mu_r must be positive");
   for (double x : s) if (!(x >= 0) || !std::isfinite(x)) return fail(c, SBP_EINVAL, "sigma must be >= 0");
   const int kind_before = block_kind(b);
+  const bool tabled_before = b.tabled;
   b.eps.swap(e);
   b.mu.swap(m);
   b.sig.swap(s);
@@ -1676,7 +1760,7 @@ sbp_status sbp_set_materials(sbp_ctx* c, int block, const double* eps_r, const d
   if (st != SBP_OK) return st;
   // a block whose set of per-cell materials changed takes other kernels:
   // rebuild the tile lists (this also drops a captured graph)
-  if (block_kind(b) != kind_before) return build_tiles(c);
+  if (block_kind(b) != kind_before || b.tabled != tabled_before) return build_tiles(c);
   if (old[0] != c->mat[0] || old[1] != c->mat[1] || old[2] != c->mat[2]) drop_graph(c);
   return SBP_OK;
 }
@@ -1707,6 +1791,17 @@ sbp_status sbp_set_cpml(sbp_ctx* c, int cells, int order, double sigma_factor, d
   c->pml_kappa_max = kappa_max;
   c->pml_alpha_max = alpha_max;
   return SBP_OK;
+}
+
+sbp_status sbp_set_cell_tables(sbp_ctx* c, int enable) {
+  if (!c) return SBP_EINVAL;
+  if (c->lts) return fail(c, SBP_ESTATE, "the context steps by local time stepping (sbp_lts_step)");
+  c->tables_off = enable == 0;
+  if (!c->finalized) return SBP_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const sbp_status st = upload_materials(c);
+  if (st != SBP_OK) return st;
+  return build_tiles(c);  // blocks may change kind; this also drops a captured graph
 }
 
 sbp_status sbp_set_fused(sbp_ctx* c, int enable, int planes) {

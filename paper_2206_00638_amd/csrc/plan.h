@@ -22,6 +22,9 @@ struct Row {
 };
 
 // Rows of D+ held in the table: 0, 1, n-1, n.  Rows of D-: 0, 1, 2, n-1, n, n+1.
+// Plain blocks whose per-cell permittivity takes at most kCellTab distinct
+// values (in the field precision) hold a byte index per cell and a table.
+constexpr int kCellTab = 64;
 constexpr int DP_ROWS = 4;
 constexpr int DM_ROWS = 6;
 
@@ -167,6 +170,8 @@ struct KArgs {
   void* pool;   // field pools: step n reads pool (n even) or pool2 (n odd)
   void* pool2;  // and writes the other one
   const void* mat_eps;
+  const unsigned char* mat_idx;  // byte index per cell of the tabled blocks (kind bit 5)
+  const void* mat_tab;           // their tables: block b's kCellTab values at b * kCellTab
   const void* mat_mu;
   const void* mat_sig;
   const double* face;

@@ -873,6 +873,7 @@ struct EIn {
   T hz_yy, hx_yy;     // y rows of interface blocks: likewise
   double hz_fy, hx_fy;
   T e0a, e0b, e0c, e0d, e1a, e1b, e1c, e1d;
+  unsigned i1a, i1b, i1c, i1d;  // tabled permittivity: the plane's table indices, looked up when used
   T psi[6];  // absorbing layers: the node's recursion variables (slots 6-11)
 };
 
@@ -891,12 +892,25 @@ __device__ __forceinline__ ColCells col_cells(const BC<T>& c, int i, int j) {
   return ColCells{ci0 + (long long)nx * cj0, (long long)nx * ny, ci1 - ci0, (cj1 - cj0) * nx};
 }
 
-template <typename T, bool HAS_EPS>
+// Permittivity of a plane's four cells from the table indices loaded with it.
+template <typename T>
+__device__ __forceinline__ void e_cells(EIn<T>& v, const T* etab) {
+  v.e1a = etab[v.i1a];
+  v.e1b = etab[v.i1b];
+  v.e1c = etab[v.i1c];
+  v.e1d = etab[v.i1d];
+}
+
+// EIDX: the block's cells as byte indices (MI) into its table; the indices
+// stay in registers until the plane's other loads are needed too (a lookup
+// here would wait for the whole prefetch of the plane).
+template <typename T, bool HAS_EPS, bool EIDX = false>
 __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __restrict__ Ex,
                                        const T* __restrict__ Ey, const T* __restrict__ Ez,
                                        const T* __restrict__ Hz, const T* __restrict__ Hx,
                                        const T* __restrict__ Hy, const T* __restrict__ ME, const ColCells& q,
-                                       int i, int j, int k, long long o) {
+                                       int i, int j, int k, long long o,
+                                       const unsigned char* __restrict__ MI = nullptr) {
   const unsigned u = (unsigned)o;
   const unsigned uz = u + (k <= c.nz ? (unsigned)c.sxy : 0u), uy = u + (j <= c.ny ? (unsigned)c.sx : 0u),
                  ux = u + (i <= c.nx ? 1u : 0u);
@@ -915,12 +929,19 @@ __device__ __forceinline__ void e_load(EIn<T>& v, const BC<T>& c, const T* __res
     v.hz_xx = ld32(Hz, u + (unsigned)xd);
     v.hy_xx = ld32(Hy, u + (unsigned)xd);
   }
-  if (HAS_EPS) {  // ME: the block's cells; q.A relative to them
+  if (HAS_EPS) {  // ME (MI): the block's cells; q.A relative to them
     const unsigned p1 = (unsigned)(q.A + q.cp * clampi(k, 0, c.nz - 1));
-    v.e1a = ld32(ME, p1);
-    v.e1b = ld32(ME, p1 + (unsigned)q.dx);
-    v.e1c = ld32(ME, p1 + (unsigned)q.dy);
-    v.e1d = ld32(ME, p1 + (unsigned)(q.dx + q.dy));
+    if constexpr (EIDX) {
+      v.i1a = MI[p1];
+      v.i1b = MI[p1 + (unsigned)q.dx];
+      v.i1c = MI[p1 + (unsigned)q.dy];
+      v.i1d = MI[p1 + (unsigned)(q.dx + q.dy)];
+    } else {
+      v.e1a = ld32(ME, p1);
+      v.e1b = ld32(ME, p1 + (unsigned)q.dx);
+      v.e1c = ld32(ME, p1 + (unsigned)q.dy);
+      v.e1d = ld32(ME, p1 + (unsigned)(q.dx + q.dy));
+    }
   }
 }
 
@@ -1040,9 +1061,15 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   T cax = T(1), cay = T(1), caz = T(1), cbx, cby, cbz;
   if (HAS_EPS) {
     const T dte0x4 = c.dte0x4;
-    cbx = dte0x4 / mx;
-    cby = dte0x4 / my;
-    cbz = dte0x4 / mz;
+    if constexpr (sizeof(T) == 4 && !GEN) {
+      cbx = dte0x4 * __builtin_amdgcn_rcpf(mx);
+      cby = dte0x4 * __builtin_amdgcn_rcpf(my);
+      cbz = dte0x4 * __builtin_amdgcn_rcpf(mz);
+    } else {
+      cbx = dte0x4 / mx;
+      cby = dte0x4 / my;
+      cbz = dte0x4 / mz;
+    }
   } else {
     cbx = cby = cbz = c.cb_u;
   }
@@ -1101,7 +1128,12 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   onz = nez;
   // norm weights / h: 1 inside, Appendix P+ / P- on the boundary rows
   const T kxy = vz ? (T)wp1(nz, k) : T(0), kz = (T)wm1(nz, k);
-  return (lw.x * kxy) * mx * (ex * ex) + (lw.y * kxy) * my * (ey * ey) + (lw.z * kz) * mz * (ez * ez);
+  {
+    // rounded product by product, so that the value does not depend on
+    // which kernel variant the compiler fuses into multiply-adds
+#pragma clang fp contract(off)
+    return (lw.x * kxy) * mx * (ex * ex) + (lw.y * kxy) * my * (ey * ey) + (lw.z * kz) * mz * (ez * ez);
+  }
 }
 
 // E step over the tiles [t0, t1) of the tile list (one kind of block): each
@@ -1110,17 +1142,36 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // loads anyway), to the H partial of the same tile from the H launch; the
 // finish kernel then writes W^n to energy slot n and advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
-template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML, bool TF = false>
-__global__ __launch_bounds__(256) void k_e_update(KArgs a) {
+// EIDX: plain blocks with per-cell permittivity whose cells take at most
+// kCellTab values read one byte per cell and look the value up in the
+// block's table.  Each wave keeps its own copy of the table in LDS, written
+// by its 64 lanes whenever its tile changes block (before any lane leaves
+// the tile) and read back by the same wave: LDS operations of one wave
+// complete in order, so no workgroup barrier holds the other waves.
+template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML, bool TF = false, bool EIDX = false>
+__global__ __launch_bounds__(256, (EIDX && sizeof(T) == 4) ? 5 : 1) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
   const void* pin = pool_in(a, nstep);
   void* pout = pool_out(a, nstep);
+  static_assert(kCellTab == 64, "one table entry per lane of a wave64");
+  __shared__ T wtabs[EIDX ? 4 : 1][EIDX ? kCellTab : 1];  // one table per wave (at most 256 threads)
+  T* etab = wtabs[EIDX ? (threadIdx.x >> 6) : 0];
+  int tab_block = -1;
   TileIter it(a.t1 - a.t0, a.order);
   for (int tv; it.next(tv);) {
     const int t = __builtin_amdgcn_readfirstlane(tv) + a.t0;
     const SBP_CONST Tile& tl = as_const(a.tiles)[t];
     const int tb = tl.block, tq0 = tl.q0, tz0 = tl.z0, tflags = tl.pad;
+    if constexpr (EIDX) {
+      if (tb != tab_block) {  // uniform: the workgroup walks one tile sequence
+        etab[threadIdx.x & 63] = ((const T*)a.mat_tab)[(long long)tb * kCellTab + (threadIdx.x & 63)];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        tab_block = tb;
+      }
+    }
     const DevBlock& B = a.blocks[tb];
     const SBP_CONST DevBlock& Bc = as_const(a.blocks)[tb];
     const BC<T> c(Bc);
@@ -1128,7 +1179,8 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     const T* base = (const T*)pin + Bc.foff;  // E^n
     T* bout = (T*)pout + Bc.foff;             // H^{n+1/2} (read), E^{n+1} (written)
     const long long csz = Bc.csz;
-    const T* ME = HAS_EPS ? (const T*)a.mat_eps + Bc.coff : nullptr;  // the block's permittivity cells
+    const T* ME = (HAS_EPS && !EIDX) ? (const T*)a.mat_eps + Bc.coff : nullptr;  // the block's permittivity cells
+    const unsigned char* MI = EIDX ? a.mat_idx + Bc.coff : nullptr;             // or their table indices
     const T* MS = (GEN && (c.mat & MAT_SIG)) ? (const T*)a.mat_sig : nullptr;
     const int q = tq0 + (int)threadIdx.x;
     if (q >= (int)c.sx * (c.ny + 2)) continue;
@@ -1154,13 +1206,20 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     cur.hx = Hx[o];
     cur.hy = Hy[o];
     if (HAS_EPS) {
-      const T* p0 = ME + cc.A + cc.cp * clampi(k0 - 1, 0, c.nz - 1);
-      cur.e0a = p0[0];
-      cur.e0b = p0[cc.dx];
-      cur.e0c = p0[cc.dy];
-      cur.e0d = p0[cc.dx + cc.dy];
+      const unsigned p0 = (unsigned)(cc.A + cc.cp * clampi(k0 - 1, 0, c.nz - 1));
+      if constexpr (EIDX) {
+        cur.e0a = etab[MI[p0]];
+        cur.e0b = etab[MI[p0 + (unsigned)cc.dx]];
+        cur.e0c = etab[MI[p0 + (unsigned)cc.dy]];
+        cur.e0d = etab[MI[p0 + (unsigned)(cc.dx + cc.dy)]];
+      } else {
+        cur.e0a = ME[p0];
+        cur.e0b = ME[p0 + (unsigned)cc.dx];
+        cur.e0c = ME[p0 + (unsigned)cc.dy];
+        cur.e0d = ME[p0 + (unsigned)(cc.dx + cc.dy)];
+      }
     }
-    e_load<T, HAS_EPS>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o);
+    e_load<T, HAS_EPS, EIDX>(cur, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k0, o, MI);
     if (IFACE && rx.nbr) e_face<T>(a, c, fc, k0, cur);
     if (IFACE && !ry.in) e_yrow<T>(a, c, fc, ry, Hz, Hx, j, k0, o, cur);
     if constexpr (PML) psi_load<T, true>(a, Bc, pc, k0, o, cur.psi);
@@ -1169,18 +1228,19 @@ __global__ __launch_bounds__(256) void k_e_update(KArgs a) {
     for (int k = k0; k < k1; ++k, o += c.sxy) {
       EIn<T> nxt;
       if (k + 1 < k1) {  // next plane first: its loads overlap this plane's arithmetic
-        nxt.hx = cur.hx_z;
-        nxt.hy = cur.hy_z;
-        nxt.e0a = cur.e1a;
-        nxt.e0b = cur.e1b;
-        nxt.e0c = cur.e1c;
-        nxt.e0d = cur.e1d;
-        e_load<T, HAS_EPS>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy);
+        e_load<T, HAS_EPS, EIDX>(nxt, c, Ex, Ey, Ez, Hz, Hx, Hy, ME, cc, i, j, k + 1, o + c.sxy, MI);
         if (IFACE && rx.nbr) e_face<T>(a, c, fc, k + 1, nxt);
         if (IFACE && !ry.in) e_yrow<T>(a, c, fc, ry, Hz, Hx, j, k + 1, o + c.sxy, nxt);
         if constexpr (PML) psi_load<T, true>(a, Bc, pc, k + 1, o + c.sxy, nxt.psi);
         if (TF && (tflags & 4)) tf_gather<true>(a, i, j, k + 1, tnxt);
       }
+      if constexpr (EIDX) e_cells(cur, etab);  // this plane's cells, their indices loaded with the plane
+      nxt.hx = cur.hx_z;  // carried to the next plane
+      nxt.hy = cur.hy_z;
+      nxt.e0a = cur.e1a;
+      nxt.e0b = cur.e1b;
+      nxt.e0c = cur.e1c;
+      nxt.e0d = cur.e1d;
       T jx = T(0), jy = T(0), jz = T(0);
       if (tflags & 1) source_terms<T>(a, B, i, j, k, jx, jy, jz);
       if (TF && (tflags & 4)) tf_combine<true, T>(a, Bc, tcur, jx, jy, jz);
@@ -1491,8 +1551,10 @@ __global__ __launch_bounds__(256) void k_face_gather(const DevBlock* blocks, con
 // kind bit 0: per-cell permittivity; bit 1: general block (loss, absorbing
 // faces, per-cell permeability, absorbing layers or the TF/SF box); bit 2:
 // interface faces (periodic faces included); bit 3: absorbing layers; bit 4:
-// the TF/SF box.  Bits 3 and 4 imply bit 1; bit 2 alone (lossless interface
-// blocks) takes the interface rows without the general terms.
+// the TF/SF box; bit 5: permittivity cells held as byte indices into the
+// block's table (plain blocks only: kind 33).  Bits 3 and 4 imply bit 1; bit
+// 2 alone (lossless interface blocks) takes the interface rows without the
+// general terms.
 template <typename T>
 hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
   const dim3 g(grid), b(threads);
@@ -1511,6 +1573,10 @@ hipError_t launch_h(const KArgs& a, int kind, int grid, int threads, hipStream_t
 template <typename T>
 hipError_t launch_e(const KArgs& a, int kind, int grid, int threads, hipStream_t s) {
   const dim3 g(grid), b(threads);
+  if (kind == 33) {  // plain, per-cell permittivity from a table
+    hipLaunchKernelGGL((k_e_update<T, true, false, false, false, false, true>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
   switch (kind & 31) {
     case 0: hipLaunchKernelGGL((k_e_update<T, false, false, false, false>), g, b, 0, s, a); break;
     case 18: hipLaunchKernelGGL((k_e_update<T, false, true, false, false, true>), g, b, 0, s, a); break;

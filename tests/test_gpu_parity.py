@@ -544,6 +544,46 @@ def test_set_materials_changes_block_kind(sbp):
         b.close()
 
 
+def _tables_run(sbp, prob, prec, steps, tables, launch=None, switch_at=None):
+    ctx = sbp.build_problem(prob, prec=prec, launch=launch)
+    ctx.set_cell_tables(tables)
+    if switch_at is not None:
+        ctx.step(switch_at)
+        ctx.set_cell_tables(not tables)
+        ctx.step(steps - switch_at)
+    else:
+        ctx.step(steps)
+    nb = len(prob["blocks"])
+    out = {(b, c): ctx.read_field(b, c) for b in range(nb) for c in COMPS}
+    out["probes"] = np.array([ctx.read_probe(p, 0, steps) for p in range(len(prob.get("probes", [])))])
+    out["energy"] = ctx.read_energy(0, steps)
+    ctx.close()
+    return out
+
+
+def test_cell_tables_equal_cell_arrays(sbp):
+    """A plain block whose permittivity takes at most 64 values reads it as a
+    byte per cell indexing a table of the values (with one workgroup per tile
+    of 8 or more planes); every result equals the run that reads the cell
+    array, bitwise: the 32^3 dielectric-boxes block (33 values) in fp64 and
+    fp32 at two launch shapes, and 16 cavities with tables of their own (five
+    values each, 65 in all), once with the storage switched midway."""
+    from sbp_inputs import make_config
+    from sbp_inputs.configs import config4
+    boxes = make_config(2, scale=8)
+    cav = config4(scale=4, ncav=16)
+    assert len(np.unique(np.concatenate([np.unique(b["eps_r"]) for b in cav["blocks"]]))) > 64
+    cases = ((boxes, ("f64", "f32"), (128, 1, 8, 0), 60), (boxes, ("f32",), (256, 1, 16, 0), 60),
+             (cav, ("f32",), (128, 1, 8, 0), 40))
+    for prob, precs, launch, steps in cases:
+        for prec in precs:
+            ref = _tables_run(sbp, prob, prec, steps, False, launch)
+            for switch in (None, steps // 2):
+                got = _tables_run(sbp, prob, prec, steps, True, launch, switch)
+                for k in ref:
+                    assert np.array_equal(got[k], ref[k]), (prob["name"], prec, launch, switch, k)
+
+
 # ---------------------------------------------------------------- errors
 def test_error_statuses(sbp):
     from paper_2206_00638_amd.binding import SBP_EINVAL, SBP_ESTATE, SBP_EUNSTABLE, SBP_ERANGE, Context, SbpError
