@@ -153,6 +153,15 @@ struct TileIter {
   }
 };
 
+// Material coefficients q / d (Cb, Db and the loss factors; d >= 1 times
+// a positive constant): fp32 multiplies by the hardware reciprocal (within
+// 1 ulp of 1/d, so within 2 ulp of the quotient), fp64 divides.
+template <typename T>
+__device__ __forceinline__ T quot(T q, T d) {
+  if constexpr (sizeof(T) == 4) return q * __builtin_amdgcn_rcpf(d);
+  else return q / d;
+}
+
 // ------------------------------------------------------------- rows
 // One row of D+ or D- along an axis at node index r, coefficients in the
 // field precision: interior rows are flagged (two-point difference), closure
@@ -709,9 +718,9 @@ __device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP
     my = T(0.5) * (A0 + M[c0 + (long long)(cj1 - cj0) * nx]);
     mz = T(0.5) * (A0 + M[c.coff + ci0 + (long long)nx * cj0 + cp * clampi(k, 0, nz - 1)]);
     const T dtm0x2 = c.dtm0x2;
-    dbx = dtm0x2 / (mx + mx);
-    dby = dtm0x2 / (my + my);
-    dbz = dtm0x2 / (mz + mz);
+    dbx = quot(dtm0x2, mx + mx);
+    dby = quot(dtm0x2, my + my);
+    dbz = quot(dtm0x2, mz + mz);
   }
   T chx = dzEy - dyEz, chy = dxEz - dzEx, chz = dyEx - dxEy;
   if constexpr (TF) {  // TF/SF corrections (zero off the box surface)
@@ -1061,15 +1070,9 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
   T cax = T(1), cay = T(1), caz = T(1), cbx, cby, cbz;
   if (HAS_EPS) {
     const T dte0x4 = c.dte0x4;
-    if constexpr (sizeof(T) == 4 && !GEN) {
-      cbx = dte0x4 * __builtin_amdgcn_rcpf(mx);
-      cby = dte0x4 * __builtin_amdgcn_rcpf(my);
-      cbz = dte0x4 * __builtin_amdgcn_rcpf(mz);
-    } else {
-      cbx = dte0x4 / mx;
-      cby = dte0x4 / my;
-      cbz = dte0x4 / mz;
-    }
+    cbx = quot(dte0x4, mx);
+    cby = quot(dte0x4, my);
+    cbz = quot(dte0x4, mz);
   } else {
     cbx = cby = cbz = c.cb_u;
   }
@@ -1105,14 +1108,14 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
         if (gEz != T(0)) sz4 += T(8) * gEz / sqrt(me0 * muz / mz);
       }
       const T hdte0 = c.hdte0, dte0x4 = c.dte0x4;
-      const T bx = hdte0 * sx4 / mx, by = hdte0 * sy4 / my, bz = hdte0 * sz4 / mz;
-      const T rxx = T(1) / (T(1) + bx), ryy = T(1) / (T(1) + by), rzz = T(1) / (T(1) + bz);
+      const T bx = quot(hdte0 * sx4, mx), by = quot(hdte0 * sy4, my), bz = quot(hdte0 * sz4, mz);
+      const T rxx = quot(T(1), T(1) + bx), ryy = quot(T(1), T(1) + by), rzz = quot(T(1), T(1) + bz);
       cax = (T(1) - bx) * rxx;
       cay = (T(1) - by) * ryy;
       caz = (T(1) - bz) * rzz;
-      cbx = dte0x4 / mx * rxx;
-      cby = dte0x4 / my * ryy;
-      cbz = dte0x4 / mz * rzz;
+      cbx = quot(dte0x4, mx) * rxx;
+      cby = quot(dte0x4, my) * ryy;
+      cbz = quot(dte0x4, mz) * rzz;
     }
   }
   const T nex = cax * ex + cbx * (cx + jx);
@@ -1444,9 +1447,9 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
             mx = (q0a + q0c) + (q1a + q1c);
             my = (q0a + q0b) + (q1a + q1b);
             mz = (q0a + q0b) + (q0c + q0d);
-            cbx = c.dte0x4 / mx;
-            cby = c.dte0x4 / my;
-            cbz = c.dte0x4 / mz;
+            cbx = quot(c.dte0x4, mx);
+            cby = quot(c.dte0x4, my);
+            cbz = quot(c.dte0x4, mz);
           } else {
             cbx = cby = cbz = c.cb_u;
           }
