@@ -1145,6 +1145,15 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // loads anyway), to the H partial of the same tile from the H launch; the
 // finish kernel then writes W^n to energy slot n and advances the step
 // index.  GEN: loss, absorbing faces, per-cell permeability or interfaces.
+// Waves per SIMD the E kernels are held to (1: no bound): the tabled fp32
+// variant would take 97 VGPRs (4 waves) unbounded and fits 5 waves in 95.
+// (The plain fp64 variants take 141-143 VGPRs, 3 waves; held to 4 they
+// spill 12-20 B per lane and run 1% slower.)
+template <typename T, bool GENERAL, bool EIDX>
+constexpr int e_waves() {
+  return (!GENERAL && EIDX && sizeof(T) == 4) ? 5 : 1;
+}
+
 // EIDX: plain blocks with per-cell permittivity whose cells take at most
 // kCellTab values read one byte per cell and look the value up in the
 // block's table.  Each wave keeps its own copy of the table in LDS, written
@@ -1152,7 +1161,7 @@ __device__ __forceinline__ T e_node(const KArgs& a, const DevBlock& B, const SBP
 // the tile) and read back by the same wave: LDS operations of one wave
 // complete in order, so no workgroup barrier holds the other waves.
 template <typename T, bool HAS_EPS, bool GEN, bool IFACE, bool PML, bool TF = false, bool EIDX = false>
-__global__ __launch_bounds__(256, (EIDX && sizeof(T) == 4) ? 5 : 1) void k_e_update(KArgs a) {
+__global__ __launch_bounds__(256, (e_waves<T, (GEN || IFACE || PML || TF), EIDX>())) void k_e_update(KArgs a) {
   double eacc = 0.0;
   const long long nstep = a.st->step;
   const void* pin = pool_in(a, nstep);
