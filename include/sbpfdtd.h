@@ -292,8 +292,8 @@ sbp_status sbp_adjoint(sbp_ctx *ctx, int block, long nsteps, const int region[6]
  * node per thread and run; `workgroups` resident workgroups loop over the
  * tile list (0 = one workgroup per tile).  tx*ty must be 64, 128 or 256;
  * 1 <= cz <= 1024.  Without this call (or sbp_autotune) the shape is
- * 128, 1, 8, 0, with 4 planes per tile instead when the blocks give fewer
- * than 2048 tiles of 8 planes. */
+ * 128, 1, 8, 0, with fewer planes per tile when the blocks give few tiles of
+ * 8 planes: 4 below 2048 such tiles, 2 below 512 and 1 below 160. */
 sbp_status sbp_set_launch(sbp_ctx *ctx, int tx, int ty, int cz, int workgroups);
 sbp_status sbp_get_launch(const sbp_ctx *ctx, int out[4]);
 

@@ -1718,15 +1718,19 @@ sbp_status sbp_finalize(sbp_ctx* c, double cfl, int force, long history, double*
   sbp_status st = upload_materials(c);
   if (st != SBP_OK) return st;
   if (!c->launch_set) {
-    // small problems: fewer than 2048 tiles of 8 planes leave CUs idle, and
-    // tiles of 4 planes fill them (96^3 step 27 -> 22 us); 2 planes per tile
-    // cost more in per-tile set-up than they gain
+    // small problems: few tiles of 8 planes leave CUs idle, and a thread's
+    // march through its planes is a chain of load latencies; shorter tiles
+    // fill the chip.  Measured (graph-replayed us per step; 1 / 2 / 4 / 8
+    // planes at 128 threads): 16^3 fp64 11.5 / 13.6 / 18.2 / -, 40^3
+    // 11.2 / 12.5 / 14.3 / 23.2 (84 tiles of 8 planes), 56^3 13.1 / 12.9 /
+    // 15.2 / 19.7 (216), 72^3 17.5 / 15.2 / 17.2 / 22.9 (430), 80^3 20.1 /
+    // 17.1 / 17.0 / 21.9 (583), 96^3 30.5 / 24.1 / 21.7 / 27 (988)
     long long tiles = 0;
     for (const HostBlock& b : c->blocks) {
       const long long sxy = (long long)(b.n[0] + 2) * (b.n[1] + 2);
       tiles += (sxy + c->tx * c->ty - 1) / (c->tx * c->ty) * ((b.n[2] + 2 + c->cz - 1) / c->cz);
     }
-    if (tiles < 2048 && c->cz == 8) c->cz = 4;
+    if (c->cz == 8) c->cz = tiles < 160 ? 1 : (tiles < 512 ? 2 : (tiles < 2048 ? 4 : 8));
   }
   st = build_tiles(c);
   if (st != SBP_OK) return st;
@@ -2349,7 +2353,7 @@ sbp_status sbp_autotune(sbp_ctx* c, int steps_per_trial, double* best_ms) {
   // threads per tile x planes per tile, one workgroup per tile; then the
   // kept shape with resident workgroups looping over the tile list
   const int ths[3] = {64, 128, 256};
-  const int czs[4] = {2, 4, 8, 16};
+  const int czs[5] = {1, 2, 4, 8, 16};
   for (int t : ths)
     for (int cz : czs) cand.push_back({t, 1, cz, 0});
   cand.push_back({keep[0], keep[1], keep[2], dev_cus * 8});

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void k_sources(KArgs a) { eval_sources(a, a.st
 // source values of step n+1.
 __global__ __launch_bounds__(1024) void k_finish(KArgs a, int p0, int nparts) {
   __shared__ double red[16];
+  const long long n = a.st->step;  // read first: the source values below need it, not the partials
   if (a.tf) {
     // the TF/SF incident line, stepped one half step ahead of the 3D fields:
     // E^{n+1} with the source value of step n (at (n + 1/2) dt), then
@@ -98,12 +99,11 @@ __global__ __launch_bounds__(1024) void k_finish(KArgs a, int p0, int nparts) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] += a.partials[p + u * nb];
   for (; p < nparts; p += nb) acc[0] += a.partials[p];
+  eval_sources(a, n + 1);  // its arithmetic overlaps the partials' loads
   double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane == 0) red[wid] = s;
-  const long long n = a.st->step;
-  eval_sources(a, n + 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
