@@ -344,8 +344,10 @@ class Context:
             pass
 
 
-def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, force=False, stream=None):
-    """Creates and finalizes a Context from a problem dict (see sbp_inputs)."""
+def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, force=False, stream=None,
+                  cell_tables=None):
+    """Creates and finalizes a Context from a problem dict (see sbp_inputs);
+    launch and cell_tables (sbp_set_cell_tables) are applied before finalize."""
     ctx = Context(prec or problem.get("prec", "f64"), stream=stream)
     for b in problem["blocks"]:
         bid = ctx.add_block(b["n"], b["h"], b.get("origin", (0.0, 0.0, 0.0)), b.get("eps_r"),
@@ -386,5 +388,7 @@ def build_problem(problem, prec=None, cfl=None, history=1 << 16, launch=None, fo
         ctx.add_probe(p["block"], p["comp"], p["node"])
     if launch is not None:
         ctx.set_launch(*launch)
+    if cell_tables is not None:
+        ctx.set_cell_tables(cell_tables)
     ctx.finalize(problem.get("cfl", 0.9) if cfl is None else cfl, force=force, history=history)
     return ctx

@@ -544,9 +544,10 @@ def test_set_materials_changes_block_kind(sbp):
         b.close()
 
 
-def _tables_run(sbp, prob, prec, steps, tables, launch=None, switch_at=None):
-    ctx = sbp.build_problem(prob, prec=prec, launch=launch)
-    ctx.set_cell_tables(tables)
+def _tables_run(sbp, prob, prec, steps, tables, launch=None, switch_at=None, before=False):
+    ctx = sbp.build_problem(prob, prec=prec, launch=launch, cell_tables=tables if before else None)
+    if not before:
+        ctx.set_cell_tables(tables)
     if switch_at is not None:
         ctx.step(switch_at)
         ctx.set_cell_tables(not tables)
@@ -567,7 +568,8 @@ def test_cell_tables_equal_cell_arrays(sbp):
     of 8 or more planes); every result equals the run that reads the cell
     array, bitwise: the 32^3 dielectric-boxes block (33 values) in fp64 and
     fp32 at two launch shapes, and 16 cavities with tables of their own (five
-    values each, 65 in all), once with the storage switched midway."""
+    values each, 65 in all), once with the storage switched midway; the
+    reference run turns the tables off before finalize, the others after."""
     from sbp_inputs import make_config
     from sbp_inputs.configs import config4
     boxes = make_config(2, scale=8)
@@ -577,7 +579,7 @@ def test_cell_tables_equal_cell_arrays(sbp):
              (cav, ("f32",), (128, 1, 8, 0), 40))
     for prob, precs, launch, steps in cases:
         for prec in precs:
-            ref = _tables_run(sbp, prob, prec, steps, False, launch)
+            ref = _tables_run(sbp, prob, prec, steps, False, launch, before=True)
             for switch in (None, steps // 2):
                 got = _tables_run(sbp, prob, prec, steps, True, launch, switch)
                 for k in ref:
