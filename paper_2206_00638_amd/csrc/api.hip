@@ -63,6 +63,23 @@ const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
 // by the tile lists for the launch shapes where it pays).
 constexpr int kKinds = 64;
 
+// Kinds in tile-list and launch order: the tabled plain kind (33) right
+// after the plain kind that reads the permittivity cells (1), so that
+// turning the tables on or off leaves the order of the tiles, of the
+// launches and so of the energy partial sums unchanged.
+struct KindOrder {
+  int k[kKinds];
+  KindOrder() {
+    int n = 0;
+    for (int v = 0; v < kKinds; ++v) {
+      if (v == 33) continue;
+      k[n++] = v;
+      if (v == 1) k[n++] = 33;
+    }
+  }
+};
+const KindOrder kKindOrder;
+
 struct HostBlock {
   int n[3];
   double h[3], x0[3];
@@ -719,7 +736,7 @@ sbp_status build_tiles(sbp_ctx* c) {
     if (k == 1 && b.tabled && tables) return k | 32;
     return (gen_iface && (k & 30) == 4) ? (k | 2) : k;
   };
-  for (int kind = 0; kind < kKinds; ++kind) {
+  for (int kind : kKindOrder.k) {
     c->kind_t0[kind] = (int)tl.size();
     for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
       const HostBlock& b = c->blocks[bi];
@@ -806,7 +823,7 @@ sbp_status build_tiles(sbp_ctx* c) {
                              c->stream));
   }
   size_t sum = 0;
-  for (int kind = 0; kind < kKinds; ++kind)
+  for (int kind : kKindOrder.k)
     if (c->kind_t1[kind] > c->kind_t0[kind]) sum += (size_t)grid_of(c, c->kind_t1[kind] - c->kind_t0[kind]);
   size_t fsum = 0;
   for (int kind = 0; kind < 2; ++kind)
@@ -928,7 +945,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* li
   int nparts = 0, hpoff[kKinds];
   for (int& v : hpoff) v = -1;
   a.hpoff = -1;
-  for (int kind = 0; kind < kKinds; ++kind) {
+  for (int kind : kKindOrder.k) {
     if (!two_pass(kind)) continue;
     a.t0 = kt0[kind];
     a.t1 = kt1[kind];
@@ -946,7 +963,7 @@ sbp_status enqueue_step_on(sbp_ctx* c, KArgs a, bool events, const StepLists* li
     HIPCHK(c, e);
   }
   if ((st = mark()) != SBP_OK) return st;
-  for (int kind = 0; kind < kKinds; ++kind) {
+  for (int kind : kKindOrder.k) {
     if (!two_pass(kind)) continue;
     a.t0 = kt0[kind];
     a.t1 = kt1[kind];
@@ -1081,7 +1098,7 @@ std::vector<LtsBox> lts_boxes(const sbp_ctx* c, const std::vector<int>& refined,
 sbp_status lts_lists(sbp_ctx* c) {
   const int threads = c->tx * c->ty;
   std::vector<Tile> nt, ft;
-  for (int kind = 0; kind < kKinds; ++kind) {
+  for (int kind : kKindOrder.k) {
     c->nk_t0[kind] = (int)nt.size();
     c->fk_t0x[kind] = (int)ft.size();
     for (int t = c->kind_t0[kind]; t < c->kind_t1[kind]; ++t) {

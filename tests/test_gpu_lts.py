@@ -275,3 +275,36 @@ def test_lts_launch_change_midway_bitwise(sbp, prec):
     for got in out[1:]:
         for k in out[0]:
             assert np.array_equal(got[k], out[0][k]), k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lts_with_permittivity_tables_bitwise(sbp, prec):
+    """Local time stepping on a context that also holds an uncoupled plain
+    dielectric block (three permittivity values, so its E update reads a
+    byte per cell and a table at 8 planes per tile): E and the energy equal
+    the run that reads the permittivity cells, bitwise."""
+    prob = _pair(0, 41)
+    rng = np.random.default_rng(42)
+    n = (12, 10, 9)
+    vals = np.array([1.0, 2.5, 3.75])
+    prob["blocks"].append({"n": n, "h": (2e-3,) * 3, "origin": (0.1, 0.0, 0.0),
+                           "eps_r": vals[rng.integers(0, 3, size=(n[2], n[1], n[0]))], "mu_r": None,
+                           "sigma": None, "faces": ["pec"] * 6})
+    init = _init(prob, 43)
+    dt = 1.5 * S.cfl_dt(prob["blocks"], 0.9)
+    steps = 20
+    out = []
+    for tables in (True, False):
+        ctx = sbp.build_problem(prob, prec=prec, history=steps + 8, launch=(128, 1, 8, 0), cell_tables=tables)
+        try:
+            write_fields(ctx, init)
+            ctx.lts_start([1], 2, dt, 1)
+            ctx.lts_step(steps)
+            e = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"])) for c in E_COMPS}
+            out.append((e, ctx.read_energy(0, steps)))
+        finally:
+            ctx.close()
+    for k in out[0][0]:
+        assert np.array_equal(out[0][0][k], out[1][0][k]), (prec, k)
+    assert np.array_equal(out[0][1], out[1][1]), prec
+    assert np.all(np.isfinite(out[0][1]))
