@@ -20,9 +20,9 @@ def sbp():
     return p
 
 
-def _gpu_adjoint(sbp, prob, prec, steps, region, blk=0, ckpt=0):
+def _gpu_adjoint(sbp, prob, prec, steps, region, blk=0, ckpt=0, launch=None, cell_tables=None):
     import torch
-    ctx = sbp.build_problem(prob, prec=prec, history=steps + 8)
+    ctx = sbp.build_problem(prob, prec=prec, history=steps + 8, launch=launch, cell_tables=cell_tables)
     n = prob["blocks"][blk]["n"]
     grad = torch.zeros((n[2], n[1], n[0]), dtype=torch.float64, device="cuda")
     J = ctx.adjoint(blk, steps, region, grad.data_ptr(), ckpt)
@@ -169,3 +169,23 @@ def test_adjoint_repeatable_and_objective_alone(sbp):
     obj.close()
     assert float(Jn) == J1 and float(Jg.detach()) == J1
     assert np.array_equal(e.grad.cpu().numpy(), g1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_with_permittivity_tables_bitwise(sbp, prec):
+    """A plain PEC/PMC block with four permittivity values, at 8 planes per
+    tile (the forward and the reverse E updates read a byte per cell and a
+    table): J and dJ/d eps_r equal those of the run that reads the cells,
+    bitwise."""
+    rng = np.random.default_rng(61)
+    n = (17, 14, 15)
+    prob = _one_block(61, n=n, mu=False)
+    vals = np.array([1.0, 1.7, 2.9, 3.6])
+    prob["blocks"][0]["eps_r"] = vals[rng.integers(0, 4, size=(n[2], n[1], n[0]))]
+    region = (4, 9, 3, 8, 5, 11)
+    steps = 80
+    ref = _gpu_adjoint(sbp, prob, prec, steps, region, ckpt=9, launch=(128, 1, 8, 0), cell_tables=False)
+    got = _gpu_adjoint(sbp, prob, prec, steps, region, ckpt=9, launch=(128, 1, 8, 0), cell_tables=True)
+    assert got[0] == ref[0], (prec, got[0], ref[0])
+    assert np.array_equal(got[1], ref[1]), prec
+    assert np.abs(ref[1]).max() > 0
