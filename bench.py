@@ -679,7 +679,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if tr is None else tr["bytes_per_launch"],
-                     "kernel": dom, "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": dom_ms},
+                     "kernel": dom, "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": dom_ms,
+                     "bytes_note": "per node: the updated field read and written, the other field read (elem "
+                                   "bytes each); per cell: the permittivity, one byte (its table index) when the "
+                                   "block has at most 64 values, else elem bytes"},
         "kernels_ms": {"h_update": h_ms, "e_update": e_ms, "step_fused": f_ms},
         "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms_per_step * 1e-3) / 1e9,
         "event_ms_per_step": f32["event_ms"] / args.steps,
