@@ -556,31 +556,60 @@ def host_cpu():
     return model, ncpu
 
 
+_ALL_THREADS = []
+
+
+def all_threads():
+    """The oracle's thread count before any one-thread run (a one-thread run
+    leaves OpenMP at one thread, and thread count 0 keeps that setting), so
+    every all-core run passes it explicitly."""
+    if not _ALL_THREADS:
+        from oracle import loops
+        _ALL_THREADS.append(loops.max_threads())
+    return _ALL_THREADS[0]
+
+
+def progress(msg):
+    """A line on stderr per finished measurement (the JSON line stays alone on
+    stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
+def grow_rate(timed, cells, target_s):
+    """Cell-updates per second from `timed(steps)` (wall seconds of one call,
+    its set-up included): a call of 1 step, then calls of k + 1 steps with k
+    growing until the k steps beyond the first call take about target_s (the
+    set-up cancels in the difference)."""
+    t1 = timed(1)
+    k = 2
+    while True:
+        dt = timed(k + 1) - t1
+        progress(f"  cpu: {k} steps of {cells} cells in {dt:.2f} s")
+        if dt >= 0.8 * target_s or k >= 2000:
+            return k * cells / max(dt, 1e-9), k
+        k = int(min(2000, 8 * k, max(2 * k, k * target_s / max(dt, 1e-3))))
+
+
 def cpu_rate(problem, threads, target_s):
-    """Cell-updates per second of the loop oracle on `threads` host threads
-    (0: all), with its one-off set-up (node coefficients) excluded: one run
-    of 1 step and one of k+1 steps, k sized to about target_s."""
+    """Cell-updates per second of the loop oracle on `threads` host threads,
+    its one-off set-up (node coefficients) excluded (grow_rate)."""
     from oracle import loops
     n = problem["blocks"][0]["n"]
-    cells = n[0] * n[1] * n[2]
-    t0 = time.perf_counter()
-    loops.run_block(problem, steps=1, threads=threads)
-    t1 = time.perf_counter() - t0
-    k = int(max(2, min(200, target_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    loops.run_block(problem, steps=k + 1, threads=threads)
-    tk = time.perf_counter() - t0
-    return k * cells / max(tk - t1, 1e-9), k
+
+    def timed(steps):
+        t0 = time.perf_counter()
+        loops.run_block(problem, steps=steps, threads=threads)
+        return time.perf_counter() - t0
+    return grow_rate(timed, n[0] * n[1] * n[2], target_s)
 
 
 def cpu_baseline(problem):
     """The loop oracle (plain C, fp64, OpenMP over z planes) on the host
     cores, on a bounded sample of the workload (the full block for a few
     steps): on all the cores this process may use, and on one core."""
-    from oracle import loops
     model, ncpu = host_cpu()
-    threads = loops.max_threads()
-    rate_all, k_all = cpu_rate(problem, 0, 12.0)
+    threads = all_threads()
+    rate_all, k_all = cpu_rate(problem, threads, 12.0)
     rate_one, k_one = cpu_rate(problem, 1, 8.0)
     n = problem["blocks"][0]["n"]
     return {"value": rate_all / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
@@ -588,6 +617,60 @@ def cpu_baseline(problem):
                       f"(set-up excluded), fp64 loop form",
             "one_core": {"value": rate_one / 1e6, "unit": "Mcell-updates/s", "cores": 1},
             "cpu_model": model, "nproc": ncpu}
+
+
+def cpu_configs(targets=((1, 3.0), (3, 10.0), (4, 10.0), (5, 6.0))):
+    """The loop oracle on the other workloads, on all the host threads this
+    process may use and on one, fp64, cell-updates per second with each
+    call's set-up excluded (grow_rate).  Single blocks (configs 1 and 5, the latter's forward
+    run) take the one-block loop form; config 4's cavities are independent,
+    so a sample of its first 8 cavities takes it cavity by cavity; config 3's
+    27 coupled blocks take the multi-block form in full."""
+    import numpy as np
+    from oracle import loops
+    from sbp_inputs import make_config
+
+    def single(prob, b):
+        blk = dict(prob["blocks"][b])
+        pick = lambda items: [dict(x, block=0) for x in items if x["block"] == b]
+        return {"blocks": [blk], "interfaces": [], "cfl": prob["cfl"], "steps": prob.get("steps", 1),
+                "sources": pick(prob.get("sources", [])), "probes": pick(prob.get("probes", []))}
+
+    def multi_rate(prob, threads, target):
+        m = loops.MultiBlock(prob, threads=threads)
+
+        def timed(steps):
+            t0 = time.perf_counter()
+            m.advance(steps)
+            return time.perf_counter() - t0
+        return grow_rate(timed, int(sum(np.prod(b["n"]) for b in prob["blocks"])), target)
+
+    out = {}
+    for cfg, target in targets:
+        prob = make_config(cfg)
+        rec = {"workload": prob["name"], "cells": int(sum(np.prod(b["n"]) for b in prob["blocks"])),
+               "blocks": len(prob["blocks"])}
+        for threads, label in ((all_threads(), "all_cores"), (1, "one_core")):
+            if cfg == 3:
+                rate, k = multi_rate(prob, threads, target)
+                sample = f"all 27 blocks, {k} steps, multi-block loop form"
+            elif cfg == 4:
+                work = secs = 0.0
+                for b in range(8):
+                    one = single(prob, b)
+                    r, k = cpu_rate(one, threads, target / 8)
+                    cells = int(np.prod(one["blocks"][0]["n"]))
+                    work += k * cells
+                    secs += k * cells / r
+                rate = work / secs
+                sample = "cavities 0-7 of 64 (one-block loop form, cavity by cavity)"
+            else:
+                rate, k = cpu_rate(prob, threads, target)
+                sample = f"the full block, {k} steps, one-block loop form"
+            rec[label] = {"value": rate / 1e6, "unit": "Mcell-updates/s", "sample": sample}
+            progress(f"cpu config {cfg} {label}: {rate / 1e6:.1f} Mcell-updates/s")
+        out[f"config{cfg}"] = rec
+    return out
 
 
 def paper_context(problem):
@@ -630,6 +713,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the loop oracle on configs 1, 3, 4 and 5 (about two minutes of CPU)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -740,6 +825,9 @@ def main():
         "the energy sums and probes (pattern_ceiling); the paper's figure compares whole solvers")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+    if args.cpu_configs:
+        model, ncpu = host_cpu()
+        out["cpu_configs"] = {"cpu_model": model, "nproc": ncpu, "threads": all_threads(), **cpu_configs()}
     print(json.dumps(out), flush=True)
 
 
