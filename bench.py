@@ -270,9 +270,11 @@ def cpml_leg(steps, warmup, tfsf=False):
             "kernels_ms": list(kern)}
 
 
-def subgrid(steps, warmup):
+def subgrid(steps, warmup, prec="f32", fields=False):
     """The 1:2 subgrid workload: 27 blocks (coarse 192^3 region at 1 mm around
-    a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box, fp32."""
+    a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box.  With
+    `fields`, also the fields after warmup + steps + 20 steps (for the
+    accuracy comparison)."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
@@ -280,7 +282,7 @@ def subgrid(steps, warmup):
     prob = make_config(3)
     cells = int(sum(np.prod(b["n"]) for b in prob["blocks"]))
     stream = torch.cuda.Stream()
-    ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
+    ctx = build_problem(prob, prec=prec, stream=stream, history=max(steps + warmup + 8, 64))
     ctx.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -291,13 +293,40 @@ def subgrid(steps, warmup):
     ctx.step(20)
     torch.cuda.synchronize()
     kern = ctx.kernel_ms()
+    ctx.profile(False)
+    got = None
+    if fields:
+        got = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"]))
+               for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")}
     ctx.close()
-    hb, eb, fb = algorithmic_bytes(prob, 4)
+    hb, eb, fb = algorithmic_bytes(prob, 4 if prec == "f32" else 8)
     ms = wall * 1e3 / steps
-    return {"workload": prob["name"], "cells": cells, "blocks": len(prob["blocks"]),
-            "interfaces": len(prob["interfaces"]), "steps": steps, "value": cells * steps / wall / 1e6,
-            "unit": "Mcell-updates/s", "ms_per_step": ms, "kernels_ms": list(kern),
-            "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
+    rec = {"workload": prob["name"] if prec == "f32" else prob["name"].replace("fp32", "fp64"), "cells": cells,
+           "blocks": len(prob["blocks"]), "interfaces": len(prob["interfaces"]), "steps": steps,
+           "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
+           "kernels_ms": list(kern), "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
+    return (rec, got) if fields else rec
+
+
+def field_accuracy(got, ref):
+    """Relative L2 error per field (E, H over all blocks) and per component,
+    against the reference run."""
+    import numpy as np
+    out = {}
+    for group, comps in (("E", ("Ex", "Ey", "Ez")), ("H", ("Hx", "Hy", "Hz"))):
+        num = sum(float(np.sum((got[k] - ref[k]) ** 2)) for k in ref if k[1] in comps)
+        den = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1] in comps)
+        out[f"{group}_rel_l2"] = (num / den) ** 0.5
+    comp, frac = {}, {}
+    for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+        num = sum(float(np.sum((got[k] - ref[k]) ** 2)) for k in ref if k[1] == c)
+        den = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1] == c)
+        tot = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1][0] == c[0])
+        comp[c] = (num / den) ** 0.5
+        frac[c] = (den / tot) ** 0.5
+    out["components_rel_l2"] = comp
+    out["components_norm_over_field_norm"] = frac  # a weak component's relative error is large
+    return out
 
 
 def _lts_case(prob, fine, coarse_steps, warmup, init_blocks):
@@ -792,7 +821,17 @@ def main():
         if not args.no_accuracy:
             out["batched"]["accuracy"] = batched_accuracy()
     if not args.no_subgrid:
-        out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+        if args.no_fp64:
+            out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+        else:
+            out["subgrid"], g32 = subgrid(min(args.steps, 1000), max(args.warmup, 20), fields=True)
+            rec64, g64 = subgrid(min(args.steps, 1000), max(args.warmup, 20), prec="f64", fields=True)
+            out["subgrid"]["fp64"] = rec64
+            # the fp64 run is the reference here: the GPU tests pin it to the
+            # oracle at this size over the workload's full 4000 steps
+            out["subgrid"]["accuracy_vs_fp64"] = dict(field_accuracy(g32, g64),
+                                                      steps=min(args.steps, 1000) + max(args.warmup, 20) + 20)
+            del g32, g64
     if not args.no_lts:
         out["lts"] = lts_leg(min(args.steps, 500), max(args.warmup, 10))
     out["copy_ceiling"] = copy_ceiling()
