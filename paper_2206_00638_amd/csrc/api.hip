@@ -2296,7 +2296,6 @@ sbp_status sbp_load_state(sbp_ctx* c, const void* dev_buf, size_t bytes) {
   if (c->tf_on)
     HIPCHK(c, hipMemcpyAsync(c->d_line, (const char*)dev_buf + po + c->psi_elems * elem_size(c), line_bytes(c),
                              hipMemcpyDeviceToDevice, c->stream));
-  st.counter = 0;
   st.flags = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

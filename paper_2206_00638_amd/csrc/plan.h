@@ -135,7 +135,6 @@ struct GatherWG {
 
 struct StepState {
   long long step;       // index n of the next step
-  unsigned int counter; // completion counter of the last-workgroup reduction
   int flags;            // bit 0: non-finite energy seen
 };
 
