@@ -892,11 +892,8 @@ KArgs kargs(sbp_ctx* c) {
   return a;
 }
 
-int grid_size(const sbp_ctx* c) { return grid_of(c, c->ntiles); }
-
-// The pool holding the state (E^n, H^{n-1/2}) at step n, and the other one.
+// The pool holding the state (E^n, H^{n-1/2}) at step n.
 void* pool_at(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool2 : c->pool; }
-void* pool_other(const sbp_ctx* c, long long n) { return (n & 1) ? c->pool : c->pool2; }
 
 
 // One leapfrog step: [gather E faces] -> H update -> [gather H faces] -> E

@@ -630,7 +630,7 @@ __device__ __forceinline__ void h_yrow(const KArgs& a, const BC<T>& c, const Fac
 // differences on the boundary rows.  Returns the node's
 // (w/h^3) mu_r H^{n+1/2} H^{n-1/2}.
 template <typename T, bool GEN, bool IFACE, bool PML, bool TF = false>
-__device__ __forceinline__ T h_node(const KArgs& a, const DevBlock& B, const SBP_CONST DevBlock& Bc,
+__device__ __forceinline__ T h_node(const KArgs& a, const SBP_CONST DevBlock& Bc,
                                     const TRow<T>& rx, const TRow<T>& ry, const W3<T>& lw, const BC<T>& c,
                                     const HIn<T>& v,
                                     const T* __restrict__ Ex, const T* __restrict__ Ey,
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void k_h_update(KArgs a) {
       T v0, v1, v2, tcx = T(0), tcy = T(0), tcz = T(0);
       // in place: gathering one plane ahead costs the H kernel a wave per SIMD
       if (TF && (tflags & 4) && tf_near(*as_const(a.tf), i, j, k)) tf_terms<false, T>(a, Bc, i, j, k, tcx, tcy, tcz);
-      es += (double)h_node<T, GEN, IFACE, PML, TF>(a, B, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, tcx,
+      es += (double)h_node<T, GEN, IFACE, PML, TF>(a, Bc, rx, ry, lw, c, cur, Ex, Ey, Ez, HxO, HyO, HzO, M, fc, pc, tcx,
                                                tcy, tcz, i, j, k, o, true, v0, v1, v2);
       if (tflags & 2) take_probes<T>(a, B, i, j, k, true, nstep, v0, v1, v2);
       cur = nxt;
@@ -1382,7 +1382,7 @@ __global__ __launch_bounds__(FX * FY) void k_fused(KArgs a) {
         const long long o = oc + sxy * kh;
         const bool hown = own && kh <= z1;
         T v0, v1, v2;
-        const T eh = h_node<T, false, false, false>(a, B, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr,
+        const T eh = h_node<T, false, false, false>(a, Bc, hrx, hry, hlw, c, v, Ex, Ey, Ez, HxO, HyO, HzO, nullptr,
                                                     FaceCol{0, 0}, PmlCol<T>{}, T(0), T(0), T(0), i, j, kh, o, hown,
                                                     v0, v1, v2);
         if (hown) {
