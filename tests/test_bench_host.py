@@ -1,0 +1,84 @@
+"""Host logic of the benchmark (no GPU): the algorithmic byte counts behind
+the roofline figure, the permittivity-table rule they follow, the oracle
+timing helper and the field-error summary."""
+import numpy as np
+
+import bench
+from sbp_inputs import make_config
+
+
+def _nodes(n):
+    nx, ny, nz = n
+    e = (nx + 2) * (ny + 1) * (nz + 1) + (nx + 1) * (ny + 2) * (nz + 1) + (nx + 1) * (ny + 1) * (nz + 2)
+    h = (nx + 1) * (ny + 2) * (nz + 2) + (nx + 2) * (ny + 1) * (nz + 2) + (nx + 2) * (ny + 2) * (nz + 1)
+    return e, h
+
+
+def test_node_counts_are_the_component_shapes():
+    # Ex (Nx+2, Ny+1, Nz+1) ... Hz (Nx+2, Ny+2, Nz+1), written out per component
+    for n in ((4, 4, 4), (5, 7, 9), (256, 256, 256)):
+        assert bench.node_counts(n) == _nodes(n)
+
+
+def _block(n, eps):
+    return {"n": n, "h": (1e-3,) * 3, "eps_r": eps, "mu_r": None, "sigma": None, "faces": ["pec"] * 6}
+
+
+def test_algorithmic_bytes_two_pass_and_tables():
+    n = (6, 5, 4)
+    cells = 6 * 5 * 4
+    ne, nh = _nodes(n)
+    few = np.resize(np.array([1.0, 2.0, 3.5]), (4, 5, 6))           # 3 values: tabled
+    many = 1.0 + np.arange(cells, dtype=float).reshape(4, 5, 6) / cells  # 120 values: cells
+    for eps, cell_bytes in ((None, 0), (few, 1), (many, 4)):
+        prob = {"blocks": [_block(n, eps)], "interfaces": []}
+        hb, eb, fb = bench.algorithmic_bytes(prob, 4)
+        assert hb == 4 * (2 * nh + ne)
+        assert eb == 4 * (2 * ne + nh) + cell_bytes * cells
+        assert fb == 0
+    # fp64: 8 bytes per value, still one byte per tabled cell
+    hb, eb, _ = bench.algorithmic_bytes({"blocks": [_block(n, few)], "interfaces": []}, 8)
+    assert (hb, eb) == (8 * (2 * nh + ne), 8 * (2 * ne + nh) + cells)
+    # an interface block takes the general kernels: the cell array
+    prob = {"blocks": [_block(n, few), _block(n, None)], "interfaces": [(0, 1, 1, 0, 1)]}
+    assert bench.algorithmic_bytes(prob, 4)[1] == 2 * 4 * (2 * ne + nh) + 4 * cells
+    # one pass: both fields read and written once
+    _, _, fb = bench.algorithmic_bytes({"blocks": [_block(n, many)], "interfaces": []}, 4, fused=True)
+    assert fb == 4 * (2 * ne + 2 * nh + cells)
+
+
+def test_table_rule_counts_values_in_the_field_precision():
+    n = (4, 4, 4)
+    v64 = 1.0 + np.arange(64) / 64.0  # 64 distinct values: tabled
+    assert bench.tabled(_block(n, v64.reshape(4, 4, 4)), 4)
+    over = np.resize(1.0 + np.arange(65) / 65.0, (5, 4, 4))  # 65: the cell array
+    assert not bench.tabled(_block((4, 4, 5), over), 4)
+    # values equal in fp32 but not in fp64
+    close = np.resize(np.array([1.0 + k / 64.0 + d for k in range(40) for d in (0.0, 1e-12)]), (5, 4, 4))
+    assert bench.tabled(_block((4, 4, 5), close), 4)
+    assert not bench.tabled(_block((4, 4, 5), close), 8)
+    # the 256^3 dielectric-boxes workload has 33 values
+    assert bench.tabled(make_config(2, scale=8)["blocks"][0], 4)
+
+
+def test_grow_rate_excludes_setup_and_stays_bounded():
+    calls = []
+
+    def timed(steps):  # 2 s of set-up per call, 0.01 s per step
+        calls.append(steps)
+        return 2.0 + 0.01 * steps
+    rate, k = bench.grow_rate(timed, 1000, 1.0)
+    assert abs(rate - 1000 / 0.01) / (1000 / 0.01) < 1e-9
+    assert 0.01 * k >= 0.8          # the timed steps fill most of the target
+    assert max(calls) == k + 1 and len(calls) <= 5
+
+
+def test_field_accuracy_per_field_and_component():
+    rng = np.random.default_rng(5)
+    ref = {(b, c): rng.standard_normal(50) * (1e-4 if c == "Hz" else 1.0)
+           for b in range(2) for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")}
+    got = {k: v * (1 + 1e-6) for k, v in ref.items()}
+    acc = bench.field_accuracy(got, ref)
+    assert abs(acc["E_rel_l2"] - 1e-6) < 1e-12 and abs(acc["H_rel_l2"] - 1e-6) < 1e-12
+    assert all(abs(v - 1e-6) < 1e-12 for v in acc["components_rel_l2"].values())
+    assert acc["components_norm_over_field_norm"]["Hz"] < 1e-3
