@@ -270,11 +270,9 @@ def cpml_leg(steps, warmup, tfsf=False):
             "kernels_ms": list(kern)}
 
 
-def subgrid(steps, warmup, prec="f32", fields=False):
+def subgrid(steps, warmup, prec="f32"):
     """The 1:2 subgrid workload: 27 blocks (coarse 192^3 region at 1 mm around
-    a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box.  With
-    `fields`, also the fields after warmup + steps + 20 steps (for the
-    accuracy comparison)."""
+    a fine 96^3 block at 0.5 mm), absorbing outer faces, a lossy box."""
     import numpy as np
     import torch
     from paper_2206_00638_amd import build_problem
@@ -293,19 +291,33 @@ def subgrid(steps, warmup, prec="f32", fields=False):
     ctx.step(20)
     torch.cuda.synchronize()
     kern = ctx.kernel_ms()
-    ctx.profile(False)
-    got = None
-    if fields:
-        got = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"]))
-               for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")}
     ctx.close()
     hb, eb, fb = algorithmic_bytes(prob, 4 if prec == "f32" else 8)
     ms = wall * 1e3 / steps
-    rec = {"workload": prob["name"] if prec == "f32" else prob["name"].replace("fp32", "fp64"), "cells": cells,
-           "blocks": len(prob["blocks"]), "interfaces": len(prob["interfaces"]), "steps": steps,
-           "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
-           "kernels_ms": list(kern), "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
-    return (rec, got) if fields else rec
+    return {"workload": prob["name"] if prec == "f32" else prob["name"].replace("fp32", "fp64"), "cells": cells,
+            "blocks": len(prob["blocks"]), "interfaces": len(prob["interfaces"]), "steps": steps,
+            "value": cells * steps / wall / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms,
+            "kernels_ms": list(kern), "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
+
+
+def subgrid_accuracy(steps=240):
+    """The fp32 subgrid fields against the fp64 run after `steps` steps (240:
+    the source's peak, while the pulse is inside the domain; later most of it
+    has left through the absorbing faces and a relative error would be taken
+    against what remains).  The fp64 run is the reference: the GPU tests pin it
+    to the oracle at this size over the workload's full 4000 steps."""
+    import torch
+    from paper_2206_00638_amd import build_problem
+    from sbp_inputs import make_config
+    prob = make_config(3)
+    runs = {}
+    for prec in ("f32", "f64"):
+        ctx = build_problem(prob, prec=prec, stream=torch.cuda.Stream(), history=steps + 8)
+        ctx.step(steps)
+        runs[prec] = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"]))
+                      for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")}
+        ctx.close()
+    return dict(field_accuracy(runs["f32"], runs["f64"]), steps=steps)
 
 
 def field_accuracy(got, ref):
@@ -821,17 +833,10 @@ def main():
         if not args.no_accuracy:
             out["batched"]["accuracy"] = batched_accuracy()
     if not args.no_subgrid:
-        if args.no_fp64:
-            out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
-        else:
-            out["subgrid"], g32 = subgrid(min(args.steps, 1000), max(args.warmup, 20), fields=True)
-            rec64, g64 = subgrid(min(args.steps, 1000), max(args.warmup, 20), prec="f64", fields=True)
-            out["subgrid"]["fp64"] = rec64
-            # the fp64 run is the reference here: the GPU tests pin it to the
-            # oracle at this size over the workload's full 4000 steps
-            out["subgrid"]["accuracy_vs_fp64"] = dict(field_accuracy(g32, g64),
-                                                      steps=min(args.steps, 1000) + max(args.warmup, 20) + 20)
-            del g32, g64
+        out["subgrid"] = subgrid(min(args.steps, 1000), max(args.warmup, 20))
+        if not args.no_fp64:
+            out["subgrid"]["fp64"] = subgrid(min(args.steps, 1000), max(args.warmup, 20), prec="f64")
+            out["subgrid"]["accuracy_vs_fp64"] = subgrid_accuracy()
     if not args.no_lts:
         out["lts"] = lts_leg(min(args.steps, 500), max(args.warmup, 10))
     out["copy_ceiling"] = copy_ceiling()
