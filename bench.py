@@ -475,7 +475,10 @@ COMPS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
 
 def field_error_report(got, ref):
     """Relative L2 errors against the oracle: per field (all E, all H
-    components together) and each component on its own."""
+    components together), of both fields together in the vacuum energy norm
+    (eps0 |dE|^2 + mu0 |dH|^2: meaningful when one field has decayed, as H
+    has after a Gaussian current pulse that left a static E field) and each
+    component on its own."""
     import numpy as np
     num = {"E": 0.0, "H": 0.0}
     den = {"E": 0.0, "H": 0.0}
@@ -488,8 +491,10 @@ def field_error_report(got, ref):
         den[c[0]] += q
         key = c if not isinstance(k, tuple) else f"{k[0]}/{c}"
         comp[key] = math.sqrt(d / q) if q > 0 else math.sqrt(d)
+    eps0, mu0 = 8.8541878128e-12, 1.25663706212e-6
+    energy = math.sqrt((eps0 * num["E"] + mu0 * num["H"]) / (eps0 * den["E"] + mu0 * den["H"]))
     return {"E_rel_l2": math.sqrt(num["E"] / den["E"]), "H_rel_l2": math.sqrt(num["H"] / den["H"]),
-            "components_rel_l2": comp}
+            "energy_norm_rel": energy, "components_rel_l2": comp}
 
 
 def accuracy(scale):

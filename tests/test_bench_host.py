@@ -82,3 +82,15 @@ def test_field_accuracy_per_field_and_component():
     assert abs(acc["E_rel_l2"] - 1e-6) < 1e-12 and abs(acc["H_rel_l2"] - 1e-6) < 1e-12
     assert all(abs(v - 1e-6) < 1e-12 for v in acc["components_rel_l2"].values())
     assert acc["components_norm_over_field_norm"]["Hz"] < 1e-3
+
+
+def test_field_error_report_energy_norm_weighs_both_fields():
+    # E exact, H 1e-3 off, with eta0 |H| = 0.02 |E|: the energy-norm error is
+    # H's error scaled by the fields' energy ratio
+    eta0 = (1.25663706212e-6 / 8.8541878128e-12) ** 0.5
+    ref = {(0, "Ex"): np.ones(10), (0, "Hx"): np.full(10, 0.02 / eta0)}
+    got = {(0, "Ex"): ref[(0, "Ex")].copy(), (0, "Hx"): ref[(0, "Hx")] * (1 + 1e-3)}
+    rep = bench.field_error_report(got, ref)
+    assert rep["E_rel_l2"] == 0.0 and abs(rep["H_rel_l2"] - 1e-3) < 1e-12
+    expect = 1e-3 * 0.02 / (1 + 0.02 ** 2) ** 0.5
+    assert abs(rep["energy_norm_rel"] - expect) < 1e-9 * expect + 1e-15
