@@ -230,15 +230,9 @@ def bloch(steps, warmup):
             "step_hbm_gbs_algorithmic": 2 * (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
-def cpml_leg(steps, warmup, tfsf=False):
-    """The dielectric-boxes 256^3 fp32 workload with every face a PEC face
-    behind a 10-cell convolutional PML (the truncation of the paper's open
-    examples) instead of a PEC cavity wall; with `tfsf`, the boxes also
-    scatter a plane wave (along +z, E along x) brought in through a
-    total-field / scattered-field box 16 cells inside the faces."""
-    import numpy as np
-    import torch
-    from paper_2206_00638_amd import build_problem
+def cpml_problem(tfsf=False):
+    """The dielectric-boxes 256^3 recipe behind 10-cell CPML layers, with a
+    TF/SF plane wave if `tfsf`; (problem, workload name)."""
     from sbp_inputs import make_config
     prob = make_config(2)
     prob["blocks"][0]["faces"] = ["cpml"] * 6
@@ -250,6 +244,19 @@ def cpml_leg(steps, warmup, tfsf=False):
                         "margin": 16, "source": {"cell": -12, "waveform": "modgauss", "tw": 2e-10, "t0": 2.5e-10,
                                                  "f0": 1e10, "amp": 1.0}}
         name += "-tfsf16"
+    return prob, name
+
+
+def cpml_leg(steps, warmup, tfsf=False):
+    """The dielectric-boxes 256^3 fp32 workload with every face a PEC face
+    behind a 10-cell convolutional PML (the truncation of the paper's open
+    examples) instead of a PEC cavity wall; with `tfsf`, the boxes also
+    scatter a plane wave (along +z, E along x) brought in through a
+    total-field / scattered-field box 16 cells inside the faces."""
+    import numpy as np
+    import torch
+    from paper_2206_00638_amd import build_problem
+    prob, name = cpml_problem(tfsf)
     cells = int(np.prod(prob["blocks"][0]["n"]))
     stream = torch.cuda.Stream()
     ctx = build_problem(prob, prec="f32", stream=stream, history=max(steps + warmup + 8, 64))
@@ -300,44 +307,59 @@ def subgrid(steps, warmup, prec="f32"):
             "kernels_ms": list(kern), "step_hbm_gbs_algorithmic": (hb + eb + fb) / (ms * 1e-3) / 1e9}
 
 
-def subgrid_accuracy(steps=240):
-    """The fp32 subgrid fields against the fp64 run after `steps` steps (240:
-    the source's peak, while the pulse is inside the domain; later most of it
-    has left through the absorbing faces and a relative error would be taken
-    against what remains).  The fp64 run is the reference: the GPU tests pin it
-    to the oracle at this size over the workload's full 4000 steps."""
+def fp32_vs_fp64(prob, steps=240):
+    """The fp32 fields of `prob` against its fp64 run after `steps` steps
+    (every block, the imaginary-part blocks of complex fields included).  The
+    fp64 run is the reference: the GPU tests pin the fp64 path to the oracle
+    on these recipes (at full size for the subgrid workload, reduced for the
+    periodic, CPML and TF/SF ones)."""
     import torch
     from paper_2206_00638_amd import build_problem
-    from sbp_inputs import make_config
-    prob = make_config(3)
     runs = {}
     for prec in ("f32", "f64"):
         ctx = build_problem(prob, prec=prec, stream=torch.cuda.Stream(), history=steps + 8)
         ctx.step(steps)
-        runs[prec] = {(b, c): ctx.read_field(b, c) for b in range(len(prob["blocks"]))
+        nb = len(prob["blocks"]) + len(ctx.imag_part)
+        runs[prec] = {(b, c): ctx.read_field(b, c) for b in range(nb)
                       for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")}
         ctx.close()
     return dict(field_accuracy(runs["f32"], runs["f64"]), steps=steps)
 
 
+def subgrid_accuracy(steps=240):
+    """The subgrid workload's fp32 fields against its fp64 run after `steps`
+    steps (240: the source's peak, while the pulse is inside the domain;
+    later most of it has left through the absorbing faces and a relative
+    error would be taken against what remains)."""
+    from sbp_inputs import make_config
+    return fp32_vs_fp64(make_config(3), steps)
+
+
 def field_accuracy(got, ref):
     """Relative L2 error per field (E, H over all blocks) and per component,
-    against the reference run."""
+    against the reference run; a component below 1e-6 of its field's norm in
+    the reference (zero in exact arithmetic) is measured against the field's
+    norm instead."""
     import numpy as np
     out = {}
     for group, comps in (("E", ("Ex", "Ey", "Ez")), ("H", ("Hx", "Hy", "Hz"))):
         num = sum(float(np.sum((got[k] - ref[k]) ** 2)) for k in ref if k[1] in comps)
         den = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1] in comps)
         out[f"{group}_rel_l2"] = (num / den) ** 0.5
-    comp, frac = {}, {}
+    comp, frac, zero = {}, {}, []
     for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
         num = sum(float(np.sum((got[k] - ref[k]) ** 2)) for k in ref if k[1] == c)
         den = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1] == c)
         tot = sum(float(np.sum(ref[k] ** 2)) for k in ref if k[1][0] == c[0])
-        comp[c] = (num / den) ** 0.5
         frac[c] = (den / tot) ** 0.5
+        if frac[c] < 1e-6:  # zero in exact arithmetic: its error against the field's norm
+            comp[c] = (num / tot) ** 0.5
+            zero.append(c)
+        else:
+            comp[c] = (num / den) ** 0.5
     out["components_rel_l2"] = comp
     out["components_norm_over_field_norm"] = frac  # a weak component's relative error is large
+    out["components_zero_in_exact_arithmetic"] = zero
     return out
 
 
@@ -848,10 +870,17 @@ def main():
     out["pattern_ceiling"] = pattern_ceiling(h_ms, e_ms)
     if not args.no_cpml:
         out["cpml"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20))
+        if not args.no_accuracy:
+            out["cpml"]["accuracy_vs_fp64"] = fp32_vs_fp64(cpml_problem()[0])
     if not args.no_tfsf:
         out["cpml_tfsf"] = cpml_leg(min(args.steps, 1000), max(args.warmup, 20), tfsf=True)
+        if not args.no_accuracy:
+            out["cpml_tfsf"]["accuracy_vs_fp64"] = fp32_vs_fp64(cpml_problem(True)[0])
     if not args.no_bloch:
         out["bloch"] = bloch(min(args.steps, 1000), max(args.warmup, 20))
+        if not args.no_accuracy:
+            from sbp_inputs import bloch_box
+            out["bloch"]["accuracy_vs_fp64"] = fp32_vs_fp64(bloch_box())
     if not args.no_adjoint:
         import numpy as np
         out["adjoint"], g32 = adjoint_leg("f32")

@@ -94,3 +94,13 @@ def test_field_error_report_energy_norm_weighs_both_fields():
     assert rep["E_rel_l2"] == 0.0 and abs(rep["H_rel_l2"] - 1e-3) < 1e-12
     expect = 1e-3 * 0.02 / (1 + 0.02 ** 2) ** 0.5
     assert abs(rep["energy_norm_rel"] - expect) < 1e-9 * expect + 1e-15
+
+
+def test_field_accuracy_zero_component_against_field_norm():
+    ref = {(0, "Ex"): np.ones(8), (0, "Ey"): np.ones(8), (0, "Ez"): np.ones(8),
+           (0, "Hx"): np.ones(8), (0, "Hy"): np.ones(8), (0, "Hz"): np.full(8, 1e-17)}
+    got = dict(ref)
+    got[(0, "Hz")] = np.full(8, 1e-9)
+    acc = bench.field_accuracy(got, ref)
+    assert acc["components_zero_in_exact_arithmetic"] == ["Hz"]
+    assert abs(acc["components_rel_l2"]["Hz"] - 1e-9 / 2 ** 0.5) < 1e-15
